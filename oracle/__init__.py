@@ -1,0 +1,250 @@
+"""CPU oracle for the subtracted one-loop two-point integral on a complex x grid.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product library never does,
+and the two share no code.
+
+`gf_oracle.c` is the plain FP64 implementation (OpenMP over points),
+`gf_oracle_q.c` the same quadrature in __float128, `closed_forms.py` the
+analytic references the oracle is pinned against.  `build()` compiles the two
+C files with gcc into this directory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB64 = os.path.join(_HERE, "_liborc.so")
+_LIBQ = os.path.join(_HERE, "_liborcq.so")
+
+# contour classes (numbering shared by both oracle files)
+R, Y, YRES, MIRROR, SINGULAR = 0, 1, 2, 3, 4
+CLASS_NAMES = {R: "R", Y: "Y", YRES: "YRES", MIRROR: "MIRROR", SINGULAR: "SINGULAR"}
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("m1sq_re", ctypes.c_double), ("m1sq_im", ctypes.c_double),
+                ("m2sq_re", ctypes.c_double), ("m2sq_im", ctypes.c_double),
+                ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
+                ("scale", ctypes.c_double),
+                ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
+                ("n_arc", ctypes.c_int)]
+
+
+def build(verbose: bool = False) -> None:
+    """Compile both oracle libraries with gcc (always recompiles)."""
+    flags = ["-O2", "-fPIC", "-shared", "-fopenmp", "-std=gnu11"]
+    for src, out, libs in (("gf_oracle.c", _LIB64, ["-lm"]),
+                           ("gf_oracle_q.c", _LIBQ, ["-lquadmath", "-lm"])):
+        cmd = ["gcc", *flags, "-o", out + ".tmp", os.path.join(_HERE, src), *libs]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+    global _lib, _libq
+    _lib = _libq = None
+
+
+_lib = None
+_libq = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB64):
+            build()
+        lib = ctypes.CDLL(_LIB64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        lib.orc_gauss_cheb2.argtypes = [ctypes.c_int, dp, dp]
+        lib.orc_angular_sum.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, dp, dp]
+        lib.orc_eval_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                        ctypes.c_int, dp, ctypes.c_char_p, dp]
+        lib.orc_scan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, ctypes.c_long,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, dp, ctypes.c_char_p, dp]
+        lib.orc_grid_point.argtypes = [ctypes.c_long] * 4 + [ctypes.c_double] * 4 + [dp, dp]
+        lib.orc_jmu.argtypes = [ctypes.POINTER(_Problem), dp, dp]
+        lib.orc_classify_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                            ctypes.c_char_p]
+        lib.orc_evals_for_class.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int]
+        lib.orc_evals_for_class.restype = ctypes.c_long
+        _lib = lib
+    return _lib
+
+
+def _loadq():
+    global _libq
+    if _libq is None:
+        if not os.path.exists(_LIBQ):
+            build()
+        lib = ctypes.CDLL(_LIBQ)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.orcq_eval_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                         dp, ctypes.c_char_p]
+        _libq = lib
+    return _libq
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def problem(params, quad) -> _Problem:
+    """ctypes problem record from workload Params / Quadrature objects."""
+    m1, m2 = complex(params.m1sq), complex(params.m2sq)
+    return _Problem(m1.real, m1.imag, m2.real, m2.imag, float(params.mu2),
+                    float(params.lambda2), float(params.scale),
+                    int(quad.n_radial), int(quad.n_angular), int(quad.n_arc))
+
+
+# ---------------------------------------------------------------- rules
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _load().orc_gauss_legendre(n, _dp(x), _dp(w))
+    return x, w
+
+
+def gauss_cheb2(n: int):
+    z = np.zeros(n)
+    w = np.zeros(n)
+    _load().orc_gauss_cheb2(n, _dp(z), _dp(w))
+    return z, w
+
+
+def angular_sum(u: complex, v: complex, n: int) -> complex:
+    """sum_j w_j / (u - v z_j) with the oracle's GC-II rule of order n."""
+    re = ctypes.c_double()
+    im = ctypes.c_double()
+    _load().orc_angular_sum(u.real, u.imag, v.real, v.imag, n, ctypes.byref(re),
+                            ctypes.byref(im))
+    return complex(re.value, im.value)
+
+
+# ---------------------------------------------------------------- evaluation
+
+def grid_points(grid) -> np.ndarray:
+    """Cell-centred x of every grid point (row-major, Re fastest), complex128."""
+    lib = _load()
+    out = np.empty(grid.n_points, dtype=np.complex128)
+    xr = ctypes.c_double()
+    xi = ctypes.c_double()
+    for b in range(grid.n_im):
+        for a in range(grid.n_re):
+            lib.orc_grid_point(a, b, grid.n_re, grid.n_im, grid.re_lo, grid.re_hi,
+                               grid.im_lo, grid.im_hi, ctypes.byref(xr), ctypes.byref(xi))
+            out[b * grid.n_re + a] = complex(xr.value, xi.value)
+    return out
+
+
+def grid_points_at(grid, flat_idx) -> np.ndarray:
+    """Cell-centred x at the given flat indices (b * n_re + a)."""
+    lib = _load()
+    flat_idx = np.asarray(flat_idx, dtype=np.int64)
+    out = np.empty(flat_idx.size, dtype=np.complex128)
+    xr = ctypes.c_double()
+    xi = ctypes.c_double()
+    for k, f in enumerate(flat_idx.tolist()):
+        b, a = divmod(f, grid.n_re)
+        lib.orc_grid_point(a, b, grid.n_re, grid.n_im, grid.re_lo, grid.re_hi,
+                           grid.im_lo, grid.im_hi, ctypes.byref(xr), ctypes.byref(xi))
+        out[k] = complex(xr.value, xi.value)
+    return out
+
+
+def eval_points(params, quad, x, force_class: int | None = None, want_cond: bool = False):
+    """G at arbitrary complex points x.  Returns (g, cls[, cond])."""
+    lib = _load()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    g = np.zeros(2 * x.size)
+    cls = ctypes.create_string_buffer(max(x.size, 1))
+    cond = np.zeros(x.size) if want_cond else None
+    pr = problem(params, quad)
+    rc = lib.orc_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi),
+                             -1 if force_class is None else int(force_class), _dp(g), cls,
+                             _dp(cond) if want_cond else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    gc = g[0::2] + 1j * g[1::2]
+    c = np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+    if want_cond:
+        return gc, c, cond
+    return gc, c
+
+
+def scan(params, quad, grid, want_cond: bool = False):
+    """G on the whole grid (row-major, Re fastest)."""
+    lib = _load()
+    n = grid.n_points
+    g = np.zeros(2 * n)
+    cls = ctypes.create_string_buffer(max(n, 1))
+    cond = np.zeros(n) if want_cond else None
+    pr = problem(params, quad)
+    rc = lib.orc_scan(ctypes.byref(pr), grid.n_re, grid.n_im, grid.re_lo, grid.re_hi,
+                      grid.im_lo, grid.im_hi, _dp(g), cls, _dp(cond) if want_cond else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    gc = g[0::2] + 1j * g[1::2]
+    c = np.frombuffer(cls.raw[:n], dtype=np.int8).copy()
+    if want_cond:
+        return gc, c, cond
+    return gc, c
+
+
+def eval_points_q(params, quad, x):
+    """Quad-precision brute force of the same quadrature.  Returns (g, cls)."""
+    lib = _loadq()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    g = np.zeros(2 * x.size)
+    cls = ctypes.create_string_buffer(max(x.size, 1))
+    pr = problem(params, quad)
+    lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls)
+    return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+
+
+def jmu(params, quad) -> complex:
+    """Unscaled subtraction sum (real-axis contour at x = mu^2)."""
+    re = ctypes.c_double()
+    im = ctypes.c_double()
+    pr = problem(params, quad)
+    _load().orc_jmu(ctypes.byref(pr), ctypes.byref(re), ctypes.byref(im))
+    return complex(re.value, im.value)
+
+
+def classify(params, quad, x) -> np.ndarray:
+    lib = _load()
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    cls = ctypes.create_string_buffer(max(x.size, 1))
+    pr = problem(params, quad)
+    lib.orc_classify_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), cls)
+    return np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+
+
+def evals_for_classes(params, quad, cls, x=None) -> int:
+    """Integrand evaluations for points of the given classes; a MIRROR point
+    costs what its mirror image costs (needs x)."""
+    lib = _load()
+    pr = problem(params, quad)
+    per = {c: lib.orc_evals_for_class(ctypes.byref(pr), c) for c in (R, Y, YRES)}
+    cls = np.asarray(cls)
+    total = sum(int((cls == c).sum()) * per[c] for c in (R, Y, YRES))
+    m = cls == MIRROR
+    if m.any():
+        if x is None:
+            raise ValueError("mirror points need x")
+        cb = classify(params, quad, np.conj(np.asarray(x)[m]))
+        total += sum(int((cb == c).sum()) * per[c] for c in (R, Y, YRES))
+    return total

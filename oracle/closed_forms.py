@@ -1,0 +1,140 @@
+"""Analytic references the oracle is pinned against (test infrastructure).
+
+Nothing here calls the oracle's quadrature; every function is an independent
+statement of a result the quadrature must reproduce.
+
+* `eq18`               -- exact subtracted, rescaled worked-example correlator
+                          (eq. 17 / eq. 18), masses m1^2 = -i/2, m2^2 = +i/2,
+                          subtraction at x = 0.
+* `feynman`            -- textbook Feynman-parameter form of the subtracted
+                          bubble, int_0^1 log(Delta(a, mu^2) / Delta(a, x)) da,
+                          Delta(a, s) = a m1^2 + (1 - a) m2^2 + a (1 - a) s.
+* `cutoff_bias`        -- leading effect of the sharp cutoff Lambda^2 of eq. 14.
+* `cut_discontinuity`  -- G(-s + i0) - G(-s - i0) from the Kallen function.
+* `gc2_discrete`       -- exact value of the n-node Gauss-Chebyshev-II sum
+                          sum_j w_j / (U - V z_j).
+* `angular_continuum`  -- exact angular average (2/pi) int sqrt(1-z^2)/(U - V z).
+"""
+from __future__ import annotations
+
+import mpmath as mp
+import numpy as np
+
+mp.mp.dps = 40
+
+
+def eq18(x: complex) -> complex:
+    """1 - pi/(2x) + sqrt(1 - x^2) arccos(x) / x (eq. 18, principal branches)."""
+    x = mp.mpc(x)
+    r = 1 - mp.pi / (2 * x) + mp.sqrt(1 - x * x) * mp.acos(x) / x
+    return complex(r)
+
+
+def delta(a, s, m1sq, m2sq):
+    return a * m1sq + (1 - a) * m2sq + a * (1 - a) * s
+
+
+def feynman(x: complex, m1sq: complex, m2sq: complex, mu2: float) -> complex:
+    """int_0^1 [log Delta(a, mu^2) - log Delta(a, x)] da with principal logs.
+
+    Exact for real masses off the real x axis (Delta(a, x) then never crosses
+    the negative real axis).  For complex masses it is the analytic function
+    only where `feynman_principal_ok` holds."""
+    x = mp.mpc(x)
+    m1 = mp.mpc(m1sq)
+    m2 = mp.mpc(m2sq)
+    mu = mp.mpf(mu2)
+
+    def f(a):
+        return mp.log(delta(a, mu, m1, m2)) - mp.log(delta(a, x, m1, m2))
+
+    # split at the real parts of the zeros of Delta(a, x) and Delta(a, mu^2)
+    # (quadratic in a) so that the quadrature sees smooth pieces
+    pts = [mp.mpf(0), mp.mpf(1)]
+    for s in (x, mu):
+        b = m1 - m2 + s
+        if s != 0:
+            disc = mp.sqrt(b * b + 4 * s * m2)
+            roots = [(b + disc) / (2 * s), (b - disc) / (2 * s)]
+        elif b != 0:
+            roots = [-m2 / b]
+        else:
+            roots = []
+        for r in roots:
+            if 0 < mp.re(r) < 1:
+                pts.append(mp.re(r))
+    pts = sorted(set(pts))
+    return complex(mp.quad(f, pts))
+
+
+def feynman_principal_ok(x: complex, m1sq: complex, m2sq: complex, mu2: float,
+                         n: int = 4001) -> bool:
+    """True when neither Delta(a, x) nor Delta(a, mu^2) crosses the negative real
+    axis for a in [0, 1] (sampled), so that the principal-log form is analytic
+    in x there."""
+    a = np.linspace(0.0, 1.0, n)
+    for s in (complex(x), complex(mu2)):
+        d = delta(a, s, complex(m1sq), complex(m2sq))
+        im = d.imag
+        re = d.real
+        sign_change = np.nonzero(np.sign(im[1:]) * np.sign(im[:-1]) < 0)[0]
+        for k in sign_change:
+            if re[k] < 0 or re[k + 1] < 0:
+                return False
+        if np.any((np.abs(im) < 1e-15) & (re <= 0)):
+            return False
+    return True
+
+
+def cutoff_bias(x: complex, m1sq: complex, mu2: float, lambda2: float) -> complex:
+    """G_Lambda(x) - G_infinity(x) to leading order, (x - mu^2) m1^2 / (2 Lambda^4).
+
+    From the large-y expansion of the angular average,
+    <1/D1> = 1/y - m1^2/y^2 + (m1^4 - x m1^2)/y^3 + O(y^-4): the subtracted
+    integrand behaves like (mu^2 - x) m1^2 / y^3, whose tail beyond Lambda^2
+    the cutoff drops."""
+    return (complex(x) - mu2) * complex(m1sq) / (2.0 * lambda2 * lambda2)
+
+
+def kallen(a, b, c):
+    return a * a + b * b + c * c - 2 * a * b - 2 * b * c - 2 * c * a
+
+
+def cut_discontinuity(s: float, m1: float, m2: float) -> complex:
+    """G(-s + i0) - G(-s - i0) for real masses: -2 pi i sqrt(lambda)/s above the
+    threshold s > (m1 + m2)^2, zero below."""
+    if s <= (m1 + m2) ** 2:
+        return 0.0
+    lam = kallen(s, m1 * m1, m2 * m2)
+    return -2j * np.pi * np.sqrt(lam) / s
+
+
+def gc2_discrete(u: complex, v: complex, n: int) -> complex:
+    """Exact n-node GC-II sum  sum_j w_j / (u - v z_j),  z_j = cos(j pi/(n+1)),
+    w_j = 2 sin^2(j pi/(n+1)) / (n+1):
+
+        2/(u + S) * (1 - q^(2n)) / (1 - q^(2n+2)),  S = sqrt(u^2 - v^2),
+        q = v / (u + S),  with the root S chosen so that |u + S| >= |u - S|.
+
+    Evaluated in 40-digit arithmetic; v = 0 gives 1/u."""
+    u = mp.mpc(u)
+    v = mp.mpc(v)
+    if v == 0:
+        return complex(1 / u)
+    s = mp.sqrt(u * u - v * v)
+    if abs(u + s) < abs(u - s):
+        s = -s
+    q = v / (u + s)
+    r = 2 / (u + s) * (1 - q ** (2 * n)) / (1 - q ** (2 * n + 2))
+    return complex(r)
+
+
+def angular_continuum(u: complex, v: complex) -> complex:
+    """(2/pi) int_{-1}^{1} sqrt(1-z^2) / (u - v z) dz = 2 / (u + sqrt(u^2 - v^2)),
+    root with |u + S| >= |u - S| (u - v z != 0 on [-1, 1])."""
+    u = mp.mpc(u)
+    v = mp.mpc(v)
+    s = mp.sqrt(u * u - v * v)
+    if abs(u + s) < abs(u - s):
+        s = -s
+    return complex(2 / (u + s))

@@ -1,0 +1,487 @@
+/*
+ * CPU FP64 oracle for the subtracted one-loop two-point integral on a grid of
+ * complex x = p^2 (Windisch, Alkofer, Haase, Liebmann, "Examining the analytic
+ * structure of Green's functions: massive parallel complex integration using
+ * GPUs").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library) never calls it, and the two share no code.
+ *
+ * What is computed (rescaled units of eq. 18 / eq. 21, times `scale`):
+ *
+ *   G(x) = scale * ( sum over the contour C of  dy y <F(x,y,.)>
+ *                    - sum over the real axis of dy y <F(mu^2,y,.)> )
+ *
+ *   F(x,y,z)  = 1 / [ (x + y - 2 sqrt(x) sqrt(y) z + m1^2) (y + m2^2) ]
+ *               (eq. 10 with the propagators of eq. 16 / eq. 19; m1^2 sits on
+ *               the (p-k) leg, m2^2 on the k leg)
+ *   <f>       = (2/pi) int_{-1}^{1} dz sqrt(1-z^2) f(z)        (eq. 11, eq. 21)
+ *   subtraction at the real point mu^2 >= 0                     (eq. 12-14)
+ *   C = deformed y contour from 0 to Lambda^2                   (STEP 3, eq. 15)
+ *
+ * Quadrature (section "Numerical Implementation"): non-adaptive Gauss rules.
+ *   radial : n_radial-point Gauss-Legendre in t = log(1+y) on [0, log(1+Lambda^2)]
+ *   angular: n_angular-point Gauss-Chebyshev of the second kind,
+ *            z_j = cos(j pi/(n+1)), w_j = (2/(n+1)) sin^2(j pi/(n+1)), sum w_j = 1
+ *   arc    : n_arc-point Gauss-Legendre in the angle
+ *
+ * Contour per x (STEP 3; the paper's per-region contours of its worked example
+ * are replaced by the following reading):
+ *   R      real axis [0, Lambda^2]; valid while |Im sqrt(x)| < Re sqrt(m1^2);
+ *          chosen when valid and (v < 0.25 v* or 1 - v/v* >= 0.45 delta), with
+ *          v = |Im sqrt x|, v* = Re sqrt(m1^2), delta = angular distance from
+ *          arg x to the nearest bad ray, or when no rotated contour applies
+ *   Y      ray y = r e^{i phi}, phi = arg x, r in [0, Lambda^2], then the arc
+ *          |y| = Lambda^2 from angle phi back to 0
+ *   YRES   Y plus the residue of the k-leg pole y0 = -m2^2, which the ray has
+ *          swept across (+2 pi i for phi > 0, -2 pi i for phi < 0)
+ *   MIRROR G(x) = conj G(conj x)  (real masses or a conjugate mass pair)
+ * Points on a singular set (x on a "bad ray" or on the negative real axis
+ * outside region R) return NaN and class ORC_SINGULAR.
+ *
+ * Everything here is plain loops in double precision, written for a reader to
+ * check against the paper by eye, not for speed.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+enum { ORC_R = 0, ORC_Y = 1, ORC_YRES = 2, ORC_MIRROR = 3, ORC_SINGULAR = 4 };
+
+/* Region R is chosen where v = |Im sqrt x| is below ORC_R_NEAR of its bound
+ * v* = Re sqrt(m1^2), or where 1 - v/v* is at least ORC_R_SLOPE times the
+ * angular distance from arg x to the nearest bad ray. */
+#define ORC_R_NEAR 0.25
+#define ORC_R_SLOPE 0.45
+
+typedef struct {
+    double m1sq_re, m1sq_im;   /* m1^2 on the (p-k) leg */
+    double m2sq_re, m2sq_im;   /* m2^2 on the k leg */
+    double mu2;                /* real subtraction point, >= 0 */
+    double lambda2;            /* cutoff Lambda^2 of eq. 14 */
+    double scale;              /* 1 = eq. 18 units, 1/(16 pi^2) = eq. 17 units */
+    int n_radial, n_angular, n_arc;
+} orc_problem;
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature rules                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Gauss-Legendre nodes and weights on [-1,1]: roots of P_n found by Newton's
+ * method, P_n and P_n' from the three-term recurrence; w = 2/((1-x^2) P_n'^2).
+ * Nodes ascending. */
+int orc_gauss_legendre(int n, double *x, double *w)
+{
+    if (n <= 0) return -1;
+    for (int i = 0; i < n; ++i) {
+        /* i-th root from the top, initial guess cos(pi (i + 3/4) / (n + 1/2)) */
+        double r = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = r;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double pn = (n == 1) ? r : p1;
+            double pnm1 = (n == 1) ? 1.0 : p0;
+            dp = n * (r * pn - pnm1) / (r * r - 1.0);
+            double step = pn / dp;
+            r -= step;
+            if (fabs(step) < 1e-16) break;
+        }
+        /* recompute the derivative at the converged root */
+        double p0 = 1.0, p1 = r;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        double pn = (n == 1) ? r : p1;
+        double pnm1 = (n == 1) ? 1.0 : p0;
+        dp = n * (r * pn - pnm1) / (r * r - 1.0);
+        x[n - 1 - i] = r;
+        w[n - 1 - i] = 2.0 / ((1.0 - r * r) * dp * dp);
+    }
+    return 0;
+}
+
+/* Gauss-Chebyshev of the second kind, normalised so that
+ * (2/pi) int_{-1}^{1} sqrt(1-z^2) f(z) dz ~ sum_j w_j f(z_j).  j = 1..n. */
+int orc_gauss_cheb2(int n, double *z, double *w)
+{
+    if (n <= 0) return -1;
+    for (int j = 1; j <= n; ++j) {
+        double th = j * M_PI / (n + 1);
+        double s = sin(th);
+        z[j - 1] = cos(th);
+        w[j - 1] = 2.0 / (n + 1) * s * s;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The angular integral (eq. 11, inner z integral)                           */
+/* ------------------------------------------------------------------------ */
+
+/* <1/D1> for D1 = x + y + m1^2 - 2 sqrt(x) sqrt(y) z, at given sxsy = sqrt(x)sqrt(y).
+ * Also adds sum_j |w_j / D1_j| to *absum (a conditioning measure). */
+static cplx angular_d1(cplx x, cplx y, cplx sxsy, cplx m1sq, int n,
+                       const double *z, const double *w, double *absum)
+{
+    cplx acc = 0.0;
+    double a = 0.0;
+    for (int j = 0; j < n; ++j) {
+        cplx d1 = x + y - 2.0 * sxsy * z[j] + m1sq;
+        cplx t = w[j] / d1;
+        acc += t;
+        if (absum) a += cabs(t);
+    }
+    if (absum) *absum += a;
+    return acc;
+}
+
+/* Exported for the pin tests: sum_j w_j / (U - V z_j) with the oracle's GC-II
+ * rule of order n. */
+void orc_angular_sum(double u_re, double u_im, double v_re, double v_im, int n,
+                     double *out_re, double *out_im)
+{
+    double *z = malloc(sizeof(double) * n), *w = malloc(sizeof(double) * n);
+    orc_gauss_cheb2(n, z, w);
+    /* U - V z = (x + y + m1^2) - 2 sqrt(x)sqrt(y) z with x = U, y = 0, m1^2 = 0,
+     * 2 sqrt(x) sqrt(y) = V */
+    cplx r = angular_d1(u_re + I * u_im, 0.0, 0.5 * (v_re + I * v_im), 0.0, n, z, w, NULL);
+    *out_re = creal(r);
+    *out_im = cimag(r);
+    free(z);
+    free(w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contour choice (STEP 3)                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    cplx m1sq, m2sq;
+    double beta1, beta2;    /* bad-ray angles arg(-m1^2), arg(-m2^2) */
+    double lo, hi;          /* open sector (lo, hi) reachable by rotating the ray */
+    double vstar;           /* region-R bound on |Im sqrt(x)| = Re sqrt(m1^2) */
+    int mirror_ok;          /* real masses or a conjugate pair */
+} orc_geometry;
+
+static void orc_make_geometry(const orc_problem *p, orc_geometry *g)
+{
+    g->m1sq = p->m1sq_re + I * p->m1sq_im;
+    g->m2sq = p->m2sq_re + I * p->m2sq_im;
+    g->beta1 = carg(-g->m1sq);
+    g->beta2 = carg(-g->m2sq);
+    /* a real positive m^2 gives carg(-m^2) = +pi or -pi depending on the sign
+     * of the zero imaginary part; it is the negative real axis either way */
+    if (p->m1sq_im == 0.0) g->beta1 = M_PI;
+    if (p->m2sq_im == 0.0) g->beta2 = M_PI;
+    g->hi = M_PI;
+    g->lo = -M_PI;
+    double b[2] = {g->beta1, g->beta2};
+    for (int k = 0; k < 2; ++k) {
+        if (b[k] > 0.0 && b[k] < g->hi) g->hi = b[k];
+        if (b[k] <= 0.0 && b[k] > g->lo) g->lo = b[k];
+    }
+    g->vstar = creal(csqrt(g->m1sq));
+    g->mirror_ok = (p->m1sq_im == 0.0 && p->m2sq_im == 0.0) ||
+                   (p->m1sq_re == p->m2sq_re && p->m1sq_im == -p->m2sq_im);
+}
+
+/* angular distance between two angles, in [0, pi] */
+static double ang_dist(double a, double b)
+{
+    double d = fabs(a - b);
+    return d > M_PI ? 2.0 * M_PI - d : d;
+}
+
+/* Rotated-contour class of x (Y, YRES, MIRROR or SINGULAR); for YRES,
+ * *res_sign = +1 or -1. */
+static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign)
+{
+    *res_sign = 0;
+    if (phi > g->lo && phi < g->hi) return ORC_Y;
+    /* Rotating the ray from angle 0 to phi sweeps across the bad rays between. */
+    int cross1, cross2, on1, on2;
+    if (phi > 0.0) {
+        cross1 = g->beta1 > 0.0 && g->beta1 < phi;
+        cross2 = g->beta2 > 0.0 && g->beta2 < phi;
+    } else {
+        cross1 = g->beta1 <= 0.0 && g->beta1 > phi;
+        cross2 = g->beta2 <= 0.0 && g->beta2 > phi;
+    }
+    on1 = ang_dist(phi, g->beta1) == 0.0;
+    on2 = ang_dist(phi, g->beta2) == 0.0;
+    if (on1 || on2) return ORC_SINGULAR;
+    if (cross2 && !cross1) {
+        *res_sign = phi > 0.0 ? 1 : -1;
+        return ORC_YRES;
+    }
+    if (cross1 && !cross2 && g->mirror_ok) return ORC_MIRROR;
+    return ORC_SINGULAR;
+}
+
+/* Class of x; for YRES, *res_sign = +1 or -1. */
+static int orc_classify(const orc_geometry *g, cplx x, int *res_sign)
+{
+    double v = fabs(cimag(csqrt(x)));
+    double phi = carg(x);
+    int rot = orc_rotated_class(g, phi, res_sign);
+    if (v < g->vstar) {
+        double delta = fmin(ang_dist(phi, g->beta1), ang_dist(phi, g->beta2));
+        if (v < ORC_R_NEAR * g->vstar || 1.0 - v / g->vstar >= ORC_R_SLOPE * delta ||
+            rot == ORC_SINGULAR) {
+            *res_sign = 0;
+            return ORC_R;
+        }
+    }
+    return rot;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One grid point                                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_problem *p;
+    orc_geometry geo;
+    double *gl_t, *gl_w;     /* radial GL on [-1,1] */
+    double *arc_x, *arc_w;   /* arc GL on [-1,1] */
+    double *z, *w;           /* GC-II */
+    double *r, *wr;          /* radial nodes y = r_i, dy weights (incl. Jacobian) */
+    cplx jmu;                /* subtraction term: real-axis sum at x = mu^2 */
+    double jmu_abs;
+} orc_ctx;
+
+/* sum over the contour of dy y/(y + m2^2) <1/D1>, for class cls (R, Y, YRES) */
+static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, double *absum)
+{
+    const orc_problem *p = c->p;
+    cplx m1sq = c->geo.m1sq, m2sq = c->geo.m2sq;
+    cplx sx = csqrt(x);
+    cplx s = 0.0;
+    if (cls == ORC_R) {
+        for (int i = 0; i < p->n_radial; ++i) {
+            cplx y = c->r[i];
+            cplx sy = sqrt(c->r[i]);
+            double a = 0.0;
+            cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
+            cplx pre = c->wr[i] * y / (y + m2sq);
+            s += pre * ang;
+            if (absum) *absum += cabs(pre) * a;
+        }
+        return s;
+    }
+    /* ray at the angle of x: y = r e^{i phi}, dy = e^{i phi} dr */
+    double phi = carg(x);
+    cplx e = cexp(I * phi);
+    cplx eh = cexp(I * 0.5 * phi);
+    for (int i = 0; i < p->n_radial; ++i) {
+        cplx y = e * c->r[i];
+        cplx sy = eh * sqrt(c->r[i]);
+        double a = 0.0;
+        cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
+        cplx pre = e * c->wr[i] * y / (y + m2sq);
+        s += pre * ang;
+        if (absum) *absum += cabs(pre) * a;
+    }
+    /* arc |y| = Lambda^2 from angle phi back to 0: psi(s) = phi (1 - s)/2,
+     * dy = i y psi'(s) ds = -i y (phi/2) ds */
+    double lam = sqrt(p->lambda2);
+    for (int k = 0; k < p->n_arc; ++k) {
+        double psi = 0.5 * phi * (1.0 - c->arc_x[k]);
+        cplx y = p->lambda2 * cexp(I * psi);
+        cplx sy = lam * cexp(I * 0.5 * psi);
+        double a = 0.0;
+        cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
+        cplx dy = -I * y * (0.5 * phi) * c->arc_w[k];
+        cplx pre = dy * y / (y + m2sq);
+        s += pre * ang;
+        if (absum) *absum += cabs(pre) * a;
+    }
+    if (cls == ORC_YRES) {
+        /* residue of y/(y + m2^2) <1/D1>(y) at y0 = -m2^2 is y0 <1/D1>(y0) */
+        cplx y0 = -m2sq;
+        double a = 0.0;
+        cplx ang = angular_d1(x, y0, sx * csqrt(y0), m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
+        cplx pre = res_sign * 2.0 * M_PI * I * y0;
+        s += pre * ang;
+        if (absum) *absum += cabs(pre) * a;
+    }
+    return s;
+}
+
+/* G at one point; returns the class; *cond = (sum |terms|) / |G| in unscaled units. */
+static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double *cond)
+{
+    int sign = 0;
+    int cls = orc_classify(&c->geo, x, &sign);
+    if (force_class >= 0) {
+        cls = force_class;
+        if (cls == ORC_YRES) sign = carg(x) > 0.0 ? 1 : -1;
+    }
+    double absum = c->jmu_abs;
+    double *pab = cond ? &absum : NULL;
+    cplx s;
+    if (cls == ORC_SINGULAR) {
+        *g = NAN + I * NAN;
+        if (cond) *cond = NAN;
+        return cls;
+    }
+    if (cls == ORC_MIRROR) {
+        cplx xb = conj(x);
+        int sb = 0;
+        int cb = orc_classify(&c->geo, xb, &sb);
+        if (cb == ORC_MIRROR || cb == ORC_SINGULAR) {
+            *g = NAN + I * NAN;
+            if (cond) *cond = NAN;
+            return ORC_SINGULAR;
+        }
+        s = orc_contour_sum(c, xb, cb, sb, pab);
+        cplx gb = c->p->scale * (s - c->jmu);
+        *g = conj(gb);
+        if (cond) *cond = c->p->scale * absum / cabs(gb);
+        return cls;
+    }
+    s = orc_contour_sum(c, x, cls, sign, pab);
+    *g = c->p->scale * (s - c->jmu);
+    if (cond) *cond = c->p->scale * absum / cabs(*g);
+    return cls;
+}
+
+static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
+{
+    memset(c, 0, sizeof(*c));
+    c->p = p;
+    if (p->n_radial <= 0 || p->n_angular <= 0 || p->n_arc < 0) return -1;
+    orc_make_geometry(p, &c->geo);
+    int nr = p->n_radial, na = p->n_angular, nc = p->n_arc > 0 ? p->n_arc : 1;
+    c->gl_t = malloc(sizeof(double) * nr);
+    c->gl_w = malloc(sizeof(double) * nr);
+    c->r = malloc(sizeof(double) * nr);
+    c->wr = malloc(sizeof(double) * nr);
+    c->arc_x = malloc(sizeof(double) * nc);
+    c->arc_w = malloc(sizeof(double) * nc);
+    c->z = malloc(sizeof(double) * na);
+    c->w = malloc(sizeof(double) * na);
+    orc_gauss_legendre(nr, c->gl_t, c->gl_w);
+    if (p->n_arc > 0) orc_gauss_legendre(p->n_arc, c->arc_x, c->arc_w);
+    orc_gauss_cheb2(na, c->z, c->w);
+    /* t = log(1+y) on [0, T], T = log(1 + Lambda^2): y = e^t - 1, dy = (1+y) dt */
+    double T = log1p(p->lambda2);
+    for (int i = 0; i < nr; ++i) {
+        double t = 0.5 * T * (c->gl_t[i] + 1.0);
+        c->r[i] = expm1(t);
+        c->wr[i] = 0.5 * T * c->gl_w[i] * (1.0 + c->r[i]);
+    }
+    /* subtraction term (eq. 14 at x = mu^2, real axis) */
+    double a = 0.0;
+    c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, ORC_R, 0, &a);
+    c->jmu_abs = a;
+    return 0;
+}
+
+static void orc_ctx_free(orc_ctx *c)
+{
+    free(c->gl_t); free(c->gl_w); free(c->r); free(c->wr);
+    free(c->arc_x); free(c->arc_w); free(c->z); free(c->w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* G at n arbitrary points.  force_class < 0: automatic contour choice.
+ * g: 2n doubles (re, im interleaved).  cls, cond may be NULL. */
+int orc_eval_points(const orc_problem *p, long n, const double *x_re, const double *x_im,
+                    int force_class, double *g, signed char *cls, double *cond)
+{
+    orc_ctx c;
+    if (orc_ctx_init(&c, p) != 0) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < n; ++k) {
+        cplx gk;
+        double ck = 0.0;
+        int cl = orc_point(&c, x_re[k] + I * x_im[k], force_class, &gk, cond ? &ck : NULL);
+        g[2 * k] = creal(gk);
+        g[2 * k + 1] = cimag(gk);
+        if (cls) cls[k] = (signed char)cl;
+        if (cond) cond[k] = ck;
+    }
+    orc_ctx_free(&c);
+    return 0;
+}
+
+/* Cell-centred grid point (a, b) of an n_re x n_im box (STEP 4):
+ * Re x = fma(a + 1/2, (re_hi - re_lo)/n_re, re_lo), likewise Im x.
+ * Row-major, a (the Re index) fastest. */
+void orc_grid_point(long a, long b, long n_re, long n_im, double re_lo, double re_hi,
+                    double im_lo, double im_hi, double *xr, double *xi)
+{
+    double dre = (re_hi - re_lo) / (double)n_re;
+    double dim = (im_hi - im_lo) / (double)n_im;
+    *xr = fma((double)a + 0.5, dre, re_lo);
+    *xi = fma((double)b + 0.5, dim, im_lo);
+}
+
+/* Whole grid: out has 2 n_re n_im doubles, index (b n_re + a). */
+int orc_scan(const orc_problem *p, long n_re, long n_im, double re_lo, double re_hi,
+             double im_lo, double im_hi, double *g, signed char *cls, double *cond)
+{
+    long n = n_re * n_im;
+    double *xr = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *xi = malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (long b = 0; b < n_im; ++b)
+        for (long a = 0; a < n_re; ++a)
+            orc_grid_point(a, b, n_re, n_im, re_lo, re_hi, im_lo, im_hi,
+                           &xr[b * n_re + a], &xi[b * n_re + a]);
+    int rc = orc_eval_points(p, n, xr, xi, -1, g, cls, cond);
+    free(xr);
+    free(xi);
+    return rc;
+}
+
+/* The subtraction term sum (unscaled), for tests. */
+int orc_jmu(const orc_problem *p, double *re, double *im)
+{
+    orc_ctx c;
+    if (orc_ctx_init(&c, p) != 0) return -1;
+    *re = creal(c.jmu);
+    *im = cimag(c.jmu);
+    orc_ctx_free(&c);
+    return 0;
+}
+
+/* Class of each point without evaluating (for tests). */
+int orc_classify_points(const orc_problem *p, long n, const double *x_re, const double *x_im,
+                        signed char *cls)
+{
+    orc_geometry g;
+    orc_make_geometry(p, &g);
+    for (long k = 0; k < n; ++k) {
+        int s;
+        cls[k] = (signed char)orc_classify(&g, x_re[k] + I * x_im[k], &s);
+    }
+    return 0;
+}
+
+/* Integrand evaluations a point of class cls costs (n_angular per contour node). */
+long orc_evals_for_class(const orc_problem *p, int cls)
+{
+    long nodes = 0;
+    switch (cls) {
+    case ORC_R: nodes = p->n_radial; break;
+    case ORC_Y: nodes = p->n_radial + p->n_arc; break;
+    case ORC_YRES: nodes = p->n_radial + p->n_arc + 1; break;
+    default: nodes = 0;
+    }
+    return nodes * p->n_angular;
+}

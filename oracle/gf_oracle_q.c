@@ -1,0 +1,237 @@
+/*
+ * Quad-precision (__float128) brute force of the same quadrature as the FP64
+ * oracle: identical rules, contour choice and subtraction, every node, weight
+ * and sum carried in 113-bit arithmetic.  Only tiny grids are meant for it.
+ *
+ * TEST INFRASTRUCTURE ONLY (see the FP64 oracle's header).  It exists to
+ * measure the rounding error of the FP64 oracle (and, through it, of the GPU
+ * path), not to be fast.
+ *
+ * Written separately from the FP64 oracle: the two files share no code.
+ */
+#include <math.h>
+#include <quadmath.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __float128 qr;
+typedef __complex128 qc;
+
+typedef struct {
+    double m1sq_re, m1sq_im, m2sq_re, m2sq_im;
+    double mu2, lambda2, scale;
+    int n_radial, n_angular, n_arc;
+} orcq_problem;   /* same layout as the FP64 oracle's problem struct */
+
+#define QPI M_PIq
+
+static qc mkc(qr re, qr im)
+{
+    qc z;
+    __real__ z = re;
+    __imag__ z = im;
+    return z;
+}
+
+/* Legendre roots by Newton in quad precision, seeded from the asymptotic guess. */
+static void q_gauss_legendre(int n, qr *x, qr *w)
+{
+    for (int i = 0; i < n; ++i) {
+        qr r = cosq(QPI * (i + 0.75Q) / (n + 0.5Q));
+        qr dp = 1, pn = 0, pnm1 = 0;
+        for (int it = 0; it < 200; ++it) {
+            qr p0 = 1, p1 = r;
+            for (int k = 2; k <= n; ++k) {
+                qr p2 = ((2 * k - 1) * r * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            pn = (n == 1) ? r : p1;
+            pnm1 = (n == 1) ? 1 : p0;
+            dp = n * (r * pn - pnm1) / (r * r - 1);
+            qr step = pn / dp;
+            r -= step;
+            if (fabsq(step) < 1e-33Q) break;
+        }
+        qr p0 = 1, p1 = r;
+        for (int k = 2; k <= n; ++k) {
+            qr p2 = ((2 * k - 1) * r * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        pn = (n == 1) ? r : p1;
+        pnm1 = (n == 1) ? 1 : p0;
+        dp = n * (r * pn - pnm1) / (r * r - 1);
+        x[n - 1 - i] = r;
+        w[n - 1 - i] = 2 / ((1 - r * r) * dp * dp);
+    }
+}
+
+/* sum_j w_j / (x + y + m1^2 - 2 sxsy z_j), GC-II of order n */
+static qc q_angular(qc x, qc y, qc sxsy, qc m1sq, int n)
+{
+    qc acc = 0;
+    for (int j = 1; j <= n; ++j) {
+        qr th = j * QPI / (n + 1);
+        qr s = sinq(th);
+        qr z = cosq(th);
+        qr w = 2 * s * s / (n + 1);
+        acc += w / (x + y - 2 * sxsy * z + m1sq);
+    }
+    return acc;
+}
+
+/* Contour classes, numbered as in the FP64 oracle */
+enum { Q_R = 0, Q_Y = 1, Q_YRES = 2, Q_MIRROR = 3, Q_SINGULAR = 4 };
+
+typedef struct {
+    const orcq_problem *p;
+    qc m1sq, m2sq;
+    qr beta1, beta2, lo, hi, vstar;
+    int mirror_ok;
+    qr *r, *wr, *ax, *aw;
+    qc jmu;
+} qctx;
+
+static qr q_angdist(qr a, qr b)
+{
+    qr d = fabsq(a - b);
+    return d > QPI ? 2 * QPI - d : d;
+}
+
+static int q_classify(const qctx *c, qc x, int *sign)
+{
+    qr v = fabsq(cimagq(csqrtq(x)));
+    qr phi = cargq(x);
+    int rot;
+    *sign = 0;
+    if (phi > c->lo && phi < c->hi) {
+        rot = Q_Y;
+    } else {
+        int c1, c2;
+        if (phi > 0) {
+            c1 = c->beta1 > 0 && c->beta1 < phi;
+            c2 = c->beta2 > 0 && c->beta2 < phi;
+        } else {
+            c1 = c->beta1 <= 0 && c->beta1 > phi;
+            c2 = c->beta2 <= 0 && c->beta2 > phi;
+        }
+        int on = q_angdist(phi, c->beta1) == 0 || q_angdist(phi, c->beta2) == 0;
+        if (on) rot = Q_SINGULAR;
+        else if (c2 && !c1) { rot = Q_YRES; *sign = phi > 0 ? 1 : -1; }
+        else if (c1 && !c2 && c->mirror_ok) rot = Q_MIRROR;
+        else rot = Q_SINGULAR;
+    }
+    if (v < c->vstar) {
+        qr d1 = q_angdist(phi, c->beta1), d2 = q_angdist(phi, c->beta2);
+        qr delta = d1 < d2 ? d1 : d2;
+        if (v < 0.25Q * c->vstar || 1 - v / c->vstar >= 0.45Q * delta || rot == Q_SINGULAR) {
+            *sign = 0;
+            return Q_R;
+        }
+    }
+    return rot;
+}
+
+static qc q_contour(const qctx *c, qc x, int cls, int sign)
+{
+    const orcq_problem *p = c->p;
+    qc sx = csqrtq(x);
+    qc s = 0;
+    if (cls == Q_R) {
+        for (int i = 0; i < p->n_radial; ++i) {
+            qc y = mkc(c->r[i], 0);
+            qc a = q_angular(x, y, sx * sqrtq(c->r[i]), c->m1sq, p->n_angular);
+            s += c->wr[i] * y / (y + c->m2sq) * a;
+        }
+        return s;
+    }
+    qr phi = cargq(x);
+    qc e = mkc(cosq(phi), sinq(phi));
+    qc eh = mkc(cosq(phi / 2), sinq(phi / 2));
+    for (int i = 0; i < p->n_radial; ++i) {
+        qc y = e * c->r[i];
+        qc a = q_angular(x, y, sx * eh * sqrtq(c->r[i]), c->m1sq, p->n_angular);
+        s += e * c->wr[i] * y / (y + c->m2sq) * a;
+    }
+    qr L2 = p->lambda2, L = sqrtq(L2);
+    for (int k = 0; k < p->n_arc; ++k) {
+        qr psi = phi * (1 - c->ax[k]) / 2;
+        qc y = L2 * mkc(cosq(psi), sinq(psi));
+        qc sy = L * mkc(cosq(psi / 2), sinq(psi / 2));
+        qc a = q_angular(x, y, sx * sy, c->m1sq, p->n_angular);
+        qc dy = mkc(0, -1) * y * (phi / 2) * c->aw[k];
+        s += dy * y / (y + c->m2sq) * a;
+    }
+    if (cls == Q_YRES) {
+        qc y0 = -c->m2sq;
+        qc a = q_angular(x, y0, sx * csqrtq(y0), c->m1sq, p->n_angular);
+        s += sign * 2 * QPI * mkc(0, 1) * y0 * a;
+    }
+    return s;
+}
+
+/* G at n points in quad precision, rounded to double on output (g: 2n doubles). */
+int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const double *x_im,
+                     double *g, signed char *cls)
+{
+    qctx c;
+    memset(&c, 0, sizeof(c));
+    c.p = p;
+    c.m1sq = mkc(p->m1sq_re, p->m1sq_im);
+    c.m2sq = mkc(p->m2sq_re, p->m2sq_im);
+    c.beta1 = (p->m1sq_im == 0) ? QPI : cargq(-c.m1sq);
+    c.beta2 = (p->m2sq_im == 0) ? QPI : cargq(-c.m2sq);
+    c.hi = QPI;
+    c.lo = -QPI;
+    qr b[2] = {c.beta1, c.beta2};
+    for (int k = 0; k < 2; ++k) {
+        if (b[k] > 0 && b[k] < c.hi) c.hi = b[k];
+        if (b[k] <= 0 && b[k] > c.lo) c.lo = b[k];
+    }
+    c.vstar = crealq(csqrtq(c.m1sq));
+    c.mirror_ok = (p->m1sq_im == 0 && p->m2sq_im == 0) ||
+                  (p->m1sq_re == p->m2sq_re && p->m1sq_im == -p->m2sq_im);
+    int nr = p->n_radial, nc = p->n_arc > 0 ? p->n_arc : 1;
+    qr *t = malloc(sizeof(qr) * nr), *tw = malloc(sizeof(qr) * nr);
+    c.r = malloc(sizeof(qr) * nr);
+    c.wr = malloc(sizeof(qr) * nr);
+    c.ax = malloc(sizeof(qr) * nc);
+    c.aw = malloc(sizeof(qr) * nc);
+    q_gauss_legendre(nr, t, tw);
+    if (p->n_arc > 0) q_gauss_legendre(p->n_arc, c.ax, c.aw);
+    qr T = log1pq((qr)p->lambda2);
+    for (int i = 0; i < nr; ++i) {
+        qr tt = T * (t[i] + 1) / 2;
+        c.r[i] = expm1q(tt);
+        c.wr[i] = T / 2 * tw[i] * (1 + c.r[i]);
+    }
+    c.jmu = q_contour(&c, mkc(p->mu2, 0), Q_R, 0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < n; ++k) {
+        qc x = mkc(x_re[k], x_im[k]);
+        int sign;
+        int cl = q_classify(&c, x, &sign);
+        qc gk;
+        if (cl == Q_SINGULAR) {
+            gk = mkc(NAN, NAN);
+        } else if (cl == Q_MIRROR) {
+            qc xb = conjq(x);
+            int sb;
+            int cb = q_classify(&c, xb, &sb);
+            if (cb == Q_MIRROR || cb == Q_SINGULAR) {
+                gk = mkc(NAN, NAN);
+                cl = Q_SINGULAR;
+            } else {
+                gk = conjq((qr)p->scale * (q_contour(&c, xb, cb, sb) - c.jmu));
+            }
+        } else {
+            gk = (qr)p->scale * (q_contour(&c, x, cl, sign) - c.jmu);
+        }
+        g[2 * k] = (double)crealq(gk);
+        g[2 * k + 1] = (double)cimagq(gk);
+        if (cls) cls[k] = (signed char)cl;
+    }
+    free(t); free(tw); free(c.r); free(c.wr); free(c.ax); free(c.aw);
+    return 0;
+}

@@ -1,0 +1,406 @@
+"""Pins of the CPU oracle against results fixed by the paper and by the
+mathematics, independent of the oracle's own code (no GPU needed).
+
+Each test names what it pins.  A plausible slip in the oracle -- a dropped
+Jacobian, a wrong node count, a sign of the residue, a transposed mass, a
+missed conjugation in the mirror class -- fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_1205_0752_amd.workloads import Grid, Params, Quadrature
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build()
+
+
+# ---------------------------------------------------------------- quadrature rules
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 64, 257])
+def test_gauss_legendre_integrates_polynomials_exactly(n):
+    """An n-point Gauss-Legendre rule is exact for degree <= 2n-1."""
+    x, w = oracle.gauss_legendre(n)
+    for k in range(0, min(2 * n, 40)):
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** k) - exact) < 4e-15 * max(1.0, n / 16), (n, k)
+    assert np.all(np.diff(x) > 0)
+
+
+@pytest.mark.parametrize("n", [3, 32, 100, 250])
+def test_gauss_legendre_matches_numpy(n):
+    """Independent implementation: numpy's Golub-Welsch based leggauss."""
+    x, w = oracle.gauss_legendre(n)
+    xn, wn = np.polynomial.legendre.leggauss(n)
+    assert np.max(np.abs(x - xn)) < 1e-14
+    assert np.max(np.abs(w - wn)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 32, 128, 511])
+def test_gauss_chebyshev2_moments(n):
+    """(2/pi) int sqrt(1-z^2) z^(2k) dz = Catalan(k) / 4^k, exact for 2k <= 2n-1."""
+    z, w = oracle.gauss_cheb2(n)
+    assert abs(w.sum() - 1.0) < 1e-14
+    for k in range(0, min(n, 12)):
+        catalan = math.comb(2 * k, k) / (k + 1)
+        assert abs(np.sum(w * z ** (2 * k)) - catalan / 4 ** k) < 1e-14, (n, k)
+        assert abs(np.sum(w * z ** (2 * k + 1))) < 1e-14
+    # symmetric nodes: z_j = -z_{n+1-j}
+    assert np.max(np.abs(z + z[::-1])) < 1e-15
+
+
+# ---------------------------------------------------------------- inner angular sum
+
+def _random_uv(rng, k):
+    for _ in range(k):
+        u = complex(*rng.normal(size=2)) * 10 ** rng.uniform(-1, 3)
+        v = complex(*rng.normal(size=2)) * abs(u) * rng.uniform(0.05, 1.5)
+        yield u, v
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 33, 128, 512])
+def test_angular_sum_equals_discrete_closed_form(n):
+    """P1: sum_j w_j/(U - V z_j) = 2/(U+S) (1 - q^2n)/(1 - q^(2n+2)) exactly."""
+    rng = np.random.default_rng(n)
+    for u, v in _random_uv(rng, 25):
+        got = oracle.angular_sum(u, v, n)
+        ref = cf.gc2_discrete(u, v, n)
+        # conditioning of the sum: sum |terms| / |sum|
+        z, w = oracle.gauss_cheb2(n)
+        kappa = np.sum(np.abs(w / (u - v * z))) / abs(ref)
+        assert abs(got - ref) <= 4e-16 * (n + 8) * kappa * abs(ref), (u, v, n)
+
+
+def test_angular_sum_at_v_zero_is_one_over_u():
+    """P8: V = 0 (x = 0 or y = 0) gives <1/U> = 1/U since the weights sum to 1."""
+    for u in (1 + 2j, -3.5 + 0.1j, 1e6 - 1j):
+        for n in (4, 31, 256):
+            got = oracle.angular_sum(u, 0j, n)
+            assert abs(got - 1 / u) <= 4e-16 * n * abs(1 / u)
+
+
+def test_angular_sum_converges_to_continuum():
+    """Large n: the GC-II sum tends to 2/(U + sqrt(U^2 - V^2))."""
+    rng = np.random.default_rng(5)
+    for u, v in _random_uv(rng, 10):
+        ref = cf.angular_continuum(u, v)
+        got = oracle.angular_sum(u, v, 4000)
+        q = v / (u + (complex(np.sqrt(u * u - v * v)) if abs(u + np.sqrt(u * u - v * v)) >= abs(
+            u - np.sqrt(u * u - v * v)) else -complex(np.sqrt(u * u - v * v))))
+        bound = 4 * abs(ref) * abs(q) ** (2 * 4000) / max(1e-300, 1 - abs(q) ** 2) + 1e-12 * abs(ref)
+        assert abs(got - ref) <= bound, (u, v)
+
+
+def test_angular_sum_sign_flip_invariance():
+    """P7: the symmetric rule makes the sum even in V, i.e. in sqrt(x) sqrt(y)."""
+    rng = np.random.default_rng(9)
+    for u, v in _random_uv(rng, 20):
+        a = oracle.angular_sum(u, v, 64)
+        b = oracle.angular_sum(u, -v, 64)
+        assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def test_massless_angular_average():
+    """P8: for m1 = 0 and real x, y > 0, <1/((p-k)^2)> = 1/max(x, y) in D = 4."""
+    for x, y in ((1.0, 3.0), (2.5, 0.4), (10.0, 11.0)):
+        got = oracle.angular_sum(x + y, 2 * math.sqrt(x * y), 4000)
+        assert abs(got - 1 / max(x, y)) < 1e-10
+
+
+# ---------------------------------------------------------------- the worked example
+
+def _load_eq18():
+    with open(os.path.join(GOLDEN, "eq18_points.json")) as f:
+        d = json.load(f)
+    xs = np.array([p[0] + 1j * p[1] for p in d["points"]])
+    gs = np.array([p[2] + 1j * p[3] for p in d["points"]])
+    return xs, gs
+
+
+def test_golden_eq18_values_match_formula():
+    """The stored eq. 18 values re-evaluate to themselves (fixture integrity)."""
+    xs, gs = _load_eq18()
+    for x, g in zip(xs, gs):
+        assert abs(cf.eq18(x) - g) < 1e-15 * max(1, abs(g))
+
+
+def test_eq18_structure():
+    """eq. 18 vanishes at the subtraction point x = 0, is continuous across the
+    real segment (-1, 1) and for x > 1, and jumps across x < -1 (its only cut)."""
+    assert abs(cf.eq18(1e-7 + 1e-7j)) < 1e-6
+    eps = 1e-12
+    for s in (-0.7, -0.2, 0.3, 0.9, 1.5, 4.0):
+        assert abs(cf.eq18(s + eps * 1j) - cf.eq18(s - eps * 1j)) < 1e-9
+    for s in (-1.5, -3.0):
+        assert abs(cf.eq18(s + eps * 1j) - cf.eq18(s - eps * 1j)) > 0.1
+
+
+def _angle_to_bad_rays(x, m1sq, m2sq):
+    out = []
+    for m in (m1sq, m2sq):
+        d = abs(np.angle(x) - np.angle(-complex(m)))
+        out.append(min(d, 2 * math.pi - d))
+    return min(out)
+
+
+def test_oracle_reproduces_eq18_all_contour_classes():
+    """P3: the paper's worked example (eq. 16, m1^2 = -i/2, m2^2 = +i/2, mu^2 = 0)
+    against its exact solution eq. 18, on points spanning every contour class.
+    At Lambda^2 = 1e6 the cutoff effect is below 1e-11.  Points whose ray runs
+    within 0.3 rad of a bad ray (arg x near +-pi/2) converge more slowly: there
+    the error must fall by 100x when the node counts double."""
+    xs, gs = _load_eq18()
+    p = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0)
+    g, cls = oracle.eval_points(p, Quadrature(512, 256, 16), xs)
+    assert set(cls.tolist()) >= {oracle.R, oracle.Y, oracle.YRES, oracle.MIRROR}
+    err = np.abs(g - gs)
+    near = np.array([_angle_to_bad_rays(x, p.m1sq, p.m2sq) < 0.3 and cl != oracle.R
+                     for x, cl in zip(xs, cls)])
+    assert near.sum() >= 1 and (~near).sum() >= 15
+    assert np.max(err[~near]) < 5e-11, list(zip(xs[~near], err[~near], cls[~near]))
+    g2, _ = oracle.eval_points(p, Quadrature(1024, 512, 16), xs[near])
+    err2 = np.abs(g2 - gs[near])
+    assert np.all(err2 < err[near] / 100) and np.max(err2) < 1e-9
+
+
+def test_eq18_with_physical_normalisation():
+    """eq. 17 = eq. 18 / (16 pi^2): the scale parameter multiplies the result."""
+    xs, gs = _load_eq18()
+    p = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0 / (16 * math.pi ** 2))
+    g, _ = oracle.eval_points(p, Quadrature(512, 256, 16), xs[:4])
+    assert np.max(np.abs(g * 16 * math.pi ** 2 - gs[:4])) < 5e-11
+
+
+def test_mirror_class_carries_conjugated_cutoff_effect():
+    """At a finite cutoff the mirror class returns conj G_Lambda(conj x), whose
+    cutoff effect is conj(bias(conj x)) rather than bias(x); with Lambda^2 = 1e4
+    the difference (x - mu^2) i Im(m1^2) / Lambda^4 is resolved."""
+    p = Params(-0.5j, 0.5j, 0.0, 1e4, 1.0)
+    q = Quadrature(512, 256, 16)
+    xs = np.array([-4 + 3j, -2.5 + 1.0j, -4.9 + 4.9j])
+    g, cls = oracle.eval_points(p, q, xs)
+    assert np.all(cls == oracle.MIRROR)
+    for x, gg in zip(xs, g):
+        mirrored = cf.eq18(x) + np.conj(cf.cutoff_bias(np.conj(x), p.m1sq, p.mu2, p.lambda2))
+        plain = cf.eq18(x) + cf.cutoff_bias(x, p.m1sq, p.mu2, p.lambda2)
+        assert abs(gg - mirrored) < 2e-11
+        assert abs(gg - plain) > 10 * abs(gg - mirrored)
+
+
+# ---------------------------------------------------------------- Feynman closed form
+
+def _load_feynman():
+    with open(os.path.join(GOLDEN, "feynman_points.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", ["equal_m1_m2_1_mu2_1", "unequal_m1_1_m2_0p5_mu2_2",
+                                  "conjugate_1_pm_0p5i_mu2_1"])
+def test_oracle_matches_feynman_closed_form(case):
+    """P2: the quadrature converges to the Feynman-parameter form plus the
+    cutoff bias (x - mu^2) m1^2 / (2 Lambda^4).  Lambda^2 = 1e4 makes the bias
+    (~1e-8) visible, so dropping it fails."""
+    c = _load_feynman()[case]
+    m1 = complex(*c["m1sq"])
+    m2 = complex(*c["m2sq"])
+    p = Params(m1, m2, c["mu2"], 1e4, 1.0)
+    q = Quadrature(1024, 512, 32)
+    xs = np.array([pt[0] + 1j * pt[1] for pt in c["points"]])
+    ref = np.array([pt[2] + 1j * pt[3] for pt in c["points"]])
+    g, cls = oracle.eval_points(p, q, xs)
+    for x, gg, rr, cl in zip(xs, g, ref, cls):
+        if cl == oracle.MIRROR:
+            bias = np.conj(cf.cutoff_bias(np.conj(x), m1, p.mu2, p.lambda2))
+        else:
+            bias = cf.cutoff_bias(x, m1, p.mu2, p.lambda2)
+        assert abs(gg - (rr + bias)) < 5e-11, (x, cl, abs(gg - rr - bias))
+        if abs(bias) > 5e-9:
+            assert abs(gg - rr) > 1e-10
+
+
+def test_cutoff_convergence_rate():
+    """G_Lambda - G_infinity tends to (x - mu^2) m1^2 / (2 Lambda^4): the ratio
+    to the derived bias tends to 1 as Lambda grows (the BPHZ-subtracted integral
+    is cutoff independent in the limit, STEP 2)."""
+    x = 1.5 + 2.0j
+    ginf = cf.feynman(x, 1.0, 1.0, 1.0)
+    ratios = []
+    for lam2 in (30.0, 100.0, 300.0):
+        p = Params(1.0, 1.0, 1.0, lam2, 1.0)
+        g, _ = oracle.eval_points(p, Quadrature(1024, 512, 32), [x])
+        ratios.append((g[0] - ginf) / cf.cutoff_bias(x, 1.0, 1.0, lam2))
+    assert abs(ratios[-1] - 1) < 0.05
+    assert abs(ratios[-1] - 1) < abs(ratios[0] - 1)
+
+
+def test_cut_discontinuity_of_closed_form():
+    """P4 on the closed form: G(-s + i0) - G(-s - i0) = -2 pi i sqrt(lambda)/s
+    above threshold, 0 below."""
+    for m1, m2, s in ((1.0, 1.0, 6.0), (1.0, 0.5, 4.0), (1.0, 0.5, 1.8), (1.0, 1.0, 3.0)):
+        eps = 1e-10
+        up = cf.feynman(-s + 1j * eps, m1 * m1, m2 * m2, 1.0)
+        dn = cf.feynman(-s - 1j * eps, m1 * m1, m2 * m2, 1.0)
+        assert abs((up - dn) - cf.cut_discontinuity(s, m1, m2)) < 1e-7
+
+
+def test_oracle_discontinuity_at_moderate_distance():
+    """P4 on the quadrature: across the cut at |Im x| = 0.75 the oracle's jump
+    equals the closed form's jump at the same distance."""
+    p = Params(1.0, 1.0, 1.0, 1e6, 1.0)
+    q = Quadrature(1024, 512, 32)
+    s = 6.0
+    g, _ = oracle.eval_points(p, q, [-s + 0.75j, -s - 0.75j])
+    ref = cf.feynman(-s + 0.75j, 1, 1, 1) - cf.feynman(-s - 0.75j, 1, 1, 1)
+    assert abs((g[0] - g[1]) - ref) < 1e-8
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_conjugation_symmetry_real_masses_exact():
+    """P5: for real masses every step at conj(x) is the conjugate of the step at x."""
+    p = Params(1.0, 1.0, 1.0, 1e4, 1.0)
+    grid = Grid(32, 32, -8.0, 4.0, -4.0, 4.0)
+    g, _ = oracle.scan(p, Quadrature(64, 32, 16), grid)
+    gm = g.reshape(32, 32)
+    assert np.max(np.abs(gm - np.conj(gm[::-1]))) == 0.0
+
+
+def test_vanishes_at_subtraction_point_and_real_above_threshold():
+    """P5: G(mu^2) = 0; G is real on the real axis above -m1^2 (real masses)."""
+    p = Params(1.0, 1.0, 1.0, 1e4, 1.0)
+    q = Quadrature(64, 32, 16)
+    g, cls = oracle.eval_points(p, q, [1.0 + 0j])
+    assert cls[0] == oracle.R and abs(g[0]) < 1e-15
+    g, cls = oracle.eval_points(p, q, [0.3 + 0j, 2.0 + 0j, 5.0 + 0j, -0.5 + 0j])
+    assert np.all(cls == oracle.R)
+    assert np.max(np.abs(g.imag)) < 1e-13
+
+
+def test_contours_agree_where_both_apply():
+    """Cauchy: real-axis and rotated contours give the same continuation where
+    both are valid (real masses, right half plane, |Im sqrt x| < m1)."""
+    p = Params(1.0, 1.0, 1.0, 1e4, 1.0)
+    q = Quadrature(512, 256, 16)
+    xs = [0.5 + 0.3j, 2.0 + 1.0j, 0.2 - 0.4j, 3.0 - 0.5j]
+    gr, _ = oracle.eval_points(p, q, xs, force_class=oracle.R)
+    gy, _ = oracle.eval_points(p, q, xs, force_class=oracle.Y)
+    assert np.max(np.abs(gr - gy)) < 1e-11
+
+
+def test_residue_is_required_past_the_pole_ray():
+    """Rotating past arg(-m2^2) sweeps the k-leg pole: without the residue the
+    answer is off by an O(1) amount, with it eq. 18 is met."""
+    p = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0)
+    q = Quadrature(512, 256, 16)
+    x = -1.0 - 1.0j
+    g_auto, cls = oracle.eval_points(p, q, [x])
+    g_nores, _ = oracle.eval_points(p, q, [x], force_class=oracle.Y)
+    assert cls[0] == oracle.YRES
+    assert abs(g_auto[0] - cf.eq18(x)) < 1e-11
+    assert abs(g_nores[0] - cf.eq18(x)) > 0.1
+
+
+# ---------------------------------------------------------------- contour choice
+
+def _brute_min_d1(x, m1sq, ymax=400.0):
+    """min over y in [0, ymax], z in [-1, 1] of |x + y + m1^2 - 2 sqrt(x y) z|,
+    relative to |x| + |m1^2| (dense sampling)."""
+    y = np.concatenate([np.linspace(0.0, 10.0, 3001), np.geomspace(10.0, ymax, 400)])
+    z = np.linspace(-1.0, 1.0, 801)
+    sx = np.sqrt(complex(x))
+    d = x + y[:, None] + m1sq - 2.0 * sx * np.sqrt(y)[:, None] * z[None, :]
+    return np.min(np.abs(d)) / (abs(x) + abs(m1sq))
+
+
+@pytest.mark.parametrize("m1sq", [1.0, -0.5j, 1 + 0.5j])
+def test_region_R_validity_matches_brute_force(m1sq):
+    """Region R (real-axis contour) is valid iff the first propagator never
+    vanishes for real y >= 0, |z| <= 1; the oracle's test is
+    |Im sqrt x| < Re sqrt(m1^2).  Checked by dense sampling away from the edge."""
+    rng = np.random.default_rng(11)
+    vstar = np.sqrt(complex(m1sq)).real
+    p = Params(m1sq, np.conj(m1sq), 0.5, 1e4, 1.0)
+    q = Quadrature(16, 8, 4)
+    checked = 0
+    while checked < 40:
+        x = complex(rng.uniform(-6, 6), rng.uniform(-6, 6))
+        v = abs(np.sqrt(x).imag)
+        if abs(v - vstar) < 0.08 * vstar:
+            continue
+        m = _brute_min_d1(x, complex(m1sq))
+        if v < vstar:
+            assert m > 1e-3, (x, m)
+        else:
+            assert m < 2e-2, (x, m)
+        cls = oracle.classify(p, q, [x])[0]
+        if cls == oracle.R:
+            assert v < vstar
+        checked += 1
+
+
+def test_classes_of_paper_box():
+    """The paper's box (+-5, 128^2 cell-centred, STEP 4) for the worked example:
+    every point gets a contour (no singular points), all four classes occur,
+    and the mirror class sits on the side of arg(-m1^2) = +pi/2."""
+    p = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0)
+    grid = Grid(128, 128, -5.0, 5.0, -5.0, 5.0)
+    x = oracle.grid_points(grid)
+    cls = oracle.classify(p, Quadrature(64, 32, 16), x)
+    assert not np.any(cls == oracle.SINGULAR)
+    assert set(cls.tolist()) == {oracle.R, oracle.Y, oracle.YRES, oracle.MIRROR}
+    mir = x[cls == oracle.MIRROR]
+    assert np.all(np.angle(mir) > math.pi / 2)
+    res = x[cls == oracle.YRES]
+    assert np.all(np.angle(res) < -math.pi / 2)
+
+
+def test_singular_points_are_flagged():
+    """x on a bad ray outside region R, or on the negative real axis below
+    -m1^2 for real masses, has no valid fixed contour: NaN + SINGULAR."""
+    g, cls = oracle.eval_points(Params(-0.5j, 0.5j, 0.0, 1e6), Quadrature(32, 16, 4), [3j, -3j])
+    assert np.all(cls == oracle.SINGULAR) and np.all(np.isnan(g))
+    g, cls = oracle.eval_points(Params(1.0, 1.0, 1.0, 1e4), Quadrature(32, 16, 4), [-3 + 0j])
+    assert cls[0] == oracle.SINGULAR and np.isnan(g[0])
+
+
+def test_grid_points_are_cell_centred():
+    grid = Grid(7, 6, -8.0, 4.0, -4.0, 4.0)
+    x = oracle.grid_points(grid)
+    a = np.arange(7)
+    b = np.arange(6)
+    ref = (-8.0 + (a[None, :] + 0.5) * 12.0 / 7) + 1j * (-4.0 + (b[:, None] + 0.5) * 8.0 / 6)
+    assert np.max(np.abs(x.reshape(6, 7) - ref)) < 1e-15 * 8
+    assert np.all(x.imag != 0.0)
+
+
+# ---------------------------------------------------------------- rounding
+
+def test_fp64_oracle_against_quad_precision_brute_force():
+    """P6: the same quadrature in __float128 on a tiny grid, every class; the
+    FP64 oracle differs by rounding only (bounded by eps * sum |terms|)."""
+    cases = [(Params(1.0, 1.0, 1.0, 1e4), Grid(4, 4, -8.0, 4.0, -4.0, 4.0)),
+             (Params(1.0, 0.25, 2.0, 1e4), Grid(4, 4, -1.0, 3.0, -1.0, 1.0)),
+             (Params(-0.5j, 0.5j, 0.0, 1e6), Grid(4, 4, -5.0, 5.0, -5.0, 5.0)),
+             (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Grid(4, 4, -12.0, 6.0, -6.0, 6.0))]
+    q = Quadrature(64, 32, 16)
+    seen = set()
+    for p, grid in cases:
+        x = oracle.grid_points(grid)
+        g64, c64, cond = oracle.eval_points(p, q, x, want_cond=True)
+        gq, cq = oracle.eval_points_q(p, q, x)
+        assert np.array_equal(c64, cq)
+        seen |= set(c64.tolist())
+        err = np.abs(g64 - gq)
+        bound = 64 * 2.2e-16 * cond * np.abs(gq)
+        assert np.all(err <= bound), (err / np.abs(gq), cond)
+        assert np.median(err / np.abs(gq)) < 1e-13
+    assert seen >= {oracle.R, oracle.Y, oracle.YRES, oracle.MIRROR}
