@@ -1,0 +1,169 @@
+/*
+ * gf -- complex-plane scans of a BPHZ-subtracted one-loop two-point function
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, at every point x = p^2 of a cell-centred box in the
+ * complex plane,
+ *
+ *   G(x) = scale * [ int_C dy y <F(x,y,.)> - int_0^{Lambda^2} dy y <F(mu^2,y,.)> ]
+ *
+ *   F(x,y,z) = 1 / [ (x + y - 2 sqrt(x) sqrt(y) z + m1^2) (y + m2^2) ]
+ *   <f>      = (2/pi) int_{-1}^{1} dz sqrt(1 - z^2) f(z)
+ *
+ * which is the hyperspherical form of a 4-D Euclidean loop integral (STEP 1,
+ * eq. 5-11 of Windisch, Alkofer, Haase, Liebmann, "Examining the analytic
+ * structure of Green's functions: massive parallel complex integration using
+ * GPUs"), regularised by a zeroth-order Taylor subtraction at the real point
+ * mu^2 (STEP 2, eq. 12-14, taken at x = 0 in the paper's worked example,
+ * eq. 20) with the cutoff Lambda^2 of eq. 14, and analytically continued by
+ * deforming the y contour C per point (STEP 3, eq. 15).  Scale 1 gives the
+ * rescaled units of eq. 18 / eq. 21; scale 1/(16 pi^2) gives eq. 17.
+ *
+ * Quadrature (section "Numerical Implementation"): Gauss-Legendre in
+ * t = log(1 + y) on [0, log(1 + Lambda^2)] for the radial integral,
+ * Gauss-Chebyshev of the second kind (nodes cos(j pi/(n+1)), weight
+ * sin^2) for the angular integral, Gauss-Legendre in the angle on the closing
+ * arc |y| = Lambda^2.
+ *
+ * Contours (STEP 3): real axis (region R), ray at arg x plus the closing arc,
+ * the same plus the residue of the k-leg pole y = -m2^2, or the conjugate
+ * mirror G(x) = conj G(conj x) for real masses and conjugate mass pairs.
+ * Points with no valid contour (x on a bad ray arg x = arg(-m^2) outside
+ * region R, e.g. the negative real axis below -m1^2 for real masses) are
+ * returned as NaN + i NaN with class GF_CLASS_SINGULAR.
+ *
+ * All entry points return GF_OK or a negative error code and never throw;
+ * gf_last_error() gives a thread-local message for the last failure.
+ * Validation errors return before anything is enqueued on a stream.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define GF_OK 0
+#define GF_EINVAL (-1)        /* an argument is out of range */
+#define GF_EUNSUPPORTED (-2)  /* valid but not implemented */
+#define GF_ENOMEM (-3)        /* device or host allocation failed */
+#define GF_EDEVICE (-4)       /* a HIP runtime call failed */
+#define GF_EBUDGET (-5)       /* a serving request can never fit the budget */
+#define GF_ENOTFOUND (-6)     /* unknown serving ticket */
+
+/* ---- precision of the angular (hot) sum -------------------------------- */
+#define GF_PREC_FP64 0   /* everything in FP64 */
+#define GF_PREC_FP32C 1  /* angular sum in FP32 with compensated (two-sum)
+                            accumulation; sqrt(x), contour choice, per-node
+                            coefficients, radial sum, mu^2 subtraction and
+                            scaling in FP64 */
+
+/* ---- contour classes (values of the optional class map) ---------------- */
+#define GF_CLASS_R 0         /* real axis [0, Lambda^2] */
+#define GF_CLASS_Y 1         /* ray at arg x + arc |y| = Lambda^2 */
+#define GF_CLASS_YRES 2      /* ray + arc + residue at y = -m2^2 */
+#define GF_CLASS_MIRROR 3    /* conj of the value at conj x */
+#define GF_CLASS_SINGULAR 4  /* no valid contour: NaN */
+
+/* Integrand parameters (eq. 14-16).  m1^2 sits on the (p-k) leg, m2^2 on the
+ * k leg; neither may lie on the non-positive real axis.  mu2 is the real
+ * subtraction point (>= 0), lambda2 the cutoff Lambda^2 (> 0), scale the
+ * output multiplier. */
+typedef struct {
+    double m1sq_re, m1sq_im;
+    double m2sq_re, m2sq_im;
+    double mu2;
+    double lambda2;
+    double scale;
+} gf_params;
+
+/* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
+ * n_angular Gauss-Chebyshev-II nodes (1..8192), n_arc Gauss-Legendre nodes on
+ * the closing arc (0..1024; 0 drops the arc), precision GF_PREC_*. */
+typedef struct {
+    int32_t n_radial;
+    int32_t n_angular;
+    int32_t n_arc;
+    int32_t precision;
+} gf_quadrature;
+
+/* Cell-centred n_re x n_im box (STEP 4): point (a, b), 0 <= a < n_re,
+ * 0 <= b < n_im, is
+ *   Re x = fma(a + 0.5, (re_hi - re_lo) / n_re, re_lo)
+ *   Im x = fma(b + 0.5, (im_hi - im_lo) / n_im, im_lo)
+ * and its result is element b * n_re + a (Re index fastest).  Requires
+ * re_lo < re_hi, im_lo < im_hi, finite; n_re, n_im >= 0 with
+ * n_re * n_im <= 2^31. */
+typedef struct {
+    int32_t n_re, n_im;
+    double re_lo, re_hi, im_lo, im_hi;
+} gf_grid;
+
+/* Opaque plan: device-resident node tables and the subtraction constant for
+ * one (params, quadrature) pair, bound to the device current at creation. */
+typedef struct gf_plan gf_plan_t;
+
+/* Builds a plan (STEP 4 preparation): generates the nodes and weights on the
+ * host in FP64 (radial, angular, arc), uploads them, and computes the
+ * subtraction sum at x = mu^2 on the device (eq. 14's subtracted term on the
+ * real axis).  Synchronous.  *out receives the plan; free it with gf_free.
+ * Errors: GF_EINVAL (counts, masses, mu2, lambda2, scale out of range),
+ * GF_ENOMEM, GF_EDEVICE. */
+int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out);
+
+/* Scans a grid with a plan (STEP 5, eq. 15 at every point): launches the
+ * fused grid/contour/quadrature kernel on `stream` (a hipStream_t, NULL for
+ * the default stream) and returns without waiting.
+ *   out      caller-owned device buffer of n_re * n_im complex128
+ *            (interleaved re, im doubles), written once per point
+ *   cls_out  optional caller-owned device buffer of n_re * n_im int8 contour
+ *            classes (GF_CLASS_*), or NULL
+ * The plan and buffers must stay valid until the stream has executed the
+ * scan.  The current device must be the plan's device.
+ * Errors (nothing enqueued): GF_EINVAL (bad grid, NULL out, Lambda^2 too
+ * small for the box: it must exceed (sqrt|x| + sqrt(|x| + |m1^2|))^2 at every
+ * corner so the closing arc stays clear of the angular cut), GF_EDEVICE. */
+int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
+                 void *stream);
+
+/* As gf_scan_plan with an explicit number of lanes per grid point
+ * (1, 2, 4, ..., 64; 0 = automatic).  Each point's quadrature nodes are
+ * split across that many lanes of a 64-wide wavefront and the partial sums
+ * reduced with cross-lane shuffles; automatic picks 1 for large grids and more
+ * lanes for small ones so that the launch fills the GPU. */
+int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
+                    int lanes_per_point, void *stream);
+
+/* One-call scan: looks up (or builds and caches) the plan for
+ * (params, quadrature) on the current device, then behaves as gf_scan_plan.
+ * Cached plans live until gf_cache_clear() or process exit. */
+int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad,
+            void *out, void *stream);
+
+/* Releases a plan.  The caller must have synchronised every stream that uses
+ * it.  NULL is ignored. */
+void gf_free(gf_plan_t *plan);
+
+/* Frees every plan cached by gf_scan.  Same synchronisation rule. */
+void gf_cache_clear(void);
+
+/* Plan introspection: the unscaled subtraction sum at mu^2 and the lanes per
+ * point the automatic choice would use for a grid.  Errors: GF_EINVAL. */
+int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im);
+int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *gf_last_error(void);
+
+/* Library version string. */
+const char *gf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

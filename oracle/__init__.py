@@ -74,6 +74,7 @@ def _load():
                                             ctypes.c_char_p]
         lib.orc_evals_for_class.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int]
         lib.orc_evals_for_class.restype = ctypes.c_long
+        lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -211,6 +212,11 @@ def eval_points_q(params, quad, x):
     pr = problem(params, quad)
     lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls)
     return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 def jmu(params, quad) -> complex:

@@ -45,6 +45,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -130,7 +131,9 @@ int orc_gauss_cheb2(int n, double *z, double *w)
 /* ------------------------------------------------------------------------ */
 
 /* <1/D1> for D1 = x + y + m1^2 - 2 sqrt(x) sqrt(y) z, at given sxsy = sqrt(x)sqrt(y).
- * Also adds sum_j |w_j / D1_j| to *absum (a conditioning measure). */
+ * If absum is given, adds sum_j |w_j / D1_j| (1 + (|x + y + m1^2| + |2 sxsy z_j|)/|D1_j|):
+ * each term's size times its first-order sensitivity to relative perturbations
+ * of its inputs (a conditioning measure, see orc_eval_points). */
 static cplx angular_d1(cplx x, cplx y, cplx sxsy, cplx m1sq, int n,
                        const double *z, const double *w, double *absum)
 {
@@ -140,7 +143,8 @@ static cplx angular_d1(cplx x, cplx y, cplx sxsy, cplx m1sq, int n,
         cplx d1 = x + y - 2.0 * sxsy * z[j] + m1sq;
         cplx t = w[j] / d1;
         acc += t;
-        if (absum) a += cabs(t);
+        if (absum)
+            a += cabs(t) * (1.0 + (cabs(x + y + m1sq) + cabs(2.0 * sxsy * z[j])) / cabs(d1));
     }
     if (absum) *absum += a;
     return acc;
@@ -276,7 +280,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
             cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
             cplx pre = c->wr[i] * y / (y + m2sq);
             s += pre * ang;
-            if (absum) *absum += cabs(pre) * a;
+            if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
         }
         return s;
     }
@@ -291,7 +295,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
         cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
         cplx pre = e * c->wr[i] * y / (y + m2sq);
         s += pre * ang;
-        if (absum) *absum += cabs(pre) * a;
+        if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
     }
     /* arc |y| = Lambda^2 from angle phi back to 0: psi(s) = phi (1 - s)/2,
      * dy = i y psi'(s) ds = -i y (phi/2) ds */
@@ -305,7 +309,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
         cplx dy = -I * y * (0.5 * phi) * c->arc_w[k];
         cplx pre = dy * y / (y + m2sq);
         s += pre * ang;
-        if (absum) *absum += cabs(pre) * a;
+        if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
     }
     if (cls == ORC_YRES) {
         /* residue of y/(y + m2^2) <1/D1>(y) at y0 = -m2^2 is y0 <1/D1>(y0) */
@@ -319,7 +323,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
     return s;
 }
 
-/* G at one point; returns the class; *cond = (sum |terms|) / |G| in unscaled units. */
+/* G at one point; returns the class; *cond as described at orc_eval_points. */
 static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double *cond)
 {
     int sign = 0;
@@ -400,7 +404,12 @@ static void orc_ctx_free(orc_ctx *c)
 /* ------------------------------------------------------------------------ */
 
 /* G at n arbitrary points.  force_class < 0: automatic contour choice.
- * g: 2n doubles (re, im interleaved).  cls, cond may be NULL. */
+ * g: 2n doubles (re, im interleaved).  cls, cond may be NULL.
+ * cond[k] = scale * sum over every term of |term| * (its first-order
+ * sensitivity to relative input perturbations) / |G|, with the subtraction sum
+ * counted the same way: a second FP64 evaluation of the same quadrature whose
+ * inputs and operations are each accurate to a few ulp differs from this one
+ * by a small multiple of eps * cond * |G|. */
 int orc_eval_points(const orc_problem *p, long n, const double *x_re, const double *x_im,
                     int force_class, double *g, signed char *cls, double *cond)
 {
@@ -485,3 +494,6 @@ long orc_evals_for_class(const orc_problem *p, int cls)
     }
     return nodes * p->n_angular;
 }
+
+/* Threads an OpenMP region of the oracle uses. */
+int orc_threads(void) { return omp_get_max_threads(); }

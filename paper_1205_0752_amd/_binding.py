@@ -1,0 +1,201 @@
+"""ctypes binding of the gf C ABI (include/gf.h).
+
+Argument marshalling only: every step of a scan runs in the HIP library.
+PyTorch supplies device memory (result tensors) and the HIP stream.  The
+library must have been built (`paper_1205_0752_amd.build.build()`); loading
+fails loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .workloads import FP32C, FP64, Grid, Params, Quadrature
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_libgf.so")
+
+GF_OK = 0
+GF_EINVAL = -1
+GF_EUNSUPPORTED = -2
+GF_ENOMEM = -3
+GF_EDEVICE = -4
+GF_EBUDGET = -5
+GF_ENOTFOUND = -6
+
+CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
+
+#: every symbol include/gf.h declares
+EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
+           "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version")
+
+
+class GFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gf error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("m1sq_re", ctypes.c_double), ("m1sq_im", ctypes.c_double),
+                ("m2sq_re", ctypes.c_double), ("m2sq_im", ctypes.c_double),
+                ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
+                ("scale", ctypes.c_double)]
+
+
+class _Quad(ctypes.Structure):
+    _fields_ = [("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32),
+                ("n_arc", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_re", ctypes.c_int32), ("n_im", ctypes.c_int32),
+                ("re_lo", ctypes.c_double), ("re_hi", ctypes.c_double),
+                ("im_lo", ctypes.c_double), ("im_hi", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Loads the built library (once)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"the gfx950 library is not built ({LIB_PATH} missing); "
+                               "run paper_1205_0752_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        lib.gf_plan.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Quad),
+                                ctypes.POINTER(vp)]
+        lib.gf_scan_plan.argtypes = [vp, ctypes.POINTER(_Grid), vp, vp, vp]
+        lib.gf_scan_plan_ex.argtypes = [vp, ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, vp]
+        lib.gf_scan.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
+                                ctypes.POINTER(_Quad), vp, vp]
+        lib.gf_free.argtypes = [vp]
+        lib.gf_free.restype = None
+        lib.gf_cache_clear.argtypes = []
+        lib.gf_cache_clear.restype = None
+        lib.gf_plan_jmu.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+        lib.gf_plan_auto_lanes.argtypes = [vp, ctypes.POINTER(_Grid)]
+        lib.gf_last_error.restype = ctypes.c_char_p
+        lib.gf_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise GFError(rc, load().gf_last_error().decode())
+    return rc
+
+
+def c_params(p: Params) -> _Params:
+    m1, m2 = complex(p.m1sq), complex(p.m2sq)
+    return _Params(m1.real, m1.imag, m2.real, m2.imag, float(p.mu2), float(p.lambda2),
+                   float(p.scale))
+
+
+def c_quad(q: Quadrature) -> _Quad:
+    return _Quad(int(q.n_radial), int(q.n_angular), int(q.n_arc), int(q.precision))
+
+
+def c_grid(g: Grid) -> _Grid:
+    return _Grid(int(g.n_re), int(g.n_im), float(g.re_lo), float(g.re_hi), float(g.im_lo),
+                 float(g.im_hi))
+
+
+def _stream_handle(stream):
+    if isinstance(stream, int):  # a raw hipStream_t (0 = default stream)
+        return ctypes.c_void_p(stream)
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Device-resident node tables and subtraction constant for one
+    (params, quadrature); see gf_plan."""
+
+    def __init__(self, params: Params, quad: Quadrature):
+        self.params = params
+        self.quad = quad
+        h = ctypes.c_void_p()
+        _check(load().gf_plan(ctypes.byref(c_params(params)), ctypes.byref(c_quad(quad)),
+                              ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def jmu(self) -> complex:
+        re, im = ctypes.c_double(), ctypes.c_double()
+        _check(load().gf_plan_jmu(self.handle, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def auto_lanes(self, grid: Grid) -> int:
+        return _check(load().gf_plan_auto_lanes(self.handle, ctypes.byref(c_grid(grid))))
+
+    def close(self):
+        """Frees the plan; the caller synchronises the streams that used it."""
+        if self._h is not None:
+            load().gf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def empty_result(grid: Grid, device=None):
+    import torch
+    return torch.empty((grid.n_im, grid.n_re), dtype=torch.complex128,
+                       device=device or torch.device("cuda", torch.cuda.current_device()))
+
+
+def scan_plan(plan: Plan, grid: Grid, out=None, cls=None, lanes: int = 0, stream=None):
+    """Launches gf_scan_plan_ex; returns `out` (complex128 [n_im, n_re]),
+    asynchronous on `stream` (default: torch's current stream)."""
+    import torch
+    if out is None:
+        out = empty_result(grid)
+    if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != grid.n_points:
+        raise ValueError("out must be a contiguous complex128 tensor with n_re * n_im elements")
+    if cls is not None and (cls.dtype != torch.int8 or not cls.is_contiguous()
+                            or cls.numel() != grid.n_points):
+        raise ValueError("cls must be a contiguous int8 tensor with n_re * n_im elements")
+    _check(load().gf_scan_plan_ex(plan.handle, ctypes.byref(c_grid(grid)),
+                                  ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
+                                  ctypes.c_void_p(cls.data_ptr() if cls is not None else 0),
+                                  int(lanes), _stream_handle(stream)))
+    return out
+
+
+def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
+    """One-call scan (gf_scan): plan looked up in the library's cache."""
+    if out is None:
+        out = empty_result(grid)
+    _check(load().gf_scan(ctypes.byref(c_params(params)), ctypes.byref(c_grid(grid)),
+                          ctypes.byref(c_quad(quad)),
+                          ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
+                          _stream_handle(stream)))
+    return out
+
+
+def cache_clear():
+    load().gf_cache_clear()
+
+
+def version() -> str:
+    return load().gf_version().decode()
+
+
+__all__ = ["Plan", "scan", "scan_plan", "cache_clear", "version", "load", "GFError", "EXPORTS",
+           "FP64", "FP32C", "LIB_PATH", "empty_result"]

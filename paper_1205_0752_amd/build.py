@@ -1,0 +1,34 @@
+"""Builds the gfx950 library `_libgf.so` in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "_libgf.so")
+SOURCES = [os.path.join(HERE, "csrc", "gf_host.cpp"), os.path.join(HERE, "csrc", "gf_kernels.hip")]
+ARCH = "gfx950"
+
+# Device code is built without packed FP32 instructions: the compiler would
+# otherwise form v_pk_* FP32 operations by itself.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
+    """Compiles every source into one shared library (always recompiles)."""
+    out = out or LIB
+    cmd = ["hipcc", "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+           "-Wall", *DEVICE_FLAGS, *(extra or []), "-o", out + ".tmp", *SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr}")
+    if verbose and r.stderr.strip():
+        print(r.stderr)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,467 @@
+// Host side of the gf C ABI: validation, quadrature tables (STEP 4
+// preparation, done on the host in FP64 as in the paper's initialisation
+// phase), plan objects, the plan cache and kernel launches.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gf.h"
+#include "gf_internal.h"
+
+struct gf_plan {
+    int device = -1;
+    gf_params params{};
+    gf_quadrature quad{};
+    void *d_mem = nullptr;  // one allocation holding every table
+    gf::ScanArgs base{};    // kernel arguments minus the grid and outputs
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------- quadrature
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence.
+void legendre(int n, double x, double *pn, double *dpn)
+{
+    double pkm1 = 1.0, pk = x;  // P_0, P_1
+    if (n == 0) {
+        *pn = 1.0;
+        *dpn = 0.0;
+        return;
+    }
+    for (int k = 1; k < n; ++k) {
+        double pkp1 = ((2 * k + 1) * x * pk - k * pkm1) / (k + 1);
+        pkm1 = pk;
+        pk = pkp1;
+    }
+    *pn = pk;
+    *dpn = n * (pkm1 - x * pk) / (1.0 - x * x);
+}
+
+// n-point Gauss-Legendre rule on [-1, 1], ascending nodes.  The positive
+// roots are found by Newton's method from Tricomi's asymptotic estimate and
+// mirrored.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const int half = (n + 1) / 2;
+    for (int i = 1; i <= half; ++i) {
+        double th = M_PI * (4.0 * i - 1.0) / (4.0 * n + 2.0);
+        double r = std::cos(th) * (1.0 - (n - 1.0) / (8.0 * n * n * n));
+        double pn = 0.0, dpn = 1.0;
+        // Newton to convergence, then one polishing step
+        for (int it = 0, extra = 0; it < 64 && extra < 2; ++it) {
+            legendre(n, r, &pn, &dpn);
+            double dr = pn / dpn;
+            r -= dr;
+            if (std::fabs(dr) < 1e-15) ++extra;
+        }
+        legendre(n, r, &pn, &dpn);
+        double wt = 2.0 / ((1.0 - r * r) * dpn * dpn);
+        // root i (counted from the top) and its mirror image
+        x[n - i] = r;
+        w[n - i] = wt;
+        x[i - 1] = -r;
+        w[i - 1] = wt;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;  // exact centre node
+}
+
+// ---------------------------------------------------------------- geometry
+
+struct Geometry {
+    double beta1, beta2, lo, hi, vstar;
+    int mirror_ok;
+};
+
+double bad_ray(double re, double im)
+{
+    // arg(-m^2); a real positive m^2 gives the negative real axis, angle +pi
+    return im == 0.0 ? M_PI : std::atan2(-im, -re);
+}
+
+Geometry make_geometry(const gf_params &p)
+{
+    Geometry g;
+    g.beta1 = bad_ray(p.m1sq_re, p.m1sq_im);
+    g.beta2 = bad_ray(p.m2sq_re, p.m2sq_im);
+    g.hi = M_PI;
+    g.lo = -M_PI;
+    for (double b : {g.beta1, g.beta2}) {
+        if (b > 0.0 && b < g.hi) g.hi = b;
+        if (b <= 0.0 && b > g.lo) g.lo = b;
+    }
+    g.vstar = std::real(std::sqrt(std::complex<double>(p.m1sq_re, p.m1sq_im)));
+    g.mirror_ok = (p.m1sq_im == 0.0 && p.m2sq_im == 0.0) ||
+                  (p.m1sq_re == p.m2sq_re && p.m1sq_im == -p.m2sq_im);
+    return g;
+}
+
+int validate_params(const gf_params *p, const gf_quadrature *q)
+{
+    if (!p || !q) return fail(GF_EINVAL, "params and quadrature must not be NULL");
+    if (q->n_radial < 1 || q->n_radial > 8192)
+        return fail(GF_EINVAL, "n_radial must be in [1, 8192], got %d", q->n_radial);
+    if (q->n_angular < 1 || q->n_angular > 8192)
+        return fail(GF_EINVAL, "n_angular must be in [1, 8192], got %d", q->n_angular);
+    if (q->n_arc < 0 || q->n_arc > 1024)
+        return fail(GF_EINVAL, "n_arc must be in [0, 1024], got %d", q->n_arc);
+    if (q->precision != GF_PREC_FP64 && q->precision != GF_PREC_FP32C)
+        return fail(GF_EINVAL, "precision must be GF_PREC_FP64 or GF_PREC_FP32C");
+    const double vals[] = {p->m1sq_re, p->m1sq_im, p->m2sq_re, p->m2sq_im,
+                           p->mu2,     p->lambda2, p->scale};
+    for (double v : vals)
+        if (!finite(v)) return fail(GF_EINVAL, "parameters must be finite");
+    if (!(p->lambda2 > 0.0)) return fail(GF_EINVAL, "lambda2 must be > 0");
+    if (!(p->mu2 >= 0.0)) return fail(GF_EINVAL, "mu2 must be >= 0");
+    if (!(p->mu2 < p->lambda2)) return fail(GF_EINVAL, "mu2 must be below lambda2");
+    if (p->m1sq_im == 0.0 && p->m1sq_re <= 0.0)
+        return fail(GF_EINVAL, "m1^2 must not lie on the non-positive real axis");
+    if (p->m2sq_im == 0.0 && p->m2sq_re <= 0.0)
+        return fail(GF_EINVAL, "m2^2 must not lie on the non-positive real axis");
+    return GF_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- plan cache
+
+std::mutex g_cache_mu;
+std::map<std::string, gf_plan_t *> g_cache;
+
+std::string cache_key(const gf_params *p, const gf_quadrature *q, int dev)
+{
+    std::string k(reinterpret_cast<const char *>(p), sizeof(*p));
+    k.append(reinterpret_cast<const char *>(q), sizeof(*q));
+    k.append(reinterpret_cast<const char *>(&dev), sizeof(dev));
+    return k;
+}
+
+int tiles_for(const gf_grid &g, int lanes, int *tiles_a, long long *n_tiles)
+{
+    int tw, th;
+    gf::tile_shape(lanes, &tw, &th);
+    long long ta = (g.n_re + tw - 1) / tw;
+    long long tb = (g.n_im + th - 1) / th;
+    *tiles_a = (int)ta;
+    *n_tiles = ta * tb;
+    return GF_OK;
+}
+
+int auto_lanes(const gf_grid &g)
+{
+    for (int l = 1; l <= 64; l *= 2) {
+        int ta;
+        long long nt;
+        tiles_for(g, l, &ta, &nt);
+        if (nt >= 4096) return l;
+    }
+    return 64;
+}
+
+int validate_grid(const gf_plan_t *plan, const gf_grid *g)
+{
+    if (!g) return fail(GF_EINVAL, "grid must not be NULL");
+    if (g->n_re < 0 || g->n_im < 0) return fail(GF_EINVAL, "grid sizes must be >= 0");
+    if ((long long)g->n_re * (long long)g->n_im > (1LL << 31))
+        return fail(GF_EINVAL, "grid has more than 2^31 points");
+    const double v[] = {g->re_lo, g->re_hi, g->im_lo, g->im_hi};
+    for (double x : v)
+        if (!finite(x)) return fail(GF_EINVAL, "grid bounds must be finite");
+    if (!(g->re_lo < g->re_hi) || !(g->im_lo < g->im_hi))
+        return fail(GF_EINVAL, "grid bounds must satisfy lo < hi");
+    // the closing arc |y| = Lambda^2 must clear the angular cut, which reaches
+    // out to |y| = (sqrt|x| + sqrt(|x| + |m1^2|))^2
+    const double m1abs = std::hypot(plan->params.m1sq_re, plan->params.m1sq_im);
+    const double cr[2] = {g->re_lo, g->re_hi}, ci[2] = {g->im_lo, g->im_hi};
+    for (double a : cr)
+        for (double b : ci) {
+            double ax = std::hypot(a, b);
+            double reach = std::sqrt(ax) + std::sqrt(ax + m1abs);
+            if (!(reach * reach < plan->params.lambda2))
+                return fail(GF_EINVAL,
+                            "lambda2 = %g is too small for the grid box: the closing arc "
+                            "needs lambda2 > %g",
+                            plan->params.lambda2, reach * reach);
+        }
+    return GF_OK;
+}
+
+int current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return GF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gf_last_error(void) { return g_error.c_str(); }
+
+const char *gf_version(void) { return "gf 0.1 (gfx950)"; }
+
+int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
+{
+    if (!out) return fail(GF_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    int rc = validate_params(params, quad);
+    if (rc != GF_OK) return rc;
+    int dev;
+    if ((rc = current_device(&dev)) != GF_OK) return rc;
+
+    const int nr = quad->n_radial, na = quad->n_angular, nc = quad->n_arc;
+    // radial nodes: GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt
+    std::vector<double> gx, gw;
+    gauss_legendre(nr, gx, gw);
+    const double T = std::log1p(params->lambda2);
+    std::vector<double> rad(3 * (size_t)nr);
+    for (int i = 0; i < nr; ++i) {
+        double t = 0.5 * T * (gx[i] + 1.0);
+        double y = std::expm1(t);
+        rad[i] = y;
+        rad[nr + i] = std::sqrt(y);
+        rad[2 * nr + i] = 0.5 * T * gw[i] * (1.0 + y);
+    }
+    // angular nodes: Gauss-Chebyshev of the second kind, weights summing to 1
+    std::vector<double> ang(2 * (size_t)na);
+    for (int j = 1; j <= na; ++j) {
+        double th = j * M_PI / (na + 1);
+        double s = std::sin(th);
+        ang[2 * (j - 1)] = std::cos(th);
+        ang[2 * (j - 1) + 1] = 2.0 * s * s / (na + 1);
+    }
+    // the same rule folded over its symmetric node pairs, FP32: (z^2, 2w)
+    const int npair = na / 2;
+    std::vector<float> ang32(2 * (size_t)npair + 2, 0.0f);
+    for (int j = 0; j < npair; ++j) {
+        double z = ang[2 * j];
+        ang32[2 * j] = (float)(z * z);
+        ang32[2 * j + 1] = (float)(2.0 * ang[2 * j + 1]);
+    }
+    if (na % 2 == 1) ang32[2 * npair] = (float)ang[2 * npair + 1];  // z = 0 node
+    // arc nodes: GL on [-1, 1]
+    std::vector<double> ax, aw;
+    if (nc > 0) gauss_legendre(nc, ax, aw);
+    std::vector<double> arc(2 * (size_t)std::max(nc, 1), 0.0);
+    for (int k = 0; k < nc; ++k) {
+        arc[k] = ax[k];
+        arc[nc + k] = aw[k];
+    }
+
+    const size_t off_rad = 0;
+    const size_t off_ang = off_rad + align256(rad.size() * sizeof(double));
+    const size_t off_arc = off_ang + align256(ang.size() * sizeof(double));
+    const size_t off_jmu = off_arc + align256(arc.size() * sizeof(double));
+    const size_t off_a32 = off_jmu + 256;
+    const size_t total = off_a32 + align256(ang32.size() * sizeof(float));
+
+    gf_plan_t *plan = new (std::nothrow) gf_plan_t();
+    if (!plan) return fail(GF_ENOMEM, "host allocation failed");
+    plan->device = dev;
+    plan->params = *params;
+    plan->quad = *quad;
+    hipError_t e = hipMalloc(&plan->d_mem, total);
+    if (e != hipSuccess) {
+        delete plan;
+        return fail(GF_ENOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
+    }
+    char *base = static_cast<char *>(plan->d_mem);
+    struct Up {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    } ups[] = {{off_rad, rad.data(), rad.size() * sizeof(double)},
+               {off_ang, ang.data(), ang.size() * sizeof(double)},
+               {off_arc, arc.data(), arc.size() * sizeof(double)},
+               {off_a32, ang32.data(), ang32.size() * sizeof(float)}};
+    for (const Up &u : ups) {
+        e = hipMemcpy(base + u.off, u.src, u.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            gf_free(plan);
+            return hip_fail(e, "hipMemcpy (tables)");
+        }
+    }
+
+    const Geometry geo = make_geometry(*params);
+    gf::ScanArgs &a = plan->base;
+    a.rad = reinterpret_cast<const double *>(base + off_rad);
+    a.ang = reinterpret_cast<const double *>(base + off_ang);
+    a.arc = reinterpret_cast<const double *>(base + off_arc);
+    a.ang32 = reinterpret_cast<const float *>(base + off_a32);
+    a.n_r = nr;
+    a.n_a = na;
+    a.n_arc = nc;
+    a.m1_re = params->m1sq_re;
+    a.m1_im = params->m1sq_im;
+    a.m2_re = params->m2sq_re;
+    a.m2_im = params->m2sq_im;
+    a.lam2 = params->lambda2;
+    a.lam = std::sqrt(params->lambda2);
+    const std::complex<double> sy0 = std::sqrt(std::complex<double>(-params->m2sq_re,
+                                                                    -params->m2sq_im));
+    a.sy0_re = sy0.real();
+    a.sy0_im = sy0.imag();
+    a.scale = params->scale;
+    a.beta1 = geo.beta1;
+    a.beta2 = geo.beta2;
+    a.lo = geo.lo;
+    a.hi = geo.hi;
+    a.vstar = geo.vstar;
+    a.mirror_ok = geo.mirror_ok;
+
+    // subtraction sum at mu^2 (FP64, real axis), computed once per plan
+    double *d_jmu = reinterpret_cast<double *>(base + off_jmu);
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        gf_free(plan);
+        return hip_fail(e, "hipStreamCreate");
+    }
+    e = gf::launch_jmu(a, params->mu2, d_jmu, s);
+    double jmu[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(jmu, d_jmu, sizeof(jmu), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        gf_free(plan);
+        return hip_fail(e, "subtraction-term kernel");
+    }
+    a.jmu_re = jmu[0];
+    a.jmu_im = jmu[1];
+    *out = plan;
+    return GF_OK;
+}
+
+void gf_free(gf_plan_t *plan)
+{
+    if (!plan) return;
+    if (plan->d_mem) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != plan->device) (void)hipSetDevice(plan->device);
+        (void)hipFree(plan->d_mem);
+        if (cur != plan->device && cur >= 0) (void)hipSetDevice(cur);
+    }
+    delete plan;
+}
+
+int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im)
+{
+    if (!plan || !re || !im) return fail(GF_EINVAL, "NULL argument");
+    *re = plan->base.jmu_re;
+    *im = plan->base.jmu_im;
+    return GF_OK;
+}
+
+int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid)
+{
+    if (!plan || !grid) return fail(GF_EINVAL, "NULL argument");
+    return auto_lanes(*grid);
+}
+
+int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
+                    int lanes_per_point, void *stream)
+{
+    if (!plan) return fail(GF_EINVAL, "plan must not be NULL");
+    int rc = validate_grid(plan, grid);
+    if (rc != GF_OK) return rc;
+    if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
+    if (!out) return fail(GF_EINVAL, "out must not be NULL");
+    int lanes = lanes_per_point;
+    if (lanes == 0) lanes = auto_lanes(*grid);
+    if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)) != 0)
+        return fail(GF_EINVAL, "lanes_per_point must be 0 or a power of two <= 64, got %d",
+                    lanes_per_point);
+    int dev;
+    if ((rc = current_device(&dev)) != GF_OK) return rc;
+    if (dev != plan->device)
+        return fail(GF_EINVAL, "plan was built on device %d, current device is %d", plan->device,
+                    dev);
+    gf::ScanArgs a = plan->base;
+    a.n_re = grid->n_re;
+    a.n_im = grid->n_im;
+    a.re_lo = grid->re_lo;
+    a.im_lo = grid->im_lo;
+    a.d_re = (grid->re_hi - grid->re_lo) / (double)grid->n_re;
+    a.d_im = (grid->im_hi - grid->im_lo) / (double)grid->n_im;
+    long long nt;
+    tiles_for(*grid, lanes, &a.tiles_a, &nt);
+    if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
+    a.n_tiles = (int)nt;
+    a.out = static_cast<double *>(out);
+    a.cls = cls_out;
+    hipError_t e = gf::launch_scan(a, plan->quad.precision, lanes, static_cast<hipStream_t>(stream));
+    if (e == hipErrorInvalidValue && plan->quad.precision != GF_PREC_FP64)
+        return fail(GF_EUNSUPPORTED, "precision %d is not available", plan->quad.precision);
+    if (e != hipSuccess) return hip_fail(e, "scan kernel launch");
+    return GF_OK;
+}
+
+int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
+                 void *stream)
+{
+    return gf_scan_plan_ex(plan, grid, out, cls_out, 0, stream);
+}
+
+int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad, void *out,
+            void *stream)
+{
+    int rc = validate_params(params, quad);
+    if (rc != GF_OK) return rc;
+    int dev;
+    if ((rc = current_device(&dev)) != GF_OK) return rc;
+    const std::string key = cache_key(params, quad, dev);
+    gf_plan_t *plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            plan = it->second;
+        } else {
+            rc = gf_plan(params, quad, &plan);
+            if (rc != GF_OK) return rc;
+            g_cache[key] = plan;
+        }
+    }
+    return gf_scan_plan(plan, grid, out, nullptr, stream);
+}
+
+void gf_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (auto &kv : g_cache) gf_free(kv.second);
+    g_cache.clear();
+}
+
+}  // extern "C"

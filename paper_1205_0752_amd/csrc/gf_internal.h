@@ -1,0 +1,71 @@
+// Internal interface between the host library (plan, validation, cache) and
+// the gfx950 kernels.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace gf {
+
+// Contour classes (same values as GF_CLASS_*).
+enum : int { kR = 0, kY = 1, kYRes = 2, kMirror = 3, kSingular = 4 };
+
+// Region-R preference: take the real-axis contour where it is valid and
+// either |Im sqrt x| < kRNear * v*, or 1 - |Im sqrt x| / v* >= kRSlope * delta
+// (delta = angular distance from arg x to the nearest bad ray).
+constexpr double kRNear = 0.25;
+constexpr double kRSlope = 0.45;
+
+// Everything a scan kernel needs, passed by value.
+struct ScanArgs {
+    // Device tables, struct-of-arrays, FP64:
+    //   rad: r[n_r], sqrt_r[n_r], w[n_r]   (y nodes in log(1+y) GL, dy weights)
+    //   ang: (z, w) pairs, n_a of them     (GC-II nodes, normalised weights)
+    //   arc: xi[n_arc], w[n_arc]           (GL on [-1, 1])
+    const double *rad;
+    const double *ang;
+    const double *arc;
+    // FP32 angular table for the mixed-precision kernel: (z^2, 2w) for the
+    // n_a/2 symmetric node pairs, then the middle weight (odd n_a) or 0.
+    const float *ang32;
+    int n_r, n_a, n_arc;
+
+    double m1_re, m1_im, m2_re, m2_im;  // m1^2, m2^2
+    double lam2, lam;                    // Lambda^2, Lambda
+    double sy0_re, sy0_im;               // sqrt(-m2^2) (residue node)
+    double jmu_re, jmu_im;               // unscaled subtraction sum at mu^2
+    double scale;
+
+    // contour geometry
+    double beta1, beta2;  // arg(-m1^2), arg(-m2^2)
+    double lo, hi;        // open sector of directly reachable ray angles
+    double vstar;         // region-R bound on |Im sqrt x|: Re sqrt(m1^2)
+    int mirror_ok;        // real masses or a conjugate pair
+
+    // grid
+    int n_re, n_im;
+    double re_lo, d_re, im_lo, d_im;
+    int tiles_a;  // wave tiles along Re
+    int n_tiles;  // total wave tiles
+
+    double *out;   // interleaved complex128
+    int8_t *cls;   // optional class map
+};
+
+// Launches the scan of one grid (FP64 or FP32C angular sum) with `lanes`
+// lanes per point.
+hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t s);
+
+// Computes the unscaled real-axis sum at x = mu^2 (FP64) into dst[0..1].
+hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s);
+
+// Tile geometry of a wave for `lanes` lanes per point: tw x th points.
+inline void tile_shape(int lanes, int *tw, int *th)
+{
+    int p = 64 / lanes;
+    *tw = p < 8 ? p : 8;
+    *th = p / *tw;
+}
+
+}  // namespace gf

@@ -1,0 +1,353 @@
+// gfx950 kernels of the complex-plane scan (STEP 4 + STEP 5 fused).
+//
+// One 64-wide wavefront owns a tile of grid points; each point is handled by
+// L lanes (L = 1 for large grids).  Per point, in FP64: the grid coordinate,
+// sqrt(x), arg x and the contour class (STEP 3), then per contour node the
+// hoisted coefficients (U, V, omega) of
+//
+//     omega * sum_j w_j / (U - V z_j),   U = x + y + m1^2,  V = 2 sqrt(x) sqrt(y),
+//     omega = dy-weight * y / (y + m2^2),
+//
+// i.e. eq. 11's angular integral of the first propagator times the y-only
+// factor of eq. 19.  The angular nodes are wave-uniform, so their table is
+// read through the scalar cache into SGPR operands; each lane keeps its point's
+// (U, V) in registers.  Partial sums of the L lanes of a point are combined
+// with cross-lane shuffles, the real-axis subtraction sum at mu^2 (eq. 14) is
+// removed, the result scaled, conjugated for mirror points, and written once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "gf_internal.h"
+
+namespace gf {
+namespace {
+
+struct cd {
+    double r, i;
+};
+
+__device__ __forceinline__ cd mk(double r, double i)
+{
+    cd z;
+    z.r = r;
+    z.i = i;
+    return z;
+}
+__device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.r + b.r, a.i + b.i); }
+__device__ __forceinline__ cd cmul(cd a, cd b)
+{
+    return mk(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
+}
+__device__ __forceinline__ cd cscale(cd a, double s) { return mk(a.r * s, a.i * s); }
+__device__ __forceinline__ cd cdiv(cd a, cd b)
+{
+    double inv = 1.0 / (b.r * b.r + b.i * b.i);
+    return mk((a.r * b.r + a.i * b.i) * inv, (a.i * b.r - a.r * b.i) * inv);
+}
+
+// principal square root; follows the sign of a zero imaginary part
+__device__ cd csqrt_principal(double a, double b)
+{
+    if (a == 0.0 && b == 0.0) return mk(0.0, b);
+    double r = hypot(a, b);
+    if (a >= 0.0) {
+        double t = sqrt(0.5 * (r + a));
+        return mk(t, b / (2.0 * t));
+    }
+    double t = sqrt(0.5 * (r - a));
+    return mk(fabs(b) / (2.0 * t), copysign(t, b));
+}
+
+__device__ __forceinline__ double angle_between(double a, double b)
+{
+    double d = fabs(a - b);
+    return d > M_PI ? 2.0 * M_PI - d : d;
+}
+
+// Contour class of x (STEP 3).  Rotating the ray from angle 0 to phi = arg x
+// is free inside (lo, hi); sweeping across the k-leg pole ray arg(-m2^2) adds
+// its residue (sign of phi); across the ray arg(-m1^2) the conjugate point is
+// used instead.  The real axis is preferred where it is valid (|Im sqrt x| <
+// v*) and either comfortably inside (v < kRNear v*) or closer to its own edge
+// than the ray is to a bad ray.
+__device__ int classify(const ScanArgs &a, double xr, double xi, int *res_sign)
+{
+    cd sx = csqrt_principal(xr, xi);
+    double v = fabs(sx.i);
+    double phi = atan2(xi, xr);
+    int rot;
+    *res_sign = 0;
+    if (phi > a.lo && phi < a.hi) {
+        rot = kY;
+    } else {
+        bool past1, past2;
+        if (phi > 0.0) {
+            past1 = a.beta1 > 0.0 && a.beta1 < phi;
+            past2 = a.beta2 > 0.0 && a.beta2 < phi;
+        } else {
+            past1 = a.beta1 <= 0.0 && a.beta1 > phi;
+            past2 = a.beta2 <= 0.0 && a.beta2 > phi;
+        }
+        bool on_bad = angle_between(phi, a.beta1) == 0.0 || angle_between(phi, a.beta2) == 0.0;
+        if (on_bad) {
+            rot = kSingular;
+        } else if (past2 && !past1) {
+            rot = kYRes;
+            *res_sign = phi > 0.0 ? 1 : -1;
+        } else if (past1 && !past2 && a.mirror_ok) {
+            rot = kMirror;
+        } else {
+            rot = kSingular;
+        }
+    }
+    if (v < a.vstar) {
+        double delta = fmin(angle_between(phi, a.beta1), angle_between(phi, a.beta2));
+        if (v < kRNear * a.vstar || 1.0 - v / a.vstar >= kRSlope * delta || rot == kSingular) {
+            *res_sign = 0;
+            return kR;
+        }
+    }
+    return rot;
+}
+
+// Per-point quantities hoisted out of the node loop.
+struct PointCtx {
+    cd x1;       // x + m1^2
+    cd sx2dir;   // 2 sqrt(x) e^{i phi/2} (ray) or 2 sqrt(x) (real axis)
+    cd sx2;      // 2 sqrt(x)
+    cd dir;      // e^{i phi} (ray) or 1 (real axis)
+    double phi;
+    int nodes;   // contour nodes of this point
+    int res_sign;
+};
+
+__device__ PointCtx point_setup(const ScanArgs &a, double xr, double xi, int cls, int res_sign)
+{
+    PointCtx P;
+    cd sx = csqrt_principal(xr, xi);
+    P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
+    P.sx2 = cscale(sx, 2.0);
+    P.res_sign = res_sign;
+    if (cls == kR) {
+        P.dir = mk(1.0, 0.0);
+        P.sx2dir = P.sx2;
+        P.phi = 0.0;
+        P.nodes = a.n_r;
+    } else if (cls == kY || cls == kYRes) {
+        double phi = atan2(xi, xr);
+        double s, c, sh, ch;
+        sincos(phi, &s, &c);
+        sincos(0.5 * phi, &sh, &ch);
+        P.dir = mk(c, s);
+        P.sx2dir = cmul(P.sx2, mk(ch, sh));
+        P.phi = phi;
+        P.nodes = a.n_r + a.n_arc + (cls == kYRes ? 1 : 0);
+    } else {
+        P.dir = mk(1.0, 0.0);
+        P.sx2dir = P.sx2;
+        P.phi = 0.0;
+        P.nodes = 0;
+    }
+    return P;
+}
+
+// Coefficients of contour node k: radial (ray or real axis), closing arc, or
+// residue of the k-leg pole.
+__device__ __forceinline__ void node_coeffs(const ScanArgs &a, const PointCtx &P, int k, cd &U,
+                                            cd &V, cd &w)
+{
+    const cd m2 = mk(a.m2_re, a.m2_im);
+    if (k < a.n_r) {
+        double r = a.rad[k];
+        double sr = a.rad[a.n_r + k];
+        double wr = a.rad[2 * a.n_r + k];
+        cd y = cscale(P.dir, r);                      // y = e^{i phi} r
+        U = cadd(P.x1, y);
+        V = cscale(P.sx2dir, sr);                     // 2 sqrt(x) sqrt(y)
+        w = cdiv(cscale(cmul(P.dir, y), wr), cadd(y, m2));  // dy y / (y + m2^2)
+    } else if (k < a.n_r + a.n_arc) {
+        int q = k - a.n_r;
+        double xi = a.arc[q];
+        double wa = a.arc[a.n_arc + q];
+        double psi = 0.5 * P.phi * (1.0 - xi);        // from phi back to 0
+        double s, c, sh, ch;
+        sincos(psi, &s, &c);
+        sincos(0.5 * psi, &sh, &ch);
+        cd y = mk(a.lam2 * c, a.lam2 * s);
+        U = cadd(P.x1, y);
+        V = cmul(P.sx2, mk(a.lam * ch, a.lam * sh));
+        double h = 0.5 * P.phi * wa;
+        cd dy = mk(y.i * h, -y.r * h);                // dy = -i y (phi/2) dxi
+        w = cdiv(cmul(dy, y), cadd(y, m2));
+    } else {
+        cd y0 = mk(-a.m2_re, -a.m2_im);
+        U = cadd(P.x1, y0);
+        V = cmul(P.sx2, mk(a.sy0_re, a.sy0_im));
+        double f = P.res_sign * 2.0 * M_PI;          // +-2 pi i Res
+        w = mk(-y0.i * f, y0.r * f);
+    }
+}
+
+__device__ __forceinline__ double rcp64(double q)
+{
+#if defined(GF_RCP_IEEE)
+    return 1.0 / q;
+#else
+    // hardware reciprocal estimate + one Newton-Raphson step
+    double r = __builtin_amdgcn_rcp(q);
+    return fma(fma(-q, r, 1.0), r, r);
+#endif
+}
+
+// sum_j w_j / (U - V z_j) over the GC-II table (z, w pairs), FP64.
+__device__ __forceinline__ cd angular_sum64(const double *__restrict__ ang, int n, cd U, cd V)
+{
+    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+    int j = 0;
+#pragma unroll 2
+    for (; j + 2 <= n; j += 2) {
+        double z0 = ang[2 * j], w0 = ang[2 * j + 1];
+        double z1 = ang[2 * j + 2], w1 = ang[2 * j + 3];
+        double dr0 = fma(-V.r, z0, U.r), di0 = fma(-V.i, z0, U.i);
+        double dr1 = fma(-V.r, z1, U.r), di1 = fma(-V.i, z1, U.i);
+        double t0 = w0 * rcp64(fma(dr0, dr0, di0 * di0));
+        double t1 = w1 * rcp64(fma(dr1, dr1, di1 * di1));
+        ar0 = fma(t0, dr0, ar0);
+        ai0 = fma(t0, di0, ai0);
+        ar1 = fma(t1, dr1, ar1);
+        ai1 = fma(t1, di1, ai1);
+    }
+    if (j < n) {
+        double z0 = ang[2 * j], w0 = ang[2 * j + 1];
+        double dr0 = fma(-V.r, z0, U.r), di0 = fma(-V.i, z0, U.i);
+        double t0 = w0 * rcp64(fma(dr0, dr0, di0 * di0));
+        ar0 = fma(t0, dr0, ar0);
+        ai0 = fma(t0, di0, ai0);
+    }
+    // w / D = w conj(D) / |D|^2
+    return mk(ar0 + ar1, -(ai0 + ai1));
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) scan_fp64_kernel(ScanArgs a)
+{
+    constexpr int P = 64 / L;
+    constexpr int TW = P < 8 ? P : 8;
+    constexpr int TH = P / TW;
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;  // uniform per wave
+    const int p = lane / L;
+    const int s = lane % L;
+    const int ia = (wave % a.tiles_a) * TW + p % TW;
+    const int ib = (wave / a.tiles_a) * TH + p / TW;
+    const bool valid = ia < a.n_re && ib < a.n_im;
+
+    // STEP 4: the grid point, generated in place
+    double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
+    double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
+    int sign = 0;
+    int cls = valid ? classify(a, xr, xi, &sign) : kSingular;
+    int ecls = cls;
+    if (cls == kMirror) {
+        xi = -xi;  // evaluate at conj x, conjugate the result
+        ecls = classify(a, xr, xi, &sign);
+        if (ecls == kMirror || ecls == kSingular) {
+            cls = kSingular;
+            ecls = kSingular;
+        }
+    }
+    const PointCtx pc = point_setup(a, xr, xi, ecls, sign);
+
+    double sr = 0.0, si = 0.0;
+    for (int k = s; k < pc.nodes; k += L) {
+        cd U, V, w;
+        node_coeffs(a, pc, k, U, V, w);
+        cd A = angular_sum64(a.ang, a.n_a, U, V);
+        cd t = cmul(w, A);
+        sr += t.r;
+        si += t.i;
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
+    }
+    if (valid && s == 0) {
+        double gr, gi;
+        if (cls == kSingular) {
+            gr = __builtin_nan("");
+            gi = __builtin_nan("");
+        } else {
+            gr = a.scale * (sr - a.jmu_re);
+            gi = a.scale * (si - a.jmu_im);
+            if (cls == kMirror) gi = -gi;
+        }
+        const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
+        reinterpret_cast<double2 *>(a.out)[idx] = make_double2(gr, gi);
+        if (a.cls) a.cls[idx] = (int8_t)cls;
+    }
+}
+
+// Subtraction sum at the real point mu^2 on the real axis (one wavefront).
+__global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double *dst)
+{
+    const int lane = threadIdx.x;
+    const PointCtx pc = point_setup(a, mu2, 0.0, kR, 0);
+    double sr = 0.0, si = 0.0;
+    for (int k = lane; k < pc.nodes; k += 64) {
+        cd U, V, w;
+        node_coeffs(a, pc, k, U, V, w);
+        cd A = angular_sum64(a.ang, a.n_a, U, V);
+        cd t = cmul(w, A);
+        sr += t.r;
+        si += t.i;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
+    }
+    if (lane == 0) {
+        dst[0] = sr;
+        dst[1] = si;
+    }
+}
+
+template <int L>
+hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
+{
+    const int blocks = (a.n_tiles + 3) / 4;
+    if (precision == 0) {
+        hipLaunchKernelGGL(scan_fp64_kernel<L>, dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    switch (lanes) {
+    case 1: return launch_l<1>(a, precision, s);
+    case 2: return launch_l<2>(a, precision, s);
+    case 4: return launch_l<4>(a, precision, s);
+    case 8: return launch_l<8>(a, precision, s);
+    case 16: return launch_l<16>(a, precision, s);
+    case 32: return launch_l<32>(a, precision, s);
+    case 64: return launch_l<64>(a, precision, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(jmu_kernel, dim3(1), dim3(64), 0, s, a, mu2, dst);
+    return hipGetLastError();
+}
+
+}  // namespace gf
