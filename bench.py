@@ -22,7 +22,12 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (256 CU x 2.4 GHz x 128 flop/clk)
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
-FLOPS_PER_EVAL = 13        # one term w/(U - V z): 5 FMA (x2) + 2 MUL + 1 RCP
+# Algorithmic flops per integrand evaluation of the folded angular sum: one
+# symmetric node pair (two evaluations) costs D = U^2 - V^2 z^2 (2 FMA), |D|^2
+# (1 MUL + 1 FMA), 1/|D|^2 (1 RCP), 2w/|D|^2 (1 MUL), acc += t conj(D) (2 FMA)
+# = 13 flops with FMA = 2, MUL = RCP = 1; Newton steps, the shared-reciprocal
+# multiplies and compensation are not counted.
+FLOPS_PER_EVAL = 6.5
 
 
 def evals_per_scan(cls, quad) -> int:
@@ -61,6 +66,38 @@ def cpu_baseline(params, quad, grid, seconds: float):
             "points_per_s": len(idx) / dt}
 
 
+def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
+    """Times `steps` scans with HIP events on the launch stream; the plan and the
+    output buffer are resident before timing starts."""
+    plan = gf.Plan(params, quad)
+    out = gf.empty_result(grid)
+    cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
+    gf.scan_plan(plan, grid, out, cls, lanes=lanes)
+    torch.cuda.synchronize()
+    evals = evals_per_scan(cls.cpu().numpy(), quad)
+    used_lanes = lanes or plan.auto_lanes(grid)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        gf.scan_plan(plan, grid, out, lanes=lanes, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        gf.scan_plan(plan, grid, out, lanes=lanes, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    plan.close()
+    sec = ms / 1e3
+    return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
+            "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
+            "wall": wall, "lanes": used_lanes,
+            "kernel": f"scan_kernel<{quad.precision},{used_lanes}>"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +107,10 @@ def main() -> int:
     ap.add_argument("--lanes", type=int, default=0, help="lanes per point (0 = automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp32c", action="store_true")
+    ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes three times "
+                         "(reference for the HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the scan "
@@ -81,60 +122,58 @@ def main() -> int:
     import paper_1205_0752_amd as gf
     from paper_1205_0752_amd.workloads import CONFIGS
 
+    if args.profile_copy:
+        n = args.profile_copy // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "repeats": 3}), flush=True)
+        return 0
+
     params, grid, quad = CONFIGS[args.config]
     torch.cuda.set_device(0)
-    plan = gf.Plan(params, quad)
-    out = gf.empty_result(grid)
-    cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
-    gf.scan_plan(plan, grid, out, cls, lanes=args.lanes)
-    torch.cuda.synchronize()
-    evals = evals_per_scan(cls.cpu().numpy(), quad)
-    lanes = args.lanes or plan.auto_lanes(grid)
-
-    for _ in range(args.warmup):
-        gf.scan_plan(plan, grid, out, lanes=args.lanes)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        gf.scan_plan(plan, grid, out, lanes=args.lanes, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
-    sec = ms / 1e3
-    flops = evals * FLOPS_PER_EVAL
-    achieved = flops / sec / 1e12
+    t = time_scan(gf, torch, params, grid, quad, args.steps, args.warmup, args.lanes)
     result = {
         "metric": "complex grid points/s & integrand evals/s (FP64 vs FP32+compensated); "
                   "p99 scan latency",
-        "value": evals / sec,
+        "value": t["evals_per_s"],
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": t["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if quad.precision == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {grid.n_re}x{grid.n_im} grid, "
                                f"{quad.n_radial}x{quad.n_angular}(+{quad.n_arc} arc) nodes, "
                                f"m1^2={params.m1sq}, m2^2={params.m2sq}, mu^2={params.mu2}, "
                                f"Lambda^2={params.lambda2:g}",
-                   "grid_points": grid.n_points, "evals_per_step": evals,
-                   "lanes_per_point": lanes, "parallelism": "single GPU"},
-        "points_per_s": grid.n_points / sec,
-        "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "scan_fp64_kernel", "flops_per_eval": FLOPS_PER_EVAL},
+                   "grid_points": grid.n_points, "evals_per_step": t["evals"],
+                   "lanes_per_point": t["lanes"], "parallelism": "single GPU"},
+        "points_per_s": t["points_per_s"],
+        "wall_s_timed": t["wall"],
+        "roofline": {"bound": "alu", "achieved": t["tflops"],
+                     "peak": FP64_PEAK_TFLOPS if quad.precision == 0 else FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": t["tflops"] / (FP64_PEAK_TFLOPS if quad.precision == 0
+                                            else FP32_PEAK_TFLOPS),
+                     "traffic": None, "kernel": t["kernel"], "flops_per_eval": FLOPS_PER_EVAL},
     }
-    plan.close()
+    if not args.skip_fp32c and args.config == "c1_fp64_1024sq":
+        p2, g2, q2 = CONFIGS["c2_fp32c_1024sq"]
+        t2 = time_scan(gf, torch, p2, g2, q2, max(2, args.steps // 2), 1, 0)
+        result["fp32c"] = {"workload": f"c2_fp32c_1024sq: {g2.n_re}x{g2.n_im} grid, "
+                                       f"{q2.n_radial}x{q2.n_angular}(+{q2.n_arc} arc) nodes",
+                           "evals_per_s": t2["evals_per_s"], "points_per_s": t2["points_per_s"],
+                           "ms_per_step": t2["ms"], "tflops": t2["tflops"],
+                           "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
+                           "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(params, quad, grid, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -144,6 +144,7 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     if (!(p->lambda2 > 0.0)) return fail(GF_EINVAL, "lambda2 must be > 0");
     if (!(p->mu2 >= 0.0)) return fail(GF_EINVAL, "mu2 must be >= 0");
     if (!(p->mu2 < p->lambda2)) return fail(GF_EINVAL, "mu2 must be below lambda2");
+    if (!(p->lambda2 <= 1e30)) return fail(GF_EINVAL, "lambda2 must be <= 1e30");
     if (p->m1sq_im == 0.0 && p->m1sq_re <= 0.0)
         return fail(GF_EINVAL, "m1^2 must not lie on the non-positive real axis");
     if (p->m2sq_im == 0.0 && p->m2sq_re <= 0.0)
@@ -253,23 +254,21 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
         rad[nr + i] = std::sqrt(y);
         rad[2 * nr + i] = 0.5 * T * gw[i] * (1.0 + y);
     }
-    // angular nodes: Gauss-Chebyshev of the second kind, weights summing to 1
-    std::vector<double> ang(2 * (size_t)na);
-    for (int j = 1; j <= na; ++j) {
-        double th = j * M_PI / (na + 1);
-        double s = std::sin(th);
-        ang[2 * (j - 1)] = std::cos(th);
-        ang[2 * (j - 1) + 1] = 2.0 * s * s / (na + 1);
-    }
-    // the same rule folded over its symmetric node pairs, FP32: (z^2, 2w)
+    // angular nodes: Gauss-Chebyshev of the second kind, weights summing to 1;
+    // stored folded over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j),
+    // z_j = cos(j pi/(n+1)), j = 1..n/2; the middle node of an odd rule is z = 0
     const int npair = na / 2;
-    std::vector<float> ang32(2 * (size_t)npair + 2, 0.0f);
-    for (int j = 0; j < npair; ++j) {
-        double z = ang[2 * j];
-        ang32[2 * j] = (float)(z * z);
-        ang32[2 * j + 1] = (float)(2.0 * ang[2 * j + 1]);
+    std::vector<double> ang(2 * (size_t)std::max(npair, 1), 0.0);
+    std::vector<float> ang32(2 * (size_t)std::max(npair, 1), 0.0f);
+    for (int j = 1; j <= npair; ++j) {
+        double th = j * M_PI / (na + 1);
+        double s = std::sin(th), c = std::cos(th);
+        ang[2 * (j - 1)] = c * c;
+        ang[2 * (j - 1) + 1] = 4.0 * s * s / (na + 1);
+        ang32[2 * (j - 1)] = (float)ang[2 * (j - 1)];
+        ang32[2 * (j - 1) + 1] = (float)ang[2 * (j - 1) + 1];
     }
-    if (na % 2 == 1) ang32[2 * npair] = (float)ang[2 * npair + 1];  // z = 0 node
+    const double wmid = (na % 2 == 1) ? 2.0 / (na + 1) : 0.0;  // sin^2(pi/2) = 1
     // arc nodes: GL on [-1, 1]
     std::vector<double> ax, aw;
     if (nc > 0) gauss_legendre(nc, ax, aw);
@@ -322,6 +321,7 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     a.n_r = nr;
     a.n_a = na;
     a.n_arc = nc;
+    a.wmid = wmid;
     a.m1_re = params->m1sq_re;
     a.m1_im = params->m1sq_im;
     a.m2_re = params->m2sq_re;

@@ -19,17 +19,17 @@ constexpr double kRSlope = 0.45;
 
 // Everything a scan kernel needs, passed by value.
 struct ScanArgs {
-    // Device tables, struct-of-arrays, FP64:
-    //   rad: r[n_r], sqrt_r[n_r], w[n_r]   (y nodes in log(1+y) GL, dy weights)
-    //   ang: (z, w) pairs, n_a of them     (GC-II nodes, normalised weights)
-    //   arc: xi[n_arc], w[n_arc]           (GL on [-1, 1])
+    // Device tables:
+    //   rad: r[n_r], sqrt_r[n_r], w[n_r]   (y nodes of GL in log(1+y), dy weights), FP64
+    //   ang: (z^2, 2w) for the n_a/2 symmetric pairs of the GC-II rule, FP64
+    //   arc: xi[n_arc], w[n_arc]           (GL on [-1, 1]), FP64
+    //   ang32: the pair table rounded to FP32
     const double *rad;
     const double *ang;
     const double *arc;
-    // FP32 angular table for the mixed-precision kernel: (z^2, 2w) for the
-    // n_a/2 symmetric node pairs, then the middle weight (odd n_a) or 0.
     const float *ang32;
     int n_r, n_a, n_arc;
+    double wmid;  // weight of the middle node z = 0 (odd n_a), else 0
 
     double m1_re, m1_im, m2_re, m2_im;  // m1^2, m2^2
     double lam2, lam;                    // Lambda^2, Lambda

@@ -191,46 +191,128 @@ __device__ __forceinline__ void node_coeffs(const ScanArgs &a, const PointCtx &P
 
 __device__ __forceinline__ double rcp64(double q)
 {
-#if defined(GF_RCP_IEEE)
-    return 1.0 / q;
-#else
-    // hardware reciprocal estimate + one Newton-Raphson step
+    // hardware reciprocal estimate (24 bits on gfx950) + one Newton-Raphson step
     double r = __builtin_amdgcn_rcp(q);
     return fma(fma(-q, r, 1.0), r, r);
-#endif
 }
 
-// sum_j w_j / (U - V z_j) over the GC-II table (z, w pairs), FP64.
-__device__ __forceinline__ cd angular_sum64(const double *__restrict__ ang, int n, cd U, cd V)
+// Angular sum A = sum_j w_j / (U - V z_j) over the GC-II rule.  The rule is
+// symmetric (z_{n+1-j} = -z_j, equal weights), so each node pair is folded:
+//   w/(U - V z) + w/(U + V z) = 2 w U / (U^2 - V^2 z^2),
+// one complex denominator per two integrand evaluations; the middle node of an
+// odd rule (z = 0) adds w/U.  Two denominators share one reciprocal
+// (1/q0 = q1/(q0 q1)).  Table: (z^2, 2w) per pair, FP64.
+__device__ __forceinline__ cd angular_sum64(const double *__restrict__ tab, int npair, double wmid,
+                                            cd U, cd V)
 {
+    const cd U2 = cmul(U, U);
+    const cd V2 = cmul(V, V);
     double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
-    int j = 0;
+    int p = 0;
 #pragma unroll 2
-    for (; j + 2 <= n; j += 2) {
-        double z0 = ang[2 * j], w0 = ang[2 * j + 1];
-        double z1 = ang[2 * j + 2], w1 = ang[2 * j + 3];
-        double dr0 = fma(-V.r, z0, U.r), di0 = fma(-V.i, z0, U.i);
-        double dr1 = fma(-V.r, z1, U.r), di1 = fma(-V.i, z1, U.i);
-        double t0 = w0 * rcp64(fma(dr0, dr0, di0 * di0));
-        double t1 = w1 * rcp64(fma(dr1, dr1, di1 * di1));
+    for (; p + 2 <= npair; p += 2) {
+        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        const double zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
+        const double dr0 = fma(-V2.r, zz0, U2.r), di0 = fma(-V2.i, zz0, U2.i);
+        const double dr1 = fma(-V2.r, zz1, U2.r), di1 = fma(-V2.i, zz1, U2.i);
+        const double q0 = fma(dr0, dr0, di0 * di0);
+        const double q1 = fma(dr1, dr1, di1 * di1);
+        const double inv = rcp64(q0 * q1);
+        const double t0 = ww0 * (q1 * inv);
+        const double t1 = ww1 * (q0 * inv);
         ar0 = fma(t0, dr0, ar0);
         ai0 = fma(t0, di0, ai0);
         ar1 = fma(t1, dr1, ar1);
         ai1 = fma(t1, di1, ai1);
     }
-    if (j < n) {
-        double z0 = ang[2 * j], w0 = ang[2 * j + 1];
-        double dr0 = fma(-V.r, z0, U.r), di0 = fma(-V.i, z0, U.i);
-        double t0 = w0 * rcp64(fma(dr0, dr0, di0 * di0));
+    if (p < npair) {
+        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        const double dr0 = fma(-V2.r, zz0, U2.r), di0 = fma(-V2.i, zz0, U2.i);
+        const double t0 = ww0 * rcp64(fma(dr0, dr0, di0 * di0));
         ar0 = fma(t0, dr0, ar0);
         ai0 = fma(t0, di0, ai0);
     }
-    // w / D = w conj(D) / |D|^2
-    return mk(ar0 + ar1, -(ai0 + ai1));
+    // sum 2w / D = sum 2w conj(D) / |D|^2, then times U
+    cd A = cmul(U, mk(ar0 + ar1, -(ai0 + ai1)));
+    if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    return A;
 }
 
-template <int L>
-__global__ void __launch_bounds__(256) scan_fp64_kernel(ScanArgs a)
+// Knuth's two-sum: s + e == a + b exactly (round-to-nearest, no contraction).
+__device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
+{
+    const float s = hi + b;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (b - bb);
+    hi = s;
+    lo += e;
+}
+
+// FP32 angular sum with compensated accumulation.  U^2 and V^2 are formed in
+// FP64 and scaled by an exact power of two 2^-e (e = exponent of their largest
+// component) before rounding to FP32, so every FP32 denominator is O(1) and the
+// shared-reciprocal product q0 q1 stays in range.  Terms are summed in FP32
+// blocks of kBlock pairs; block sums enter a (hi, lo) two-sum accumulator; the
+// node's sum leaves in FP64 as U 2^-e (hi + lo).
+constexpr int kBlock = 16;
+
+__device__ __forceinline__ cd angular_sum32c(const float *__restrict__ tab, int npair, double wmid,
+                                             cd U, cd V)
+{
+    const cd U2 = cmul(U, U);
+    const cd V2 = cmul(V, V);
+    const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
+    int e = 0;
+    frexp(big, &e);
+    const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
+    const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
+    float hr = 0.0f, lr = 0.0f, hi = 0.0f, li = 0.0f;
+    int p = 0;
+    while (p < npair) {
+        const int pe = min(p + kBlock, npair);
+        float br0 = 0.0f, bi0 = 0.0f, br1 = 0.0f, bi1 = 0.0f;
+        for (; p + 2 <= pe; p += 2) {
+            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+            const float zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
+            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
+            const float dr1 = fmaf(-v2r, zz1, u2r), di1 = fmaf(-v2i, zz1, u2i);
+            const float q0 = fmaf(dr0, dr0, di0 * di0);
+            const float q1 = fmaf(dr1, dr1, di1 * di1);
+            const float inv = __builtin_amdgcn_rcpf(q0 * q1);
+            const float t0 = ww0 * (q1 * inv);
+            const float t1 = ww1 * (q0 * inv);
+            br0 = fmaf(t0, dr0, br0);
+            bi0 = fmaf(t0, di0, bi0);
+            br1 = fmaf(t1, dr1, br1);
+            bi1 = fmaf(t1, di1, bi1);
+        }
+        if (p < pe) {
+            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
+            const float t0 = ww0 * __builtin_amdgcn_rcpf(fmaf(dr0, dr0, di0 * di0));
+            br0 = fmaf(t0, dr0, br0);
+            bi0 = fmaf(t0, di0, bi0);
+            ++p;
+        }
+        two_sum(hr, lr, br0 + br1);
+        two_sum(hi, li, bi0 + bi1);
+    }
+    const double sr = ldexp((double)hr + (double)lr, -e);
+    const double si = ldexp((double)hi + (double)li, -e);
+    cd A = cmul(U, mk(sr, -si));
+    if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    return A;
+}
+
+template <int PREC>
+__device__ __forceinline__ cd angular_sum(const ScanArgs &a, cd U, cd V)
+{
+    if (PREC == 0) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V);
+    return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V);
+}
+
+template <int PREC, int L>
+__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
 {
     constexpr int P = 64 / L;
     constexpr int TW = P < 8 ? P : 8;
@@ -264,7 +346,7 @@ __global__ void __launch_bounds__(256) scan_fp64_kernel(ScanArgs a)
     for (int k = s; k < pc.nodes; k += L) {
         cd U, V, w;
         node_coeffs(a, pc, k, U, V, w);
-        cd A = angular_sum64(a.ang, a.n_a, U, V);
+        cd A = angular_sum<PREC>(a, U, V);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -299,7 +381,7 @@ __global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double 
     for (int k = lane; k < pc.nodes; k += 64) {
         cd U, V, w;
         node_coeffs(a, pc, k, U, V, w);
-        cd A = angular_sum64(a.ang, a.n_a, U, V);
+        cd A = angular_sum<0>(a, U, V);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -320,7 +402,9 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
     const int blocks = (a.n_tiles + 3) / 4;
     if (precision == 0) {
-        hipLaunchKernelGGL(scan_fp64_kernel<L>, dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((scan_kernel<0, L>), dim3(blocks), dim3(256), 0, s, a);
+    } else if (precision == 1) {
+        hipLaunchKernelGGL((scan_kernel<1, L>), dim3(blocks), dim3(256), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }

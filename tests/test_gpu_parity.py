@@ -228,3 +228,80 @@ def test_large_node_counts():
     g, c = _gpu_scan(p, q, grid)
     go, co, cond = oracle.scan(p, q, grid, want_cond=True)
     _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
+
+
+# ---------------------------------------------------------------- FP32C (FP32 bulk)
+
+def _fp32c_report(g32, g_ref, x, cut_threshold):
+    """Error statistics of an FP32C scan against reference values, separately
+    within 0.05 of the cut x < -(m1 + m2)^2 and elsewhere."""
+    band = (np.abs(x.imag) < 0.05) & (x.real < -cut_threshold)
+    out = {}
+    for name, m in (("band", band), ("elsewhere", ~band)):
+        if not m.any():
+            continue
+        err = np.abs(g32[m] - g_ref[m])
+        rel = err / np.abs(g_ref[m])
+        out[name] = {"n": int(m.sum()), "max_abs": float(err.max()), "mean_abs": float(err.mean()),
+                     "max_rel": float(rel.max()), "mean_rel": float(rel.mean())}
+    return out
+
+
+def _fp32c_bar(g32, g_or, cond):
+    """|G32 - G| <= 1e-6 max(|G|, 1) where kappa <= 100 (the stated FP32-bulk
+    target, mixed absolute/relative since G(mu^2) = 0); everywhere
+    |G32 - G| <= 16 eps32 kappa |G| (eps32 = 2^-24: FP32 inputs of every
+    denominator and a 1.5-ulp reciprocal, first-order in kappa)."""
+    err = np.abs(g32 - g_or)
+    mag = np.abs(g_or)
+    good = cond <= 100
+    assert np.all(err[good] <= 1e-6 * np.maximum(mag[good], 1.0)), np.max(
+        err[good] / np.maximum(mag[good], 1.0))
+    assert np.all(err <= np.maximum(16 * 2.0 ** -24 * cond * mag, 1e-6 * np.maximum(mag, 1.0)))
+
+
+def test_fp32c_config2_sampled():
+    """Mixed precision on the 1024^2 box (512 x 256 nodes): sampled points
+    against the FP64 oracle; errors reported inside and outside the cut band."""
+    p, grid, q = CONFIGS["c2_fp32c_1024sq"]
+    g, c = _gpu_scan(p, q, grid)
+    assert np.all(np.isfinite(g))
+    idx = sample_points(grid, 400, seed=3)
+    x = oracle.grid_points_at(grid, idx)
+    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
+    assert np.array_equal(c[idx], co) or (c[idx] != co).sum() <= 1
+    keep = c[idx] == co
+    _fp32c_bar(g[idx][keep], go[keep], cond[keep])
+    print("fp32c c2", _fp32c_report(g[idx][keep], go[keep], x[keep], 4.0))
+
+
+def test_fp32c_full_grid_against_fp64_gpu_and_oracle():
+    """FP32C against the parity-checked FP64 path at every point of a 256^2 box
+    (config c2's window and node counts), and against the oracle on a sample."""
+    p = Params(1.0, 1.0, 1.0, 1e6, 1.0)
+    grid = Grid(256, 256, -16.0, 8.0, -8.0, 8.0)
+    q32 = Quadrature(512, 256, 16, gf.FP32C)
+    q64 = Quadrature(512, 256, 16, gf.FP64)
+    g32, c32 = _gpu_scan(p, q32, grid)
+    g64, c64 = _gpu_scan(p, q64, grid)
+    assert np.array_equal(c32, c64)
+    x = oracle.grid_points(grid)
+    rep = _fp32c_report(g32, g64, x, 4.0)
+    print("fp32c vs fp64 (all points)", rep)
+    idx = sample_points(grid, 200, seed=5)
+    go, co, cond = oracle.eval_points(p, q64, x[idx], want_cond=True)
+    _fp32c_bar(g32[idx], go, cond)
+
+
+def test_fp32c_ragged_and_odd_rules():
+    """FP32C on a ragged grid with odd angular order (middle node) and several
+    lane splits; complex conjugate masses (all four classes)."""
+    p = Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0)
+    q = Quadrature(96, 49, 8, gf.FP32C)
+    grid = Grid(29, 19, -12.0, 6.0, -6.0, 6.0)
+    go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+    for lanes in (1, 4, 64):
+        g, c = _gpu_scan(p, q, grid, lanes=lanes)
+        keep = c == co
+        assert (~keep).sum() <= 1
+        _fp32c_bar(g[keep], go[keep], cond[keep])
