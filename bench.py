@@ -98,6 +98,44 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
             "kernel": f"scan_kernel<{quad.precision},{used_lanes}>"}
 
 
+def serve_trace(gf, n_requests, rate, budget_bytes, seed=0):
+    """Replays a seeded Poisson trace of scan requests in real time against the
+    continuous-batching server; results are released as they complete."""
+    from paper_1205_0752_amd.workloads import serving_trace
+    reqs = serving_trace(n_requests, rate, seed=seed)
+    lag = 0.0
+    with gf.Server(budget_bytes=budget_bytes, max_inflight=4096) as srv:
+        t0 = time.perf_counter()
+        outstanding = 0
+        i = 0
+        while i < len(reqs) or outstanding:
+            now = time.perf_counter() - t0
+            if i < len(reqs) and reqs[i].arrival_s <= now:
+                srv.submit(reqs[i].params, reqs[i].grid, reqs[i].quad)
+                lag = max(lag, now - reqs[i].arrival_s)
+                i += 1
+                outstanding += 1
+                continue
+            wait_ms = (reqs[i].arrival_s - now) * 1e3 if i < len(reqs) else 1000.0
+            t = srv.wait_any(max(wait_ms, 0.0))
+            if t is not None:
+                srv.release(t)
+                outstanding -= 1
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    span = st["first_submit_to_last_done_s"]
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "seed": seed,
+            "completed": st["completed"], "wall_s": wall,
+            "throughput_req_per_s": st["completed"] / span,
+            "points_per_s": st["points_done"] / span,
+            "nominal_evals_per_s": st["nominal_evals_done"] / span,
+            "latency_ms": {"mean": st["latency_mean_ms"], "p50": st["latency_p50_ms"],
+                           "p90": st["latency_p90_ms"], "p99": st["latency_p99_ms"],
+                           "max": st["latency_max_ms"]},
+            "max_submit_lag_ms": lag * 1e3, "batches": st["batches"],
+            "device_budget_bytes": st["bytes_budget"], "peak_bytes": st["bytes_peak"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +146,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32c", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-rate", type=float, default=400.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-budget", type=int, default=1 << 30, help="device bytes")
     ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM traffic counters) and exit")
@@ -174,6 +216,9 @@ def main() -> int:
                            "ms_per_step": t2["ms"], "tflops": t2["tflops"],
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
                            "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS}
+    if not args.skip_serving and args.config == "c1_fp64_1024sq":
+        result["serving"] = serve_trace(gf, args.serve_requests, args.serve_rate,
+                                        args.serve_budget)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(params, quad, grid, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -156,6 +156,80 @@ void gf_cache_clear(void);
 int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im);
 int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
 
+/* ---- serving: continuous batching of scan requests ----------------------
+ *
+ * A server owns one HIP stream, a device-memory arena of `device_budget_bytes`
+ * and a scheduler thread.  Submitted requests wait in FIFO order until their
+ * output (16 bytes per point) and any node tables not yet resident fit in the
+ * arena and a slot is free; admitted requests run concurrently: each scheduler
+ * iteration packs wave tiles of every running request (a fair share of
+ * `batch_evals` integrand evaluations each, oldest first) into persistent
+ * kernel launches, and keeps two such batches in flight.  A request completes
+ * when its last tile has run; its result stays in the arena until
+ * gf_server_release.  Every point is computed by the same device code, lane
+ * split and tables as gf_scan_plan with automatic lanes, so a served result is
+ * bitwise identical to a standalone scan of the same request.  Node tables are
+ * cached by (n_radial, lambda2), n_angular and n_arc and shared by requests.
+ *
+ * Thread safety: all gf_server_* calls may be made from any thread. */
+typedef struct gf_server gf_server_t;
+
+typedef struct {
+    size_t device_budget_bytes;  /* arena for outputs + node tables (>= 1 MiB) */
+    int32_t max_inflight;        /* admitted requests at once, 1..65536 */
+    double batch_evals;          /* target integrand evaluations per batch (0 = 2e10) */
+} gf_server_config;
+
+#define GF_REQ_QUEUED 0
+#define GF_REQ_RUNNING 1
+#define GF_REQ_DONE 2
+
+typedef struct {
+    int64_t submitted, completed, released, rejected;
+    int64_t queued, running;
+    int64_t bytes_in_use, bytes_peak, bytes_budget;
+    int64_t batches, work_items, points_done;
+    double nominal_evals_done;  /* points x (n_radial + n_arc) x n_angular */
+    double latency_mean_ms, latency_p50_ms, latency_p90_ms, latency_p99_ms, latency_max_ms;
+    double first_submit_to_last_done_s;
+} gf_server_stats;
+
+/* Creates a server on the current device.  Errors: GF_EINVAL, GF_ENOMEM,
+ * GF_EDEVICE. */
+int gf_server_create(const gf_server_config *cfg, gf_server_t **out);
+
+/* Queues a scan request; *ticket identifies it.  Validation as gf_plan and
+ * gf_scan_plan.  GF_EBUDGET if its output alone exceeds the arena. */
+int gf_server_submit(gf_server_t *srv, const gf_params *params, const gf_grid *grid,
+                     const gf_quadrature *quad, uint64_t *ticket);
+
+/* *state = GF_REQ_QUEUED / RUNNING / DONE.  GF_ENOTFOUND for unknown tickets. */
+int gf_server_poll(gf_server_t *srv, uint64_t ticket, int *state);
+
+/* Blocks until the request is done or timeout_ms passes (< 0: no limit).
+ * Returns 1 if done, 0 on timeout, < 0 on error. */
+int gf_server_wait(gf_server_t *srv, uint64_t ticket, double timeout_ms);
+
+/* Pops the oldest completed-but-not-yet-reported ticket, waiting up to
+ * timeout_ms.  Returns 1 and sets *ticket, or 0 on timeout. */
+int gf_server_wait_any(gf_server_t *srv, double timeout_ms, uint64_t *ticket);
+
+/* Device pointer to a done request's complex128 result [n_im][n_re] (valid
+ * until gf_server_release) and its point count. */
+int gf_server_result(gf_server_t *srv, uint64_t ticket, const void **dev_ptr, int64_t *n_points);
+
+/* Copies a done request's result to host memory (n_points complex128). */
+int gf_server_copy_result(gf_server_t *srv, uint64_t ticket, void *host_dst);
+
+/* Frees a done request's output and slot (its memory returns to the arena). */
+int gf_server_release(gf_server_t *srv, uint64_t ticket);
+
+int gf_server_stats_get(gf_server_t *srv, gf_server_stats *stats);
+
+/* Stops the scheduler after in-flight batches finish and frees everything.
+ * Requests not yet done are dropped. */
+int gf_server_destroy(gf_server_t *srv);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *gf_last_error(void);
 

@@ -9,10 +9,10 @@ The library is loaded on first use; importing this package does not touch the
 GPU.
 """
 from ._binding import (CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
-                       GFError, LIB_PATH, Plan, cache_clear, empty_result, load, scan, scan_plan,
+                       REQ_DONE, REQ_QUEUED, REQ_RUNNING, GFError, LIB_PATH, Plan, Server, cache_clear, empty_result, load, scan, scan_plan,
                        version)
 from .workloads import CONFIGS, FP32C, FP64, Grid, Params, Quadrature
 
-__all__ = ["Params", "Grid", "Quadrature", "Plan", "scan", "scan_plan", "cache_clear",
+__all__ = ["Params", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_plan", "cache_clear",
            "empty_result", "version", "load", "GFError", "EXPORTS", "LIB_PATH", "FP64", "FP32C",
-           "CONFIGS", "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]
+           "CONFIGS", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]

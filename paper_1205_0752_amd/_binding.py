@@ -27,7 +27,12 @@ CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
-           "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version")
+           "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
+           "gf_server_create", "gf_server_submit", "gf_server_poll", "gf_server_wait",
+           "gf_server_wait_any", "gf_server_result", "gf_server_copy_result",
+           "gf_server_release", "gf_server_stats_get", "gf_server_destroy")
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 
 class GFError(RuntimeError):
@@ -52,6 +57,20 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n_re", ctypes.c_int32), ("n_im", ctypes.c_int32),
                 ("re_lo", ctypes.c_double), ("re_hi", ctypes.c_double),
                 ("im_lo", ctypes.c_double), ("im_hi", ctypes.c_double)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int32),
+                ("batch_evals", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "released", "rejected", "queued", "running", "bytes_in_use",
+        "bytes_peak", "bytes_budget", "batches", "work_items", "points_done")] + [
+        (n, ctypes.c_double) for n in (
+            "nominal_evals_done", "latency_mean_ms", "latency_p50_ms", "latency_p90_ms",
+            "latency_p99_ms", "latency_max_ms", "first_submit_to_last_done_s")]
 
 
 _lib = None
@@ -81,6 +100,19 @@ def load():
         lib.gf_plan_auto_lanes.argtypes = [vp, ctypes.POINTER(_Grid)]
         lib.gf_last_error.restype = ctypes.c_char_p
         lib.gf_version.restype = ctypes.c_char_p
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.gf_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
+        lib.gf_server_submit.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
+                                         ctypes.POINTER(_Quad), u64p]
+        lib.gf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        lib.gf_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
+        lib.gf_server_wait_any.argtypes = [vp, ctypes.c_double, u64p]
+        lib.gf_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        lib.gf_server_copy_result.argtypes = [vp, ctypes.c_uint64, vp]
+        lib.gf_server_release.argtypes = [vp, ctypes.c_uint64]
+        lib.gf_server_stats_get.argtypes = [vp, ctypes.POINTER(_ServerStats)]
+        lib.gf_server_destroy.argtypes = [vp]
         _lib = lib
     return _lib
 
@@ -189,6 +221,81 @@ def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
     return out
 
 
+class Server:
+    """Continuous-batching scan server (gf_server_*) on the current device."""
+
+    def __init__(self, budget_bytes: int = 1 << 30, max_inflight: int = 1024,
+                 batch_evals: float = 0.0):
+        h = ctypes.c_void_p()
+        cfg = _ServerConfig(int(budget_bytes), int(max_inflight), float(batch_evals))
+        _check(load().gf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("server is closed")
+        return self._h
+
+    def submit(self, params: Params, grid: Grid, quad: Quadrature) -> int:
+        t = ctypes.c_uint64()
+        _check(load().gf_server_submit(self.handle, ctypes.byref(c_params(params)),
+                                       ctypes.byref(c_grid(grid)), ctypes.byref(c_quad(quad)),
+                                       ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int()
+        _check(load().gf_server_poll(self.handle, ticket, ctypes.byref(st)))
+        return st.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> bool:
+        return _check(load().gf_server_wait(self.handle, ticket, float(timeout_ms))) == 1
+
+    def wait_any(self, timeout_ms: float = -1.0):
+        """Next completed ticket, or None on timeout."""
+        t = ctypes.c_uint64()
+        r = _check(load().gf_server_wait_any(self.handle, float(timeout_ms), ctypes.byref(t)))
+        return t.value if r == 1 else None
+
+    def result(self, ticket: int):
+        """The result as a numpy complex128 array [n_im, n_re] (copied to host)."""
+        import numpy as np
+        p = ctypes.c_void_p()
+        n = ctypes.c_int64()
+        _check(load().gf_server_result(self.handle, ticket, ctypes.byref(p), ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.complex128)
+        if n.value:
+            _check(load().gf_server_copy_result(self.handle, ticket,
+                                                ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def release(self, ticket: int):
+        _check(load().gf_server_release(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(load().gf_server_stats_get(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            load().gf_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def cache_clear():
     load().gf_cache_clear()
 
@@ -197,5 +304,6 @@ def version() -> str:
     return load().gf_version().decode()
 
 
-__all__ = ["Plan", "scan", "scan_plan", "cache_clear", "version", "load", "GFError", "EXPORTS",
+__all__ = ["Plan", "Server", "scan", "scan_plan", "cache_clear", "version", "load", "GFError",
+           "EXPORTS",
            "FP64", "FP32C", "LIB_PATH", "empty_result"]

@@ -6,12 +6,16 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "_libgf.so")
-SOURCES = [os.path.join(HERE, "csrc", "gf_host.cpp"), os.path.join(HERE, "csrc", "gf_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name) for name in ("gf_host.cpp", "gf_server.cpp", "gf_kernels.hip")]
 ARCH = "gfx950"
 
-# Device code is built without packed FP32 instructions: the compiler would
-# otherwise form v_pk_* FP32 operations by itself.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Device code is built without packed FP32 instructions (the compiler would
+# otherwise form them by itself), and with multiply-add contraction decided per
+# source expression rather than by the backend: a point's arithmetic is then
+# the same in every kernel that computes it (one-grid scan, serving launch),
+# so results are reproducible bit for bit across them.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-ffp-contract=on"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:

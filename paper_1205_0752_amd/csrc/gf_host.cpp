@@ -3,6 +3,7 @@
 // phase), plan objects, the plan cache and kernel launches.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -20,33 +21,17 @@ struct gf_plan {
     int device = -1;
     gf_params params{};
     gf_quadrature quad{};
-    void *d_mem = nullptr;  // one allocation holding every table
-    gf::ScanArgs base{};    // kernel arguments minus the grid and outputs
+    void *d_mem = nullptr;       // one allocation holding every table
+    gf::ScanArgs base{};         // kernel arguments minus the grid and outputs
+    double jmu[2] = {0.0, 0.0};  // host copy of the subtraction sum
 };
 
-namespace {
+namespace gf {
 
+namespace {
 thread_local std::string g_error;
 
-int fail(int code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_error = buf;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char *what)
-{
-    return fail(GF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
 bool finite(double v) { return std::isfinite(v); }
-
-// ---------------------------------------------------------------- quadrature
 
 // Legendre P_n(x) and P_n'(x) by the three-term recurrence.
 void legendre(int n, double x, double *pn, double *dpn)
@@ -65,6 +50,42 @@ void legendre(int n, double x, double *pn, double *dpn)
     *pn = pk;
     *dpn = n * (pkm1 - x * pk) / (1.0 - x * x);
 }
+
+double bad_ray(double re, double im)
+{
+    // arg(-m^2); a real positive m^2 gives the negative real axis, angle +pi
+    return im == 0.0 ? M_PI : std::atan2(-im, -re);
+}
+
+int tiles_for(const gf_grid &g, int lanes, int *tiles_a, long long *n_tiles)
+{
+    int tw, th;
+    tile_shape(lanes, &tw, &th);
+    long long ta = (g.n_re + tw - 1) / tw;
+    long long tb = (g.n_im + th - 1) / th;
+    *tiles_a = (int)ta;
+    *n_tiles = ta * tb;
+    return GF_OK;
+}
+}  // namespace
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const char *last_error() { return g_error.c_str(); }
 
 // n-point Gauss-Legendre rule on [-1, 1], ascending nodes.  The positive
 // roots are found by Newton's method from Tricomi's asymptotic estimate and
@@ -96,34 +117,80 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     if (n % 2 == 1) x[n / 2] = 0.0;  // exact centre node
 }
 
-// ---------------------------------------------------------------- geometry
-
-struct Geometry {
-    double beta1, beta2, lo, hi, vstar;
-    int mirror_ok;
-};
-
-double bad_ray(double re, double im)
+void radial_table(int nr, double lambda2, std::vector<double> &rad)
 {
-    // arg(-m^2); a real positive m^2 gives the negative real axis, angle +pi
-    return im == 0.0 ? M_PI : std::atan2(-im, -re);
+    // GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt
+    std::vector<double> gx, gw;
+    gauss_legendre(nr, gx, gw);
+    const double T = std::log1p(lambda2);
+    rad.assign(3 * (size_t)nr, 0.0);
+    for (int i = 0; i < nr; ++i) {
+        double t = 0.5 * T * (gx[i] + 1.0);
+        double y = std::expm1(t);
+        rad[i] = y;
+        rad[nr + i] = std::sqrt(y);
+        rad[2 * nr + i] = 0.5 * T * gw[i] * (1.0 + y);
+    }
 }
 
-Geometry make_geometry(const gf_params &p)
+void angular_tables(int na, std::vector<double> &ang, std::vector<float> &ang32, double *wmid)
 {
-    Geometry g;
-    g.beta1 = bad_ray(p.m1sq_re, p.m1sq_im);
-    g.beta2 = bad_ray(p.m2sq_re, p.m2sq_im);
-    g.hi = M_PI;
-    g.lo = -M_PI;
-    for (double b : {g.beta1, g.beta2}) {
-        if (b > 0.0 && b < g.hi) g.hi = b;
-        if (b <= 0.0 && b > g.lo) g.lo = b;
+    // Gauss-Chebyshev of the second kind, weights summing to 1, stored folded
+    // over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j), z_j = cos(j pi/(n+1)),
+    // j = 1..n/2; the middle node of an odd rule is z = 0 with weight 2/(n+1)
+    const int npair = na / 2;
+    ang.assign(2 * (size_t)std::max(npair, 1), 0.0);
+    ang32.assign(2 * (size_t)std::max(npair, 1), 0.0f);
+    for (int j = 1; j <= npair; ++j) {
+        double th = j * M_PI / (na + 1);
+        double s = std::sin(th), c = std::cos(th);
+        ang[2 * (j - 1)] = c * c;
+        ang[2 * (j - 1) + 1] = 4.0 * s * s / (na + 1);
+        ang32[2 * (j - 1)] = (float)ang[2 * (j - 1)];
+        ang32[2 * (j - 1) + 1] = (float)ang[2 * (j - 1) + 1];
     }
-    g.vstar = std::real(std::sqrt(std::complex<double>(p.m1sq_re, p.m1sq_im)));
-    g.mirror_ok = (p.m1sq_im == 0.0 && p.m2sq_im == 0.0) ||
+    *wmid = (na % 2 == 1) ? 2.0 / (na + 1) : 0.0;
+}
+
+void arc_table(int nc, std::vector<double> &arc)
+{
+    std::vector<double> ax, aw;
+    if (nc > 0) gauss_legendre(nc, ax, aw);
+    arc.assign(2 * (size_t)std::max(nc, 1), 0.0);
+    for (int k = 0; k < nc; ++k) {
+        arc[k] = ax[k];
+        arc[nc + k] = aw[k];
+    }
+}
+
+void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
+{
+    a.n_r = q.n_radial;
+    a.n_a = q.n_angular;
+    a.n_arc = q.n_arc;
+    a.m1_re = p.m1sq_re;
+    a.m1_im = p.m1sq_im;
+    a.m2_re = p.m2sq_re;
+    a.m2_im = p.m2sq_im;
+    a.lam2 = p.lambda2;
+    a.lam = std::sqrt(p.lambda2);
+    const std::complex<double> sy0 = std::sqrt(std::complex<double>(-p.m2sq_re, -p.m2sq_im));
+    a.sy0_re = sy0.real();
+    a.sy0_im = sy0.imag();
+    a.scale = p.scale;
+    // bad rays arg(-m1^2), arg(-m2^2) and the open sector (lo, hi) around the
+    // positive real axis that the ray can sweep without crossing one
+    a.beta1 = bad_ray(p.m1sq_re, p.m1sq_im);
+    a.beta2 = bad_ray(p.m2sq_re, p.m2sq_im);
+    a.hi = M_PI;
+    a.lo = -M_PI;
+    for (double b : {a.beta1, a.beta2}) {
+        if (b > 0.0 && b < a.hi) a.hi = b;
+        if (b <= 0.0 && b > a.lo) a.lo = b;
+    }
+    a.vstar = std::real(std::sqrt(std::complex<double>(p.m1sq_re, p.m1sq_im)));
+    a.mirror_ok = (p.m1sq_im == 0.0 && p.m2sq_im == 0.0) ||
                   (p.m1sq_re == p.m2sq_re && p.m1sq_im == -p.m2sq_im);
-    return g;
 }
 
 int validate_params(const gf_params *p, const gf_quadrature *q)
@@ -142,9 +209,9 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     for (double v : vals)
         if (!finite(v)) return fail(GF_EINVAL, "parameters must be finite");
     if (!(p->lambda2 > 0.0)) return fail(GF_EINVAL, "lambda2 must be > 0");
+    if (!(p->lambda2 <= 1e30)) return fail(GF_EINVAL, "lambda2 must be <= 1e30");
     if (!(p->mu2 >= 0.0)) return fail(GF_EINVAL, "mu2 must be >= 0");
     if (!(p->mu2 < p->lambda2)) return fail(GF_EINVAL, "mu2 must be below lambda2");
-    if (!(p->lambda2 <= 1e30)) return fail(GF_EINVAL, "lambda2 must be <= 1e30");
     if (p->m1sq_im == 0.0 && p->m1sq_re <= 0.0)
         return fail(GF_EINVAL, "m1^2 must not lie on the non-positive real axis");
     if (p->m2sq_im == 0.0 && p->m2sq_re <= 0.0)
@@ -152,29 +219,31 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     return GF_OK;
 }
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-
-// ---------------------------------------------------------------- plan cache
-
-std::mutex g_cache_mu;
-std::map<std::string, gf_plan_t *> g_cache;
-
-std::string cache_key(const gf_params *p, const gf_quadrature *q, int dev)
+int validate_grid(const gf_params &p, const gf_grid *g)
 {
-    std::string k(reinterpret_cast<const char *>(p), sizeof(*p));
-    k.append(reinterpret_cast<const char *>(q), sizeof(*q));
-    k.append(reinterpret_cast<const char *>(&dev), sizeof(dev));
-    return k;
-}
-
-int tiles_for(const gf_grid &g, int lanes, int *tiles_a, long long *n_tiles)
-{
-    int tw, th;
-    gf::tile_shape(lanes, &tw, &th);
-    long long ta = (g.n_re + tw - 1) / tw;
-    long long tb = (g.n_im + th - 1) / th;
-    *tiles_a = (int)ta;
-    *n_tiles = ta * tb;
+    if (!g) return fail(GF_EINVAL, "grid must not be NULL");
+    if (g->n_re < 0 || g->n_im < 0) return fail(GF_EINVAL, "grid sizes must be >= 0");
+    if ((long long)g->n_re * (long long)g->n_im > (1LL << 31))
+        return fail(GF_EINVAL, "grid has more than 2^31 points");
+    const double v[] = {g->re_lo, g->re_hi, g->im_lo, g->im_hi};
+    for (double x : v)
+        if (!finite(x)) return fail(GF_EINVAL, "grid bounds must be finite");
+    if (!(g->re_lo < g->re_hi) || !(g->im_lo < g->im_hi))
+        return fail(GF_EINVAL, "grid bounds must satisfy lo < hi");
+    // the closing arc |y| = Lambda^2 must clear the angular cut, which reaches
+    // out to |y| = (sqrt|x| + sqrt(|x| + |m1^2|))^2
+    const double m1abs = std::hypot(p.m1sq_re, p.m1sq_im);
+    const double cr[2] = {g->re_lo, g->re_hi}, ci[2] = {g->im_lo, g->im_hi};
+    for (double a : cr)
+        for (double b : ci) {
+            double ax = std::hypot(a, b);
+            double reach = std::sqrt(ax) + std::sqrt(ax + m1abs);
+            if (!(reach * reach < p.lambda2))
+                return fail(GF_EINVAL,
+                            "lambda2 = %g is too small for the grid box: the closing arc "
+                            "needs lambda2 > %g",
+                            p.lambda2, reach * reach);
+        }
     return GF_OK;
 }
 
@@ -189,31 +258,18 @@ int auto_lanes(const gf_grid &g)
     return 64;
 }
 
-int validate_grid(const gf_plan_t *plan, const gf_grid *g)
+int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
 {
-    if (!g) return fail(GF_EINVAL, "grid must not be NULL");
-    if (g->n_re < 0 || g->n_im < 0) return fail(GF_EINVAL, "grid sizes must be >= 0");
-    if ((long long)g->n_re * (long long)g->n_im > (1LL << 31))
-        return fail(GF_EINVAL, "grid has more than 2^31 points");
-    const double v[] = {g->re_lo, g->re_hi, g->im_lo, g->im_hi};
-    for (double x : v)
-        if (!finite(x)) return fail(GF_EINVAL, "grid bounds must be finite");
-    if (!(g->re_lo < g->re_hi) || !(g->im_lo < g->im_hi))
-        return fail(GF_EINVAL, "grid bounds must satisfy lo < hi");
-    // the closing arc |y| = Lambda^2 must clear the angular cut, which reaches
-    // out to |y| = (sqrt|x| + sqrt(|x| + |m1^2|))^2
-    const double m1abs = std::hypot(plan->params.m1sq_re, plan->params.m1sq_im);
-    const double cr[2] = {g->re_lo, g->re_hi}, ci[2] = {g->im_lo, g->im_hi};
-    for (double a : cr)
-        for (double b : ci) {
-            double ax = std::hypot(a, b);
-            double reach = std::sqrt(ax) + std::sqrt(ax + m1abs);
-            if (!(reach * reach < plan->params.lambda2))
-                return fail(GF_EINVAL,
-                            "lambda2 = %g is too small for the grid box: the closing arc "
-                            "needs lambda2 > %g",
-                            plan->params.lambda2, reach * reach);
-        }
+    a.n_re = g.n_re;
+    a.n_im = g.n_im;
+    a.re_lo = g.re_lo;
+    a.im_lo = g.im_lo;
+    a.d_re = (g.re_hi - g.re_lo) / (double)g.n_re;
+    a.d_im = (g.im_hi - g.im_lo) / (double)g.n_im;
+    long long nt;
+    tiles_for(g, lanes, &a.tiles_a, &nt);
+    if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
+    a.n_tiles = (int)nt;
     return GF_OK;
 }
 
@@ -224,66 +280,56 @@ int current_device(int *dev)
     return GF_OK;
 }
 
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace gf
+
+namespace {
+
+std::mutex g_cache_mu;
+std::map<std::string, gf_plan_t *> g_cache;
+
+std::string cache_key(const gf_params *p, const gf_quadrature *q, int dev)
+{
+    std::string k(reinterpret_cast<const char *>(p), sizeof(*p));
+    k.append(reinterpret_cast<const char *>(q), sizeof(*q));
+    k.append(reinterpret_cast<const char *>(&dev), sizeof(dev));
+    return k;
+}
+
 }  // namespace
+
+using gf::fail;
+using gf::hip_fail;
 
 extern "C" {
 
-const char *gf_last_error(void) { return g_error.c_str(); }
+const char *gf_last_error(void) { return gf::last_error(); }
 
-const char *gf_version(void) { return "gf 0.1 (gfx950)"; }
+const char *gf_version(void) { return "gf 0.2 (gfx950)"; }
 
 int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
 {
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
     *out = nullptr;
-    int rc = validate_params(params, quad);
+    int rc = gf::validate_params(params, quad);
     if (rc != GF_OK) return rc;
     int dev;
-    if ((rc = current_device(&dev)) != GF_OK) return rc;
+    if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
 
-    const int nr = quad->n_radial, na = quad->n_angular, nc = quad->n_arc;
-    // radial nodes: GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt
-    std::vector<double> gx, gw;
-    gauss_legendre(nr, gx, gw);
-    const double T = std::log1p(params->lambda2);
-    std::vector<double> rad(3 * (size_t)nr);
-    for (int i = 0; i < nr; ++i) {
-        double t = 0.5 * T * (gx[i] + 1.0);
-        double y = std::expm1(t);
-        rad[i] = y;
-        rad[nr + i] = std::sqrt(y);
-        rad[2 * nr + i] = 0.5 * T * gw[i] * (1.0 + y);
-    }
-    // angular nodes: Gauss-Chebyshev of the second kind, weights summing to 1;
-    // stored folded over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j),
-    // z_j = cos(j pi/(n+1)), j = 1..n/2; the middle node of an odd rule is z = 0
-    const int npair = na / 2;
-    std::vector<double> ang(2 * (size_t)std::max(npair, 1), 0.0);
-    std::vector<float> ang32(2 * (size_t)std::max(npair, 1), 0.0f);
-    for (int j = 1; j <= npair; ++j) {
-        double th = j * M_PI / (na + 1);
-        double s = std::sin(th), c = std::cos(th);
-        ang[2 * (j - 1)] = c * c;
-        ang[2 * (j - 1) + 1] = 4.0 * s * s / (na + 1);
-        ang32[2 * (j - 1)] = (float)ang[2 * (j - 1)];
-        ang32[2 * (j - 1) + 1] = (float)ang[2 * (j - 1) + 1];
-    }
-    const double wmid = (na % 2 == 1) ? 2.0 / (na + 1) : 0.0;  // sin^2(pi/2) = 1
-    // arc nodes: GL on [-1, 1]
-    std::vector<double> ax, aw;
-    if (nc > 0) gauss_legendre(nc, ax, aw);
-    std::vector<double> arc(2 * (size_t)std::max(nc, 1), 0.0);
-    for (int k = 0; k < nc; ++k) {
-        arc[k] = ax[k];
-        arc[nc + k] = aw[k];
-    }
+    std::vector<double> rad, ang, arc;
+    std::vector<float> ang32;
+    double wmid = 0.0;
+    gf::radial_table(quad->n_radial, params->lambda2, rad);
+    gf::angular_tables(quad->n_angular, ang, ang32, &wmid);
+    gf::arc_table(quad->n_arc, arc);
 
     const size_t off_rad = 0;
-    const size_t off_ang = off_rad + align256(rad.size() * sizeof(double));
-    const size_t off_arc = off_ang + align256(ang.size() * sizeof(double));
-    const size_t off_jmu = off_arc + align256(arc.size() * sizeof(double));
+    const size_t off_ang = off_rad + gf::align256(rad.size() * sizeof(double));
+    const size_t off_arc = off_ang + gf::align256(ang.size() * sizeof(double));
+    const size_t off_jmu = off_arc + gf::align256(arc.size() * sizeof(double));
     const size_t off_a32 = off_jmu + 256;
-    const size_t total = off_a32 + align256(ang32.size() * sizeof(float));
+    const size_t total = off_a32 + gf::align256(ang32.size() * sizeof(float));
 
     gf_plan_t *plan = new (std::nothrow) gf_plan_t();
     if (!plan) return fail(GF_ENOMEM, "host allocation failed");
@@ -312,36 +358,17 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
         }
     }
 
-    const Geometry geo = make_geometry(*params);
     gf::ScanArgs &a = plan->base;
+    gf::fill_constants(a, *params, *quad);
     a.rad = reinterpret_cast<const double *>(base + off_rad);
     a.ang = reinterpret_cast<const double *>(base + off_ang);
     a.arc = reinterpret_cast<const double *>(base + off_arc);
     a.ang32 = reinterpret_cast<const float *>(base + off_a32);
-    a.n_r = nr;
-    a.n_a = na;
-    a.n_arc = nc;
     a.wmid = wmid;
-    a.m1_re = params->m1sq_re;
-    a.m1_im = params->m1sq_im;
-    a.m2_re = params->m2sq_re;
-    a.m2_im = params->m2sq_im;
-    a.lam2 = params->lambda2;
-    a.lam = std::sqrt(params->lambda2);
-    const std::complex<double> sy0 = std::sqrt(std::complex<double>(-params->m2sq_re,
-                                                                    -params->m2sq_im));
-    a.sy0_re = sy0.real();
-    a.sy0_im = sy0.imag();
-    a.scale = params->scale;
-    a.beta1 = geo.beta1;
-    a.beta2 = geo.beta2;
-    a.lo = geo.lo;
-    a.hi = geo.hi;
-    a.vstar = geo.vstar;
-    a.mirror_ok = geo.mirror_ok;
 
     // subtraction sum at mu^2 (FP64, real axis), computed once per plan
     double *d_jmu = reinterpret_cast<double *>(base + off_jmu);
+    a.jmu = d_jmu;
     hipStream_t s;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -349,16 +376,14 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
         return hip_fail(e, "hipStreamCreate");
     }
     e = gf::launch_jmu(a, params->mu2, d_jmu, s);
-    double jmu[2] = {0.0, 0.0};
-    if (e == hipSuccess) e = hipMemcpyAsync(jmu, d_jmu, sizeof(jmu), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->jmu, d_jmu, sizeof(plan->jmu), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
     if (e != hipSuccess) {
         gf_free(plan);
         return hip_fail(e, "subtraction-term kernel");
     }
-    a.jmu_re = jmu[0];
-    a.jmu_im = jmu[1];
     *out = plan;
     return GF_OK;
 }
@@ -379,51 +404,40 @@ void gf_free(gf_plan_t *plan)
 int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im)
 {
     if (!plan || !re || !im) return fail(GF_EINVAL, "NULL argument");
-    *re = plan->base.jmu_re;
-    *im = plan->base.jmu_im;
+    *re = plan->jmu[0];
+    *im = plan->jmu[1];
     return GF_OK;
 }
 
 int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid)
 {
     if (!plan || !grid) return fail(GF_EINVAL, "NULL argument");
-    return auto_lanes(*grid);
+    return gf::auto_lanes(*grid);
 }
 
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
                     int lanes_per_point, void *stream)
 {
     if (!plan) return fail(GF_EINVAL, "plan must not be NULL");
-    int rc = validate_grid(plan, grid);
+    int rc = gf::validate_grid(plan->params, grid);
     if (rc != GF_OK) return rc;
     if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
     int lanes = lanes_per_point;
-    if (lanes == 0) lanes = auto_lanes(*grid);
+    if (lanes == 0) lanes = gf::auto_lanes(*grid);
     if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)) != 0)
         return fail(GF_EINVAL, "lanes_per_point must be 0 or a power of two <= 64, got %d",
                     lanes_per_point);
     int dev;
-    if ((rc = current_device(&dev)) != GF_OK) return rc;
+    if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
     if (dev != plan->device)
         return fail(GF_EINVAL, "plan was built on device %d, current device is %d", plan->device,
                     dev);
     gf::ScanArgs a = plan->base;
-    a.n_re = grid->n_re;
-    a.n_im = grid->n_im;
-    a.re_lo = grid->re_lo;
-    a.im_lo = grid->im_lo;
-    a.d_re = (grid->re_hi - grid->re_lo) / (double)grid->n_re;
-    a.d_im = (grid->im_hi - grid->im_lo) / (double)grid->n_im;
-    long long nt;
-    tiles_for(*grid, lanes, &a.tiles_a, &nt);
-    if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
-    a.n_tiles = (int)nt;
+    if ((rc = gf::set_grid(a, *grid, lanes)) != GF_OK) return rc;
     a.out = static_cast<double *>(out);
     a.cls = cls_out;
     hipError_t e = gf::launch_scan(a, plan->quad.precision, lanes, static_cast<hipStream_t>(stream));
-    if (e == hipErrorInvalidValue && plan->quad.precision != GF_PREC_FP64)
-        return fail(GF_EUNSUPPORTED, "precision %d is not available", plan->quad.precision);
     if (e != hipSuccess) return hip_fail(e, "scan kernel launch");
     return GF_OK;
 }
@@ -437,10 +451,10 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
 int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad, void *out,
             void *stream)
 {
-    int rc = validate_params(params, quad);
+    int rc = gf::validate_params(params, quad);
     if (rc != GF_OK) return rc;
     int dev;
-    if ((rc = current_device(&dev)) != GF_OK) return rc;
+    if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
     const std::string key = cache_key(params, quad, dev);
     gf_plan_t *plan = nullptr;
     {

@@ -4,7 +4,11 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <cstddef>
 #include <cstdint>
+#include <vector>
+
+#include "../../include/gf.h"
 
 namespace gf {
 
@@ -34,7 +38,7 @@ struct ScanArgs {
     double m1_re, m1_im, m2_re, m2_im;  // m1^2, m2^2
     double lam2, lam;                    // Lambda^2, Lambda
     double sy0_re, sy0_im;               // sqrt(-m2^2) (residue node)
-    double jmu_re, jmu_im;               // unscaled subtraction sum at mu^2
+    const double *jmu;                   // device: unscaled subtraction sum at mu^2 (re, im)
     double scale;
 
     // contour geometry
@@ -53,12 +57,52 @@ struct ScanArgs {
     int8_t *cls;   // optional class map
 };
 
+// One unit of serving work: tile `tile` of the request whose arguments sit in
+// slot `req` of the device argument array.
+struct WorkItem {
+    int32_t req;
+    int32_t tile;
+};
+
 // Launches the scan of one grid (FP64 or FP32C angular sum) with `lanes`
 // lanes per point.
 hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t s);
 
 // Computes the unscaled real-axis sum at x = mu^2 (FP64) into dst[0..1].
 hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s);
+
+// The same for n requests at once: request i uses reqs[slots[i]] and mu2[i] and
+// writes into that request's jmu slot (device pointers).
+hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double *mu2, int n,
+                            hipStream_t s);
+
+// Persistent launch of `waves` wavefronts over n_items work items (device
+// arrays); *counter must be 0 on entry.  All items share precision and lanes.
+hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
+                        unsigned *counter, int precision, int lanes, int waves, hipStream_t s);
+
+// ---- host helpers shared by plans and the server (gf_host.cpp) ----------
+
+// Sets the thread-local error message; returns code.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+const char *last_error();
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+// radial table [r | sqrt r | W], angular pair tables, arc table [xi | w]
+void radial_table(int n_r, double lambda2, std::vector<double> &rad);
+void angular_tables(int n_a, std::vector<double> &ang, std::vector<float> &ang32, double *wmid);
+void arc_table(int n_arc, std::vector<double> &arc);
+// masses, cutoff, scale and contour geometry of a (params, quadrature)
+void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q);
+int validate_params(const gf_params *p, const gf_quadrature *q);
+int validate_grid(const gf_params &p, const gf_grid *g);
+// lanes per point the automatic choice uses for a grid
+int auto_lanes(const gf_grid &g);
+// grid fields and wave tiles of a ScanArgs for `lanes` lanes per point
+int set_grid(ScanArgs &a, const gf_grid &g, int lanes);
+int current_device(int *dev);
+size_t align256(size_t b);
 
 // Tile geometry of a wave for `lanes` lanes per point: tw x th points.
 inline void tile_shape(int lanes, int *tw, int *th)

@@ -46,6 +46,17 @@ __device__ __forceinline__ cd cdiv(cd a, cd b)
     return mk((a.r * b.r + a.i * b.i) * inv, (a.i * b.r - a.r * b.i) * inv);
 }
 
+// Plan tables and argument tables are read-only while a kernel runs.  Reading
+// them through the constant address space tells the compiler so: wave-uniform
+// reads then become scalar loads into SGPR operands even in the serving
+// kernel, whose stores of earlier work items would otherwise count as
+// possible clobbers.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *ro(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)(uintptr_t)p;
+}
+
 // principal square root; follows the sign of a zero imaginary part
 __device__ cd csqrt_principal(double a, double b)
 {
@@ -71,7 +82,8 @@ __device__ __forceinline__ double angle_between(double a, double b)
 // used instead.  The real axis is preferred where it is valid (|Im sqrt x| <
 // v*) and either comfortably inside (v < kRNear v*) or closer to its own edge
 // than the ray is to a bad ray.
-__device__ int classify(const ScanArgs &a, double xr, double xi, int *res_sign)
+template <class Args>
+__device__ int classify(const Args &a, double xr, double xi, int *res_sign)
 {
     cd sx = csqrt_principal(xr, xi);
     double v = fabs(sx.i);
@@ -122,7 +134,8 @@ struct PointCtx {
     int res_sign;
 };
 
-__device__ PointCtx point_setup(const ScanArgs &a, double xr, double xi, int cls, int res_sign)
+template <class Args>
+__device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign)
 {
     PointCtx P;
     cd sx = csqrt_principal(xr, xi);
@@ -154,22 +167,25 @@ __device__ PointCtx point_setup(const ScanArgs &a, double xr, double xi, int cls
 
 // Coefficients of contour node k: radial (ray or real axis), closing arc, or
 // residue of the k-leg pole.
-__device__ __forceinline__ void node_coeffs(const ScanArgs &a, const PointCtx &P, int k, cd &U,
+template <class Args>
+__device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V, cd &w)
 {
     const cd m2 = mk(a.m2_re, a.m2_im);
     if (k < a.n_r) {
-        double r = a.rad[k];
-        double sr = a.rad[a.n_r + k];
-        double wr = a.rad[2 * a.n_r + k];
+        const auto *rad = ro(a.rad);
+        double r = rad[k];
+        double sr = rad[a.n_r + k];
+        double wr = rad[2 * a.n_r + k];
         cd y = cscale(P.dir, r);                      // y = e^{i phi} r
         U = cadd(P.x1, y);
         V = cscale(P.sx2dir, sr);                     // 2 sqrt(x) sqrt(y)
         w = cdiv(cscale(cmul(P.dir, y), wr), cadd(y, m2));  // dy y / (y + m2^2)
     } else if (k < a.n_r + a.n_arc) {
         int q = k - a.n_r;
-        double xi = a.arc[q];
-        double wa = a.arc[a.n_arc + q];
+        const auto *arc = ro(a.arc);
+        double xi = arc[q];
+        double wa = arc[a.n_arc + q];
         double psi = 0.5 * P.phi * (1.0 - xi);        // from phi back to 0
         double s, c, sh, ch;
         sincos(psi, &s, &c);
@@ -202,9 +218,10 @@ __device__ __forceinline__ double rcp64(double q)
 // one complex denominator per two integrand evaluations; the middle node of an
 // odd rule (z = 0) adds w/U.  Two denominators share one reciprocal
 // (1/q0 = q1/(q0 q1)).  Table: (z^2, 2w) per pair, FP64.
-__device__ __forceinline__ cd angular_sum64(const double *__restrict__ tab, int npair, double wmid,
-                                            cd U, cd V)
+__device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
+                                            cd V)
 {
+    const auto *tab = ro(table);
     const cd U2 = cmul(U, U);
     const cd V2 = cmul(V, V);
     double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
@@ -256,9 +273,10 @@ __device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
 // node's sum leaves in FP64 as U 2^-e (hi + lo).
 constexpr int kBlock = 16;
 
-__device__ __forceinline__ cd angular_sum32c(const float *__restrict__ tab, int npair, double wmid,
-                                             cd U, cd V)
+__device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
+                                             cd V)
 {
+    const auto *tab = ro(table);
     const cd U2 = cmul(U, U);
     const cd V2 = cmul(V, V);
     const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
@@ -304,29 +322,28 @@ __device__ __forceinline__ cd angular_sum32c(const float *__restrict__ tab, int 
     return A;
 }
 
-template <int PREC>
-__device__ __forceinline__ cd angular_sum(const ScanArgs &a, cd U, cd V)
+template <int PREC, class Args>
+__device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V)
 {
     if (PREC == 0) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V);
     return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V);
 }
 
-template <int PREC, int L>
-__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
+// One wave's tile of grid points: STEP 4 (the point) and STEP 5 (eq. 15 on
+// the point's contour), shared by the one-grid scan and the serving kernel so a
+// point's result does not depend on which launch computes it.
+template <int PREC, int L, class Args>
+__device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 {
     constexpr int P = 64 / L;
     constexpr int TW = P < 8 ? P : 8;
     constexpr int TH = P / TW;
-    const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= a.n_tiles) return;  // uniform per wave
     const int p = lane / L;
     const int s = lane % L;
-    const int ia = (wave % a.tiles_a) * TW + p % TW;
-    const int ib = (wave / a.tiles_a) * TH + p / TW;
+    const int ia = (tile % a.tiles_a) * TW + p % TW;
+    const int ib = (tile / a.tiles_a) * TH + p / TW;
     const bool valid = ia < a.n_re && ib < a.n_im;
 
-    // STEP 4: the grid point, generated in place
     double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
     double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
     int sign = 0;
@@ -362,8 +379,8 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
             gr = __builtin_nan("");
             gi = __builtin_nan("");
         } else {
-            gr = a.scale * (sr - a.jmu_re);
-            gi = a.scale * (si - a.jmu_im);
+            gr = a.scale * (sr - a.jmu[0]);
+            gi = a.scale * (si - a.jmu[1]);
             if (cls == kMirror) gi = -gi;
         }
         const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
@@ -372,10 +389,38 @@ __global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
     }
 }
 
-// Subtraction sum at the real point mu^2 on the real axis (one wavefront).
-__global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double *dst)
+template <int PREC, int L>
+__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
 {
-    const int lane = threadIdx.x;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;  // uniform per wave
+    process_tile<PREC, L>(a, wave, threadIdx.x & 63);
+}
+
+// Serving: a persistent launch over a packed list of (request, tile) items of
+// many requests.  Each wave takes the next item from a device counter (one
+// lane's atomic, broadcast) until the list is exhausted, so every wave exits.
+template <int PREC, int L>
+__global__ void __launch_bounds__(256) serve_kernel(const ScanArgs *__restrict__ reqs,
+                                                   const WorkItem *__restrict__ items, int n_items,
+                                                   unsigned *counter)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned w = 0;
+        if (lane == 0) w = atomicAdd(counter, 1u);
+        w = __builtin_amdgcn_readlane(w, 0);  // wave-uniform item index
+        if (w >= (unsigned)n_items) break;
+        const int req = ro(items)[w].req;
+        const int tile = ro(items)[w].tile;
+        process_tile<PREC, L>(ro(reqs)[req], tile, lane);
+    }
+}
+
+// Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
+template <class Args>
+__device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
+{
     const PointCtx pc = point_setup(a, mu2, 0.0, kR, 0);
     double sr = 0.0, si = 0.0;
     for (int k = lane; k < pc.nodes; k += 64) {
@@ -397,6 +442,22 @@ __global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double 
     }
 }
 
+__global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double *dst)
+{
+    jmu_wave(a, mu2, dst, threadIdx.x);
+}
+
+// One wave per request: J_mu of request i into its args' jmu slot.
+__global__ void __launch_bounds__(64) jmu_batch_kernel(const ScanArgs *__restrict__ reqs,
+                                                       const int *__restrict__ slots,
+                                                       const double *__restrict__ mu2, int n)
+{
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const auto &a = ro(reqs)[__builtin_amdgcn_readfirstlane(slots[i])];
+    jmu_wave(a, mu2[i], const_cast<double *>(a.jmu), threadIdx.x);
+}
+
 template <int L>
 hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
@@ -405,6 +466,23 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
         hipLaunchKernelGGL((scan_kernel<0, L>), dim3(blocks), dim3(256), 0, s, a);
     } else if (precision == 1) {
         hipLaunchKernelGGL((scan_kernel<1, L>), dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t serve_l(const ScanArgs *reqs, const WorkItem *items, int n_items, unsigned *counter,
+                   int precision, int waves, hipStream_t s)
+{
+    const int blocks = (waves + 3) / 4;
+    if (precision == 0) {
+        hipLaunchKernelGGL((serve_kernel<0, L>), dim3(blocks), dim3(256), 0, s, reqs, items,
+                           n_items, counter);
+    } else if (precision == 1) {
+        hipLaunchKernelGGL((serve_kernel<1, L>), dim3(blocks), dim3(256), 0, s, reqs, items,
+                           n_items, counter);
     } else {
         return hipErrorInvalidValue;
     }
@@ -432,6 +510,30 @@ hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(jmu_kernel, dim3(1), dim3(64), 0, s, a, mu2, dst);
     return hipGetLastError();
+}
+
+hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double *mu2, int n,
+                            hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(jmu_batch_kernel, dim3(n), dim3(64), 0, s, reqs, slots, mu2, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
+                        unsigned *counter, int precision, int lanes, int waves, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    switch (lanes) {
+    case 1: return serve_l<1>(reqs, items, n_items, counter, precision, waves, s);
+    case 2: return serve_l<2>(reqs, items, n_items, counter, precision, waves, s);
+    case 4: return serve_l<4>(reqs, items, n_items, counter, precision, waves, s);
+    case 8: return serve_l<8>(reqs, items, n_items, counter, precision, waves, s);
+    case 16: return serve_l<16>(reqs, items, n_items, counter, precision, waves, s);
+    case 32: return serve_l<32>(reqs, items, n_items, counter, precision, waves, s);
+    case 64: return serve_l<64>(reqs, items, n_items, counter, precision, waves, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace gf

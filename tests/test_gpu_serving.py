@@ -1,0 +1,171 @@
+"""Serving (continuous batching) on the GPU: every served result equals the
+standalone scan of the same request bit for bit, whatever else was in flight;
+admission respects the device-memory budget; a seeded Poisson trace completes
+with latency statistics."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1205_0752_amd as gf  # noqa: E402
+from paper_1205_0752_amd.workloads import Grid, Params, Quadrature, serving_trace  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+WAIT_MS = 120000.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gf.load()
+    yield
+
+
+def _standalone(req):
+    plan = gf.Plan(req.params, req.quad)
+    out = gf.scan_plan(plan, req.grid)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().ravel()
+    plan.close()
+    return g
+
+
+def _small_trace(n, seed, sides=(16, 32, 48, 64, 96, 128), orders=(32, 64, 128)):
+    return serving_trace(n, 1e6, seed=seed, sides=sides, orders=orders)
+
+
+def test_served_results_equal_standalone_bitwise():
+    """40 mixed requests (real and conjugate masses, FP64 and FP32C, several
+    grid sizes and orders) submitted together: each result is bitwise equal to
+    its own standalone scan."""
+    reqs = _small_trace(40, seed=11)
+    assert {r.quad.precision for r in reqs} == {0, 1}
+    assert any(complex(r.params.m1sq).imag != 0 for r in reqs)
+    with gf.Server(budget_bytes=256 << 20, max_inflight=64, batch_evals=2e8) as srv:
+        tickets = [srv.submit(r.params, r.grid, r.quad) for r in reqs]
+        for t in tickets:
+            assert srv.wait(t, WAIT_MS)
+        results = [srv.result(t) for t in tickets]
+        st = srv.stats()
+        for t in tickets:
+            srv.release(t)
+    assert st["completed"] == 40 and st["batches"] >= 2
+    for r, g in zip(reqs, results):
+        ref = _standalone(r)
+        same = np.array_equal(g.view(np.float64), ref.view(np.float64), equal_nan=True)
+        assert same, (r, np.nanmax(np.abs(g - ref)), np.mean(g != ref))
+
+
+def test_served_results_match_oracle():
+    """Two served requests (conjugate pair, FP64; real masses, FP32C) against the
+    oracle on every point."""
+    reqs = [(Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Grid(24, 20, -8.0, 4.0, -4.0, 4.0),
+             Quadrature(64, 32, 16, gf.FP64)),
+            (Params(2.0, 0.7, 1.5, 1e6), Grid(20, 24, -8.0, 4.0, -4.0, 4.0),
+             Quadrature(96, 48, 16, gf.FP32C))]
+    with gf.Server(budget_bytes=64 << 20, max_inflight=8) as srv:
+        ts = [srv.submit(*r) for r in reqs]
+        for t in ts:
+            assert srv.wait(t, WAIT_MS)
+        got = [srv.result(t) for t in ts]
+    for (p, g, q), res in zip(reqs, got):
+        go, co, cond = oracle.scan(p, q, g, want_cond=True)
+        err = np.abs(res - go)
+        mag = np.abs(go)
+        if q.precision == gf.FP64:
+            assert np.all(err <= np.maximum(1e-12 * mag, 64 * 2.0 ** -53 * cond * mag))
+        else:
+            assert np.all(err <= np.maximum(1e-6 * np.maximum(mag, 1.0),
+                                            16 * 2.0 ** -24 * cond * mag))
+
+
+def test_admission_waits_for_memory_budget():
+    """A 1 MiB arena holds at most three 128^2 outputs (256 KiB each) plus
+    tables: twelve such requests queue, are admitted as memory frees, all
+    complete, the arena peak never exceeds the budget, and results are still
+    bitwise equal to standalone scans."""
+    reqs = [r for r in _small_trace(60, seed=5, sides=(128,), orders=(32, 64))][:12]
+    budget = 1 << 20
+    with gf.Server(budget_bytes=budget, max_inflight=64, batch_evals=5e8) as srv:
+        tickets = [srv.submit(r.params, r.grid, r.quad) for r in reqs]
+        peak_queued = srv.stats()["queued"]
+        results = {}
+        remaining = set(tickets)
+        t0 = time.time()
+        while remaining and time.time() - t0 < 120:
+            t = srv.wait_any(1000.0)
+            if t is None:
+                continue
+            results[t] = srv.result(t)
+            srv.release(t)
+            remaining.discard(t)
+        st = srv.stats()
+    assert not remaining
+    assert st["bytes_peak"] <= budget
+    assert peak_queued >= 1 or st["batches"] >= 4
+    for r, t in zip(reqs, tickets):
+        ref = _standalone(r)
+        assert np.array_equal(results[t].view(np.float64), ref.view(np.float64), equal_nan=True)
+
+
+def test_request_larger_than_budget_is_rejected():
+    with gf.Server(budget_bytes=1 << 20, max_inflight=4) as srv:
+        with pytest.raises(gf.GFError) as e:
+            srv.submit(Params(1.0, 1.0, 1.0, 1e6), Grid(512, 512, -8.0, 4.0, -4.0, 4.0),
+                       Quadrature(32, 32, 16))
+        assert e.value.code == -5
+        with pytest.raises(gf.GFError) as e:
+            srv.submit(Params(-1.0, 1.0, 1.0, 1e6), Grid(16, 16, -8.0, 4.0, -4.0, 4.0),
+                       Quadrature(32, 32, 16))
+        assert e.value.code == -1
+        assert srv.stats()["rejected"] == 2
+
+
+def test_poisson_trace_replay_reports_latency():
+    """A seeded Poisson trace of 300 requests replayed in real time (results
+    released as they complete): all complete; latency percentiles are ordered."""
+    reqs = serving_trace(300, 3000.0, seed=0, sides=tuple(range(16, 257, 16)),
+                         orders=(32, 64, 128, 256))
+    with gf.Server(budget_bytes=512 << 20, max_inflight=512) as srv:
+        t0 = time.perf_counter()
+        outstanding = 0
+        i = 0
+        while i < len(reqs) or outstanding:
+            now = time.perf_counter() - t0
+            if i < len(reqs) and reqs[i].arrival_s <= now:
+                srv.submit(reqs[i].params, reqs[i].grid, reqs[i].quad)
+                i += 1
+                outstanding += 1
+                continue
+            wait = (reqs[i].arrival_s - now) * 1e3 if i < len(reqs) else 1000.0
+            t = srv.wait_any(max(wait, 0.0))
+            if t is not None:
+                srv.release(t)
+                outstanding -= 1
+            assert time.perf_counter() - t0 < 300
+        st = srv.stats()
+    print("serving stats", st)
+    assert st["completed"] == 300 and st["released"] == 300
+    assert 0 < st["latency_p50_ms"] <= st["latency_p90_ms"] <= st["latency_p99_ms"] <= st[
+        "latency_max_ms"]
+    assert st["bytes_in_use"] == 0 or st["bytes_in_use"] <= st["bytes_budget"]
+
+
+def test_poll_states_and_unknown_ticket():
+    with gf.Server(budget_bytes=16 << 20, max_inflight=4) as srv:
+        t = srv.submit(Params(1.0, 1.0, 1.0, 1e6), Grid(64, 64, -8.0, 4.0, -4.0, 4.0),
+                       Quadrature(128, 64, 16))
+        assert srv.poll(t) in (gf.REQ_QUEUED, gf.REQ_RUNNING, gf.REQ_DONE)
+        assert srv.wait(t, WAIT_MS)
+        assert srv.poll(t) == gf.REQ_DONE
+        with pytest.raises(gf.GFError) as e:
+            srv.poll(t + 1000)
+        assert e.value.code == -6
+        srv.release(t)
+        with pytest.raises(gf.GFError):
+            srv.release(t)
