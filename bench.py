@@ -95,7 +95,42 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
     return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
-            "kernel": f"scan_kernel<{quad.precision},{used_lanes}>"}
+            "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}>"}
+
+
+def fp32c_errors(gf, torch, params, grid, quad):
+    """Error of an FP32C scan against the FP64 path (same grid and nodes; the
+    FP64 path matches the CPU oracle to 1e-12), max and mean, absolute and
+    relative, within 0.05 of the cut x < -(m1 + m2)^2 and elsewhere."""
+    import dataclasses
+    import numpy as np
+    q64 = dataclasses.replace(quad, precision=gf.FP64)
+    outs = []
+    for q in (quad, q64):
+        plan = gf.Plan(params, q)
+        outs.append(gf.scan_plan(plan, grid))
+        torch.cuda.synchronize()
+        plan.close()
+    g32, g64 = (o.cpu().numpy().ravel() for o in outs)
+    a = np.arange(grid.n_re)
+    b = np.arange(grid.n_im)
+    xr = np.broadcast_to(grid.re_lo + (a[None, :] + 0.5) * (grid.re_hi - grid.re_lo) / grid.n_re,
+                         (grid.n_im, grid.n_re)).ravel()
+    xi = np.broadcast_to(grid.im_lo + (b[:, None] + 0.5) * (grid.im_hi - grid.im_lo) / grid.n_im,
+                         (grid.n_im, grid.n_re)).ravel()
+    thr = (abs(complex(params.m1sq)) ** 0.5 + abs(complex(params.m2sq)) ** 0.5) ** 2
+    band = (np.abs(xi) < 0.05) & (xr < -thr)
+    rep = {}
+    for name, m in (("cut_band", band), ("elsewhere", ~band)):
+        if not m.any():
+            continue
+        err = np.abs(g32[m] - g64[m])
+        rel = err / np.abs(g64[m])
+        rep[name] = {"points": int(m.sum()), "max_abs": float(err.max()),
+                     "mean_abs": float(err.mean()), "max_rel": float(rel.max()),
+                     "mean_rel": float(rel.mean()),
+                     "frac_rel_le_1e-6": float(np.mean(rel <= 1e-6))}
+    return rep
 
 
 def serve_trace(gf, n_requests, rate, budget_bytes, seed=0):
@@ -215,7 +250,8 @@ def main() -> int:
                            "evals_per_s": t2["evals_per_s"], "points_per_s": t2["points_per_s"],
                            "ms_per_step": t2["ms"], "tflops": t2["tflops"],
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
-                           "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS}
+                           "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS,
+                           "error_vs_fp64": fp32c_errors(gf, torch, p2, g2, q2)}
     if not args.skip_serving and args.config == "c1_fp64_1024sq":
         result["serving"] = serve_trace(gf, args.serve_requests, args.serve_rate,
                                         args.serve_budget)

@@ -166,10 +166,11 @@ int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
  * `batch_evals` integrand evaluations each, oldest first) into persistent
  * kernel launches, and keeps two such batches in flight.  A request completes
  * when its last tile has run; its result stays in the arena until
- * gf_server_release.  Every point is computed by the same device code, lane
- * split and tables as gf_scan_plan with automatic lanes, so a served result is
- * bitwise identical to a standalone scan of the same request.  Node tables are
- * cached by (n_radial, lambda2), n_angular and n_arc and shared by requests.
+ * gf_server_release.  Every point is computed by the same device code and
+ * tables as gf_scan_plan_ex with one lane per point, so a served result is
+ * bitwise identical to that standalone scan of the same request, whatever else
+ * was in flight.  Node tables are cached by (n_radial, lambda2), n_angular and
+ * n_arc and shared by requests.
  *
  * Thread safety: all gf_server_* calls may be made from any thread. */
 typedef struct gf_server gf_server_t;

@@ -13,7 +13,8 @@ import os
 from .workloads import FP32C, FP64, Grid, Params, Quadrature
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_libgf.so")
+#: the in-tree build; GF_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("GF_LIBRARY") or os.path.join(_HERE, "_libgf.so")
 
 GF_OK = 0
 GF_EINVAL = -1

@@ -40,9 +40,16 @@ __device__ __forceinline__ cd cmul(cd a, cd b)
     return mk(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
 }
 __device__ __forceinline__ cd cscale(cd a, double s) { return mk(a.r * s, a.i * s); }
+__device__ __forceinline__ double rcp64(double q)
+{
+    // hardware reciprocal estimate (24 bits on gfx950) + one Newton-Raphson step
+    double r = __builtin_amdgcn_rcp(q);
+    return fma(fma(-q, r, 1.0), r, r);
+}
+// a / b = a conj(b) / |b|^2 with the refined reciprocal
 __device__ __forceinline__ cd cdiv(cd a, cd b)
 {
-    double inv = 1.0 / (b.r * b.r + b.i * b.i);
+    double inv = rcp64(b.r * b.r + b.i * b.i);
     return mk((a.r * b.r + a.i * b.i) * inv, (a.i * b.r - a.r * b.i) * inv);
 }
 
@@ -123,14 +130,14 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign)
     return rot;
 }
 
-// Per-point quantities hoisted out of the node loop.
+// Per-point quantities hoisted out of the node loop.  V^2 = 4 x y for every
+// node whatever the branches of sqrt(x) sqrt(y), and the angular sum depends
+// on V only through V^2 (symmetric rule), so no square root of y is needed.
 struct PointCtx {
-    cd x1;       // x + m1^2
-    cd sx2dir;   // 2 sqrt(x) e^{i phi/2} (ray) or 2 sqrt(x) (real axis)
-    cd sx2;      // 2 sqrt(x)
-    cd dir;      // e^{i phi} (ray) or 1 (real axis)
+    cd x1;   // x + m1^2
+    cd dir;  // e^{i phi} (ray) or 1 (real axis)
     double phi;
-    int nodes;   // contour nodes of this point
+    int nodes;  // contour nodes of this point
     int res_sign;
 };
 
@@ -138,119 +145,130 @@ template <class Args>
 __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign)
 {
     PointCtx P;
-    cd sx = csqrt_principal(xr, xi);
     P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
-    P.sx2 = cscale(sx, 2.0);
     P.res_sign = res_sign;
-    if (cls == kR) {
-        P.dir = mk(1.0, 0.0);
-        P.sx2dir = P.sx2;
-        P.phi = 0.0;
-        P.nodes = a.n_r;
-    } else if (cls == kY || cls == kYRes) {
+    if (cls == kY || cls == kYRes) {
         double phi = atan2(xi, xr);
-        double s, c, sh, ch;
+        double s, c;
         sincos(phi, &s, &c);
-        sincos(0.5 * phi, &sh, &ch);
         P.dir = mk(c, s);
-        P.sx2dir = cmul(P.sx2, mk(ch, sh));
         P.phi = phi;
         P.nodes = a.n_r + a.n_arc + (cls == kYRes ? 1 : 0);
     } else {
         P.dir = mk(1.0, 0.0);
-        P.sx2dir = P.sx2;
         P.phi = 0.0;
-        P.nodes = 0;
+        P.nodes = cls == kR ? a.n_r : 0;
     }
     return P;
 }
 
-// Coefficients of contour node k: radial (ray or real axis), closing arc, or
-// residue of the k-leg pole.
+// Coefficients of contour node k -- radial (ray or real axis), closing arc,
+// or residue of the k-leg pole: U = x + y + m1^2, V^2 = 4 x y and the node's
+// weight omega (dy-weight times y / (y + m2^2), or +-2 pi i y0).
 template <class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
-                                            cd &V, cd &w)
+                                            cd &V2, cd &w)
 {
     const cd m2 = mk(a.m2_re, a.m2_im);
+    // 4 x, recovered from x + m1^2 (recomputing it per node keeps fewer
+    // registers live across the node loop than carrying it)
+    const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
     if (k < a.n_r) {
         const auto *rad = ro(a.rad);
-        double r = rad[k];
-        double sr = rad[a.n_r + k];
-        double wr = rad[2 * a.n_r + k];
-        cd y = cscale(P.dir, r);                      // y = e^{i phi} r
+        const double r = rad[k];
+        const double wr = rad[2 * a.n_r + k];
+        const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
         U = cadd(P.x1, y);
-        V = cscale(P.sx2dir, sr);                     // 2 sqrt(x) sqrt(y)
-        w = cdiv(cscale(cmul(P.dir, y), wr), cadd(y, m2));  // dy y / (y + m2^2)
+        V2 = cmul(x4, y);                                      // 4 x y
+        w = cdiv(cscale(cmul(P.dir, P.dir), wr * r), cadd(y, m2));  // e^{i phi} dr y/(y + m2^2)
     } else if (k < a.n_r + a.n_arc) {
-        int q = k - a.n_r;
+        const int q = k - a.n_r;
         const auto *arc = ro(a.arc);
-        double xi = arc[q];
-        double wa = arc[a.n_arc + q];
-        double psi = 0.5 * P.phi * (1.0 - xi);        // from phi back to 0
-        double s, c, sh, ch;
+        const double xi = arc[q];
+        const double wa = arc[a.n_arc + q];
+        const double psi = 0.5 * P.phi * (1.0 - xi);     // from phi back to 0
+        double s, c;
         sincos(psi, &s, &c);
-        sincos(0.5 * psi, &sh, &ch);
-        cd y = mk(a.lam2 * c, a.lam2 * s);
+        const cd y = mk(a.lam2 * c, a.lam2 * s);
         U = cadd(P.x1, y);
-        V = cmul(P.sx2, mk(a.lam * ch, a.lam * sh));
-        double h = 0.5 * P.phi * wa;
-        cd dy = mk(y.i * h, -y.r * h);                // dy = -i y (phi/2) dxi
+        V2 = cmul(x4, y);
+        const double h = 0.5 * P.phi * wa;
+        const cd dy = mk(y.i * h, -y.r * h);              // dy = -i y (phi/2) dxi
         w = cdiv(cmul(dy, y), cadd(y, m2));
     } else {
-        cd y0 = mk(-a.m2_re, -a.m2_im);
+        const cd y0 = mk(-a.m2_re, -a.m2_im);
         U = cadd(P.x1, y0);
-        V = cmul(P.sx2, mk(a.sy0_re, a.sy0_im));
-        double f = P.res_sign * 2.0 * M_PI;          // +-2 pi i Res
+        V2 = cmul(x4, y0);
+        const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i Res
         w = mk(-y0.i * f, y0.r * f);
     }
-}
-
-__device__ __forceinline__ double rcp64(double q)
-{
-    // hardware reciprocal estimate (24 bits on gfx950) + one Newton-Raphson step
-    double r = __builtin_amdgcn_rcp(q);
-    return fma(fma(-q, r, 1.0), r, r);
 }
 
 // Angular sum A = sum_j w_j / (U - V z_j) over the GC-II rule.  The rule is
 // symmetric (z_{n+1-j} = -z_j, equal weights), so each node pair is folded:
 //   w/(U - V z) + w/(U + V z) = 2 w U / (U^2 - V^2 z^2),
 // one complex denominator per two integrand evaluations; the middle node of an
-// odd rule (z = 0) adds w/U.  Two denominators share one reciprocal
-// (1/q0 = q1/(q0 q1)).  Table: (z^2, 2w) per pair, FP64.
+// odd rule (z = 0) adds w/U.  U^2 and V^2 are scaled by an exact power of two
+// 2^-e (e = exponent of their largest component), which changes no rounding
+// and keeps every |D|^2 near 1, so four denominators can share one reciprocal
+// (1/q0 = q1 q2 q3 / (q0 q1 q2 q3)) without overflow.  Table: (z^2, 2w) per
+// pair, FP64.
+__device__ __forceinline__ int scale_exponent(cd U2, cd V2)
+{
+    const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
+    int e = 0;
+    frexp(big, &e);
+    return e;
+}
+
 __device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
-                                            cd V)
+                                            cd V2in)
 {
     const auto *tab = ro(table);
-    const cd U2 = cmul(U, U);
-    const cd V2 = cmul(V, V);
+    const cd U2in = cmul(U, U);
+    const int e = scale_exponent(U2in, V2in);
+    const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
+    const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
     double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
     int p = 0;
-#pragma unroll 2
-    for (; p + 2 <= npair; p += 2) {
+    for (; p + 4 <= npair; p += 4) {
         const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
         const double zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
-        const double dr0 = fma(-V2.r, zz0, U2.r), di0 = fma(-V2.i, zz0, U2.i);
-        const double dr1 = fma(-V2.r, zz1, U2.r), di1 = fma(-V2.i, zz1, U2.i);
+        const double zz2 = tab[2 * p + 4], ww2 = tab[2 * p + 5];
+        const double zz3 = tab[2 * p + 6], ww3 = tab[2 * p + 7];
+        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
+        const double dr1 = fma(-v2r, zz1, u2r), di1 = fma(-v2i, zz1, u2i);
+        const double dr2 = fma(-v2r, zz2, u2r), di2 = fma(-v2i, zz2, u2i);
+        const double dr3 = fma(-v2r, zz3, u2r), di3 = fma(-v2i, zz3, u2i);
         const double q0 = fma(dr0, dr0, di0 * di0);
         const double q1 = fma(dr1, dr1, di1 * di1);
-        const double inv = rcp64(q0 * q1);
-        const double t0 = ww0 * (q1 * inv);
-        const double t1 = ww1 * (q0 * inv);
+        const double q2 = fma(dr2, dr2, di2 * di2);
+        const double q3 = fma(dr3, dr3, di3 * di3);
+        const double p01 = q0 * q1, p23 = q2 * q3;
+        const double inv = rcp64(p01 * p23);
+        const double i01 = p23 * inv, i23 = p01 * inv;
+        const double t0 = ww0 * (q1 * i01);
+        const double t1 = ww1 * (q0 * i01);
+        const double t2 = ww2 * (q3 * i23);
+        const double t3 = ww3 * (q2 * i23);
         ar0 = fma(t0, dr0, ar0);
         ai0 = fma(t0, di0, ai0);
         ar1 = fma(t1, dr1, ar1);
         ai1 = fma(t1, di1, ai1);
+        ar0 = fma(t2, dr2, ar0);
+        ai0 = fma(t2, di2, ai0);
+        ar1 = fma(t3, dr3, ar1);
+        ai1 = fma(t3, di3, ai1);
     }
-    if (p < npair) {
+    for (; p < npair; ++p) {
         const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
-        const double dr0 = fma(-V2.r, zz0, U2.r), di0 = fma(-V2.i, zz0, U2.i);
+        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
         const double t0 = ww0 * rcp64(fma(dr0, dr0, di0 * di0));
         ar0 = fma(t0, dr0, ar0);
         ai0 = fma(t0, di0, ai0);
     }
-    // sum 2w / D = sum 2w conj(D) / |D|^2, then times U
-    cd A = cmul(U, mk(ar0 + ar1, -(ai0 + ai1)));
+    // sum 2w / D = sum 2w conj(D) / |D|^2 (scaled by 2^e), then times U
+    cd A = cmul(U, mk(ldexp(ar0 + ar1, -e), -ldexp(ai0 + ai1, -e)));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
     return A;
 }
@@ -274,14 +292,11 @@ __device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
 constexpr int kBlock = 16;
 
 __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
-                                             cd V)
+                                             cd V2)
 {
     const auto *tab = ro(table);
     const cd U2 = cmul(U, U);
-    const cd V2 = cmul(V, V);
-    const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
-    int e = 0;
-    frexp(big, &e);
+    const int e = scale_exponent(U2, V2);
     const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
     const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
     float hr = 0.0f, lr = 0.0f, hi = 0.0f, li = 0.0f;
@@ -322,11 +337,34 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
     return A;
 }
 
-template <int PREC, class Args>
-__device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V)
+// FP32C keeps a node's angular sum in FP64 when the node lies close to the
+// angular cut.  The folded denominators are U^2 - V^2 s with s = z^2 in (0, 1);
+// rounding U^2, V^2 and s to FP32 perturbs them by ~eps32 (|U^2| + |V^2|),
+// relative to their smallest size, the distance d from U^2 to the segment
+// [0, V^2].  Nodes with (|U^2| + |V^2|) > kFp32Sensitivity d (tested in
+// squares, in FP64) take the FP64 sum.  The test depends on the node alone, so
+// results stay reproducible.
+constexpr double kFp32Sensitivity = 16.0;
+
+__device__ __forceinline__ bool near_angular_cut(cd U, cd V2)
 {
-    if (PREC == 0) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V);
-    return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V);
+    const cd U2 = cmul(U, U);
+    const double vv = V2.r * V2.r + V2.i * V2.i;
+    const double uu = U2.r * U2.r + U2.i * U2.i;
+    if (vv == 0.0) return false;  // sum is exactly 1/U
+    // closest point of the segment s V^2, s in [0, 1], to U^2
+    double s = (U2.r * V2.r + U2.i * V2.i) / vv;
+    s = fmin(fmax(s, 0.0), 1.0);
+    const double dr = U2.r - s * V2.r, di = U2.i - s * V2.i;
+    const double dd = dr * dr + di * di;
+    return 2.0 * (uu + vv) > kFp32Sensitivity * kFp32Sensitivity * dd;
+}
+
+template <int PREC, class Args>
+__device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
+{
+    if (PREC == 0 || near_angular_cut(U, V2)) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+    return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V2);
 }
 
 // One wave's tile of grid points: STEP 4 (the point) and STEP 5 (eq. 15 on
@@ -361,9 +399,9 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
     double sr = 0.0, si = 0.0;
     for (int k = s; k < pc.nodes; k += L) {
-        cd U, V, w;
-        node_coeffs(a, pc, k, U, V, w);
-        cd A = angular_sum<PREC>(a, U, V);
+        cd U, V2, w;
+        node_coeffs(a, pc, k, U, V2, w);
+        cd A = angular_sum<PREC>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -389,21 +427,32 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
     }
 }
 
-template <int PREC, int L>
-__global__ void __launch_bounds__(256) scan_kernel(ScanArgs a)
+// Register budgets: the FP64 kernel runs best at 5 waves per SIMD, the FP32C
+// kernel at 6 (measured; the few spills this costs sit outside the inner loop).
+template <int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<PREC, L>(a, wave, threadIdx.x & 63);
+    process_tile<0, L>(a, wave, threadIdx.x & 63);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+scan_kernel_fp32c(ScanArgs a)
+{
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;  // uniform per wave
+    process_tile<1, L>(a, wave, threadIdx.x & 63);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
 // many requests.  Each wave takes the next item from a device counter (one
 // lane's atomic, broadcast) until the list is exhausted, so every wave exits.
 template <int PREC, int L>
-__global__ void __launch_bounds__(256) serve_kernel(const ScanArgs *__restrict__ reqs,
-                                                   const WorkItem *__restrict__ items, int n_items,
-                                                   unsigned *counter)
+__device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem *items, int n_items,
+                                           unsigned *counter)
 {
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -417,6 +466,22 @@ __global__ void __launch_bounds__(256) serve_kernel(const ScanArgs *__restrict__
     }
 }
 
+template <int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+serve_kernel_fp64(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
+                  int n_items, unsigned *counter)
+{
+    serve_loop<0, L>(reqs, items, n_items, counter);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+serve_kernel_fp32c(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
+                   int n_items, unsigned *counter)
+{
+    serve_loop<1, L>(reqs, items, n_items, counter);
+}
+
 // Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
 template <class Args>
 __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
@@ -424,9 +489,9 @@ __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst,
     const PointCtx pc = point_setup(a, mu2, 0.0, kR, 0);
     double sr = 0.0, si = 0.0;
     for (int k = lane; k < pc.nodes; k += 64) {
-        cd U, V, w;
-        node_coeffs(a, pc, k, U, V, w);
-        cd A = angular_sum<0>(a, U, V);
+        cd U, V2, w;
+        node_coeffs(a, pc, k, U, V2, w);
+        cd A = angular_sum<0>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -463,9 +528,9 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
     const int blocks = (a.n_tiles + 3) / 4;
     if (precision == 0) {
-        hipLaunchKernelGGL((scan_kernel<0, L>), dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(scan_kernel_fp64<L>, dim3(blocks), dim3(256), 0, s, a);
     } else if (precision == 1) {
-        hipLaunchKernelGGL((scan_kernel<1, L>), dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(scan_kernel_fp32c<L>, dim3(blocks), dim3(256), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -478,10 +543,10 @@ hipError_t serve_l(const ScanArgs *reqs, const WorkItem *items, int n_items, uns
 {
     const int blocks = (waves + 3) / 4;
     if (precision == 0) {
-        hipLaunchKernelGGL((serve_kernel<0, L>), dim3(blocks), dim3(256), 0, s, reqs, items,
+        hipLaunchKernelGGL(serve_kernel_fp64<L>, dim3(blocks), dim3(256), 0, s, reqs, items,
                            n_items, counter);
     } else if (precision == 1) {
-        hipLaunchKernelGGL((serve_kernel<1, L>), dim3(blocks), dim3(256), 0, s, reqs, items,
+        hipLaunchKernelGGL(serve_kernel_fp32c<L>, dim3(blocks), dim3(256), 0, s, reqs, items,
                            n_items, counter);
     } else {
         return hipErrorInvalidValue;

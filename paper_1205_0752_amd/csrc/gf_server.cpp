@@ -8,9 +8,10 @@
 // never waits for the host.  A request is done when its last tile's batch has
 // completed (HIP event); its output stays in the arena until released.
 //
-// Every point is computed by the same device function, table values, lane
-// split (the automatic choice of gf_scan_plan) and subtraction-sum kernel as a
-// standalone scan, so a served result is bitwise identical to gf_scan_plan's.
+// Every point is computed by the same device function, table values and
+// subtraction-sum kernel as a standalone scan with one lane per point, so a
+// served result is bitwise identical to gf_scan_plan_ex(..., 1, ...) and does
+// not depend on what else was in flight.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -581,7 +582,9 @@ int gf_server_submit(gf_server_t *s, const gf_params *params, const gf_grid *gri
     r->keys[0] = key_radial(*quad, *params);
     r->keys[1] = key_angular(*quad);
     r->keys[2] = key_arc(*quad);
-    r->lanes = gf::auto_lanes(*grid);
+    // one lane per point: the batch already fills the GPU with many requests,
+    // and whole 64-point tiles waste no lanes on short node lists
+    r->lanes = 1;
     r->cost_per_tile = (64.0 / r->lanes) * nominal_evals_per_point(*quad) *
                        (quad->precision == GF_PREC_FP32C ? 0.6 : 1.0);
     r->t_submit = Clock::now();

@@ -27,8 +27,10 @@ def _setup():
 
 
 def _standalone(req):
+    """The same request as a standalone scan with one lane per point (the
+    server's lane split)."""
     plan = gf.Plan(req.params, req.quad)
-    out = gf.scan_plan(plan, req.grid)
+    out = gf.scan_plan(plan, req.grid, lanes=1)
     torch.cuda.synchronize()
     g = out.cpu().numpy().ravel()
     plan.close()
@@ -59,6 +61,23 @@ def test_served_results_equal_standalone_bitwise():
         ref = _standalone(r)
         same = np.array_equal(g.view(np.float64), ref.view(np.float64), equal_nan=True)
         assert same, (r, np.nanmax(np.abs(g - ref)), np.mean(g != ref))
+
+
+def test_result_alone_equals_result_in_mix():
+    """A request served alone and the same request served inside a mix of 30
+    others give bitwise identical results."""
+    reqs = _small_trace(31, seed=21)
+    probe = reqs[7]
+    with gf.Server(budget_bytes=64 << 20, max_inflight=8) as srv:
+        t = srv.submit(probe.params, probe.grid, probe.quad)
+        assert srv.wait(t, WAIT_MS)
+        alone = srv.result(t)
+    with gf.Server(budget_bytes=64 << 20, max_inflight=64, batch_evals=1e8) as srv:
+        ts = [srv.submit(r.params, r.grid, r.quad) for r in reqs]
+        for t in ts:
+            assert srv.wait(t, WAIT_MS)
+        mixed = srv.result(ts[7])
+    assert np.array_equal(alone.view(np.float64), mixed.view(np.float64), equal_nan=True)
 
 
 def test_served_results_match_oracle():
