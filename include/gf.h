@@ -156,6 +156,30 @@ void gf_cache_clear(void);
 int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im);
 int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
 
+/* ---- y-plane diagnostics (the paper's Fig. 1 and eq. 23-25) -------------
+ *
+ * At a fixed external point x, the angular integral produces a cut in the
+ * complex y = k^2 plane where the first propagator vanishes for some
+ * z = cos(theta1) in [-1, 1]; whether that cut blocks the real y axis decides
+ * the contour (STEP 3).  gf_yscan_plan evaluates, with the plan's angular rule
+ * in FP64, at every point of a cell-centred grid of complex y:
+ *   GF_YSCAN_ANGULAR    <1/D1>(x, y) = sum_j w_j / (x + y + m1^2 - 2 sqrt(x) sqrt(y) z_j)
+ *   GF_YSCAN_INTEGRAND  y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)), the
+ *                       subtracted y-integrand of eq. 14 (eq. 22 in the
+ *                       worked example, up to the factor 2/pi)
+ * into `out` (complex128 [n_im][n_re], caller-owned device memory),
+ * asynchronously on `stream`.  Errors: GF_EINVAL, GF_EDEVICE. */
+#define GF_YSCAN_ANGULAR 0
+#define GF_YSCAN_INTEGRAND 1
+int gf_yscan_plan(const gf_plan_t *plan, double x_re, double x_im, const gf_grid *ygrid, int what,
+                  void *out, void *stream);
+
+/* The continuum cut of eq. 25 for the build's first propagator: the y where
+ * x + y + m1^2 - 2 sqrt(x) sqrt(y) cos(t) = 0, both roots, for n angles
+ * t = pi k/(n-1), k = 0..n-1 (n >= 2).  out: 4n doubles per k as
+ * (re y+, im y+, re y-, im y-).  Host only.  Errors: GF_EINVAL. */
+int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, double *out);
+
 /* ---- serving: continuous batching of scan requests ----------------------
  *
  * A server owns one HIP stream, a device-memory arena of `device_budget_bytes`

@@ -75,6 +75,8 @@ def _load():
         lib.orc_evals_for_class.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int]
         lib.orc_evals_for_class.restype = ctypes.c_long
         lib.orc_threads.restype = ctypes.c_int
+        lib.orc_yscan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_long, dp, dp, ctypes.c_int, dp]
         _lib = lib
     return _lib
 
@@ -212,6 +214,19 @@ def eval_points_q(params, quad, x):
     pr = problem(params, quad)
     lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls)
     return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+
+
+def yscan(params, quad, x: complex, y, what: int = 0) -> np.ndarray:
+    """y-plane diagnostic at fixed x: <1/D1>(x, y) (what = 0) or the subtracted
+    y-integrand y/(y + m2^2)(<1/D1>(x, y) - <1/D1>(mu^2, y)) (what = 1)."""
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.complex128).ravel())
+    yr = np.ascontiguousarray(y.real)
+    yi = np.ascontiguousarray(y.imag)
+    out = np.zeros(2 * y.size)
+    pr = problem(params, quad)
+    _load().orc_yscan(ctypes.byref(pr), complex(x).real, complex(x).imag, y.size, _dp(yr), _dp(yi),
+                      int(what), _dp(out))
+    return out[0::2] + 1j * out[1::2]
 
 
 def threads() -> int:

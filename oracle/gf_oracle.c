@@ -497,3 +497,31 @@ long orc_evals_for_class(const orc_problem *p, int cls)
 
 /* Threads an OpenMP region of the oracle uses. */
 int orc_threads(void) { return omp_get_max_threads(); }
+
+/* y-plane diagnostic at fixed x (the paper's Fig. 1): for each y_k,
+ * what = 0: <1/D1>(x, y_k); what = 1: y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)),
+ * the subtracted y-integrand of eq. 14.  out: 2n doubles. */
+int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const double *y_re,
+              const double *y_im, int what, double *out)
+{
+    if (p->n_angular <= 0) return -1;
+    double *z = malloc(sizeof(double) * p->n_angular), *w = malloc(sizeof(double) * p->n_angular);
+    orc_gauss_cheb2(p->n_angular, z, w);
+    cplx x = x_re + I * x_im, m1sq = p->m1sq_re + I * p->m1sq_im, m2sq = p->m2sq_re + I * p->m2sq_im;
+    cplx sx = csqrt(x), smu = sqrt(p->mu2);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) {
+        cplx y = y_re[k] + I * y_im[k];
+        cplx sy = csqrt(y);
+        cplx a = angular_d1(x, y, sx * sy, m1sq, p->n_angular, z, w, NULL);
+        if (what == 1) {
+            cplx amu = angular_d1(p->mu2 + 0.0 * I, y, smu * sy, m1sq, p->n_angular, z, w, NULL);
+            a = y / (y + m2sq) * (a - amu);
+        }
+        out[2 * k] = creal(a);
+        out[2 * k + 1] = cimag(a);
+    }
+    free(z);
+    free(w);
+    return 0;
+}

@@ -9,10 +9,11 @@ The library is loaded on first use; importing this package does not touch the
 GPU.
 """
 from ._binding import (CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
-                       REQ_DONE, REQ_QUEUED, REQ_RUNNING, GFError, LIB_PATH, Plan, Server, cache_clear, empty_result, load, scan, scan_plan,
+                       REQ_DONE, REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError,
+                       LIB_PATH, Plan, Server, cache_clear, cut_curve, yscan_plan, empty_result, load, scan, scan_plan,
                        version)
 from .workloads import CONFIGS, FP32C, FP64, Grid, Params, Quadrature
 
 __all__ = ["Params", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_plan", "cache_clear",
-           "empty_result", "version", "load", "GFError", "EXPORTS", "LIB_PATH", "FP64", "FP32C",
+           "empty_result", "yscan_plan", "cut_curve", "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "version", "load", "GFError", "EXPORTS", "LIB_PATH", "FP64", "FP32C",
            "CONFIGS", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]

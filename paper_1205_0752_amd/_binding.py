@@ -29,6 +29,7 @@ CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
            "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
+           "gf_yscan_plan", "gf_cut_curve",
            "gf_server_create", "gf_server_submit", "gf_server_poll", "gf_server_wait",
            "gf_server_wait_any", "gf_server_result", "gf_server_copy_result",
            "gf_server_release", "gf_server_stats_get", "gf_server_destroy")
@@ -101,6 +102,10 @@ def load():
         lib.gf_plan_auto_lanes.argtypes = [vp, ctypes.POINTER(_Grid)]
         lib.gf_last_error.restype = ctypes.c_char_p
         lib.gf_version.restype = ctypes.c_char_p
+        lib.gf_yscan_plan.argtypes = [vp, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(_Grid), ctypes.c_int, vp, vp]
+        lib.gf_cut_curve.argtypes = [ctypes.POINTER(_Params), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.gf_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
         lib.gf_server_submit.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
@@ -211,6 +216,33 @@ def scan_plan(plan: Plan, grid: Grid, out=None, cls=None, lanes: int = 0, stream
     return out
 
 
+YSCAN_ANGULAR, YSCAN_INTEGRAND = 0, 1
+
+
+def yscan_plan(plan: Plan, x: complex, ygrid: Grid, what: int = YSCAN_ANGULAR, out=None,
+               stream=None):
+    """y-plane diagnostic (gf_yscan_plan): <1/D1>(x, y) or the subtracted
+    y-integrand on a grid of complex y; complex128 [n_im, n_re] on the device."""
+    if out is None:
+        out = empty_result(ygrid)
+    x = complex(x)
+    _check(load().gf_yscan_plan(plan.handle, x.real, x.imag, ctypes.byref(c_grid(ygrid)), int(what),
+                                ctypes.c_void_p(out.data_ptr() if ygrid.n_points else 0),
+                                _stream_handle(stream)))
+    return out
+
+
+def cut_curve(params: Params, x: complex, n: int = 513):
+    """Both branches of the y-plane cut of eq. 25 at n angles in [0, pi]
+    (gf_cut_curve): returns (y_plus, y_minus) as numpy complex arrays."""
+    import numpy as np
+    out = np.zeros(4 * n)
+    x = complex(x)
+    _check(load().gf_cut_curve(ctypes.byref(c_params(params)), x.real, x.imag, int(n),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out[0::4] + 1j * out[1::4], out[2::4] + 1j * out[3::4]
+
+
 def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
     """One-call scan (gf_scan): plan looked up in the library's cache."""
     if out is None:
@@ -305,6 +337,7 @@ def version() -> str:
     return load().gf_version().decode()
 
 
-__all__ = ["Plan", "Server", "scan", "scan_plan", "cache_clear", "version", "load", "GFError",
+__all__ = ["Plan", "Server", "scan", "scan_plan", "yscan_plan", "cut_curve", "cache_clear",
+           "version", "load", "GFError",
            "EXPORTS",
            "FP64", "FP32C", "LIB_PATH", "empty_result"]

@@ -448,6 +448,60 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
     return gf_scan_plan_ex(plan, grid, out, cls_out, 0, stream);
 }
 
+int gf_yscan_plan(const gf_plan_t *plan, double x_re, double x_im, const gf_grid *ygrid, int what,
+                  void *out, void *stream)
+{
+    if (!plan) return fail(GF_EINVAL, "plan must not be NULL");
+    if (what != GF_YSCAN_ANGULAR && what != GF_YSCAN_INTEGRAND)
+        return fail(GF_EINVAL, "what must be GF_YSCAN_ANGULAR or GF_YSCAN_INTEGRAND");
+    if (!std::isfinite(x_re) || !std::isfinite(x_im)) return fail(GF_EINVAL, "x must be finite");
+    if (!ygrid) return fail(GF_EINVAL, "grid must not be NULL");
+    if (ygrid->n_re < 0 || ygrid->n_im < 0 ||
+        (long long)ygrid->n_re * (long long)ygrid->n_im > (1LL << 31))
+        return fail(GF_EINVAL, "grid sizes must be >= 0 with at most 2^31 points");
+    const double v[] = {ygrid->re_lo, ygrid->re_hi, ygrid->im_lo, ygrid->im_hi};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(GF_EINVAL, "grid bounds must be finite");
+    if (!(ygrid->re_lo < ygrid->re_hi) || !(ygrid->im_lo < ygrid->im_hi))
+        return fail(GF_EINVAL, "grid bounds must satisfy lo < hi");
+    if ((long long)ygrid->n_re * ygrid->n_im == 0) return GF_OK;
+    if (!out) return fail(GF_EINVAL, "out must not be NULL");
+    int dev, rc;
+    if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
+    if (dev != plan->device)
+        return fail(GF_EINVAL, "plan was built on device %d, current device is %d", plan->device,
+                    dev);
+    gf::ScanArgs a = plan->base;
+    if ((rc = gf::set_grid(a, *ygrid, 1)) != GF_OK) return rc;
+    a.out = static_cast<double *>(out);
+    a.cls = nullptr;
+    hipError_t e = gf::launch_yscan(a, x_re, x_im, plan->params.mu2, what,
+                                    static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "y-plane kernel launch");
+    return GF_OK;
+}
+
+int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, double *out)
+{
+    // eq. 25: the first propagator x + y + m1^2 - 2 sqrt(x) sqrt(y) cos t vanishes
+    // at sqrt(y) = sqrt(x) cos t +- sqrt(x cos^2 t - x - m1^2), t in [0, pi]
+    if (!params || !out || n < 2) return fail(GF_EINVAL, "need params, out and n >= 2");
+    const std::complex<double> x(x_re, x_im), m1(params->m1sq_re, params->m1sq_im);
+    const std::complex<double> sx = std::sqrt(x);
+    for (int k = 0; k < n; ++k) {
+        const double t = M_PI * k / (n - 1);
+        const double c = std::cos(t);
+        const std::complex<double> root = std::sqrt(x * (c * c - 1.0) - m1);
+        const std::complex<double> p = sx * c + root, m = sx * c - root;
+        const std::complex<double> yp = p * p, ym = m * m;
+        out[4 * k] = yp.real();
+        out[4 * k + 1] = yp.imag();
+        out[4 * k + 2] = ym.real();
+        out[4 * k + 3] = ym.imag();
+    }
+    return GF_OK;
+}
+
 int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad, void *out,
             void *stream)
 {

@@ -68,6 +68,11 @@ struct WorkItem {
 // lanes per point.
 hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t s);
 
+// y-plane diagnostic over a grid of y (fields of `a` set as for a one-lane
+// scan): <1/D1>(x, y) (what = 0) or the subtracted y-integrand (what = 1).
+hipError_t launch_yscan(const ScanArgs &a, double xr, double xi, double mu2, int what,
+                        hipStream_t s);
+
 // Computes the unscaled real-axis sum at x = mu^2 (FP64) into dst[0..1].
 hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s);
 

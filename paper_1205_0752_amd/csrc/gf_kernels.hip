@@ -523,6 +523,32 @@ __global__ void __launch_bounds__(64) jmu_batch_kernel(const ScanArgs *__restric
     jmu_wave(a, mu2[i], const_cast<double *>(a.jmu), threadIdx.x);
 }
 
+// y-plane diagnostic (the paper's Fig. 1): at fixed x, the angular average
+// <1/D1>(x, y) over a cell-centred grid of complex y (what = 0), or the
+// subtracted y-integrand y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)) of eq. 14
+// (what = 1).  One lane per y point, 8 x 8 tiles, FP64.
+__global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, double xi, double mu2,
+                                                    int what)
+{
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int ia = (wave % a.tiles_a) * 8 + lane % 8;
+    const int ib = (wave / a.tiles_a) * 8 + lane / 8;
+    if (ia >= a.n_re || ib >= a.n_im) return;
+    const cd y = mk(fma((double)ia + 0.5, a.d_re, a.re_lo), fma((double)ib + 0.5, a.d_im, a.im_lo));
+    const cd x = mk(xr, xi);
+    const cd m1 = mk(a.m1_re, a.m1_im);
+    cd A = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(cadd(x, y), m1), cmul(mk(4.0 * xr, 4.0 * xi), y));
+    if (what == 1) {
+        const cd Amu = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(mk(mu2 + y.r, y.i), m1),
+                                     cscale(y, 4.0 * mu2));
+        A = cdiv(cmul(y, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
+    }
+    const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
+    reinterpret_cast<double2 *>(a.out)[idx] = make_double2(A.r, A.i);
+}
+
 template <int L>
 hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
@@ -569,6 +595,15 @@ hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t 
     case 64: return launch_l<64>(a, precision, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_yscan(const ScanArgs &a, double xr, double xi, double mu2, int what,
+                        hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(yscan_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a, xr, xi, mu2,
+                       what);
+    return hipGetLastError();
 }
 
 hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s)
