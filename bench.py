@@ -30,6 +30,28 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
 FLOPS_PER_EVAL = 6.5
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_kernel_fp64_bench_workload_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1205_0752_amd", "csrc", "gf_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
+    when there is none for this kernel or the kernel source has changed since
+    the counters were taken (the summary records the source's sha256)."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("kernels_source_sha256") != sha:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def evals_per_scan(cls, quad) -> int:
     """Integrand evaluations (angular terms) one scan performs, from its class
     map: R points n_r nodes, Y points n_r + n_arc, YRES and MIRROR points
@@ -44,22 +66,22 @@ def evals_per_scan(cls, quad) -> int:
 
 
 def cpu_baseline(params, quad, grid, seconds: float):
-    """The CPU oracle timed on a bounded random sample of the same grid."""
-    import numpy as np
+    """The CPU oracle timed on a bounded random sample of the same grid: a
+    calibration sample sets the size of a second sample meant to take about
+    `seconds`, which is the one reported."""
     import oracle
     from paper_1205_0752_amd.workloads import sample_points
     oracle.build()
-    idx = sample_points(grid, 64, seed=7)
-    x = oracle.grid_points_at(grid, idx)
-    t = time.perf_counter()
-    _, c = oracle.eval_points(params, quad, x)
-    dt = time.perf_counter() - t
-    n = int(min(grid.n_points, max(64, len(idx) * seconds / max(dt, 1e-3))))
-    idx = sample_points(grid, n, seed=8)
-    x = oracle.grid_points_at(grid, idx)
-    t = time.perf_counter()
-    _, c = oracle.eval_points(params, quad, x)
-    dt = time.perf_counter() - t
+    n = 4096
+    for attempt in range(3):
+        idx = sample_points(grid, min(n, grid.n_points), seed=7 + attempt)
+        x = oracle.grid_points_at(grid, idx)
+        t = time.perf_counter()
+        _, c = oracle.eval_points(params, quad, x)
+        dt = time.perf_counter() - t
+        if dt >= 0.5 * seconds or len(idx) == grid.n_points or attempt == 2:
+            break
+        n = int(min(grid.n_points, len(idx) * seconds / max(dt, 1e-3)))
     ev = evals_per_scan(c, quad)
     return {"value": ev / dt, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{len(idx)} random points of the same grid ({ev:.3e} evals, {dt:.1f} s)",
@@ -96,6 +118,54 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
             "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}>"}
+
+
+def time_launches(torch, fn, reps):
+    """Average duration of `fn()` (launches on torch's current stream), by HIP
+    events over `reps` back-to-back calls after one warm-up call."""
+    fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extensions(gf, torch):
+    """The diagnostics and the alternative angular rule at bench-sized inputs:
+    y-plane scan (1024^2 y points at x = 2 + 1.5i, 128 angular nodes, the
+    subtracted integrand: two angular sums per point), the obstruction map
+    (1024^2 x points of the bench box, 4096 samples per contour part) and the
+    bench scan with the tanh-sinh angular rule (129 nodes)."""
+    from paper_1205_0752_amd.workloads import CONFIGS, Grid, Quadrature
+    p, g, q = CONFIGS["c1_fp64_1024sq"]
+    out = {}
+    plan = gf.Plan(p, q)
+    yg = Grid(1024, 1024, -8.0, 8.0, -8.0, 8.0)
+    buf = gf.empty_result(yg)
+    ms = time_launches(torch, lambda: gf.yscan_plan(plan, 2.0 + 1.5j, yg, gf.YSCAN_INTEGRAND, buf), 10)
+    plan.close()
+    ev = yg.n_points * 2 * q.n_angular
+    out["yscan"] = {"workload": "1024x1024 y grid over [-8,8]^2, x = 2+1.5i, 128 angular nodes, "
+                                "subtracted integrand", "ms": ms, "evals_per_s": ev / (ms / 1e3),
+                    "tflops": ev * FLOPS_PER_EVAL / (ms / 1e3) / 1e12,
+                    "kernel": "yscan_kernel"}
+    ob = torch.empty((g.n_im, g.n_re), dtype=torch.uint8, device="cuda")
+    ms = time_launches(torch, lambda: gf.obstruction_map(p, g, 4096, ob), 3)
+    out["obstruction_map"] = {"workload": "bench box, 1024x1024 points, 4096 samples per part",
+                              "ms": ms, "points_per_s": g.n_points / (ms / 1e3),
+                              "kernel": "obstruction_kernel"}
+    qt = Quadrature(q.n_radial, 129, q.n_arc, gf.FP64, gf.TANH_SINH)
+    t = time_scan(gf, torch, p, g, qt, 5, 1, 0)
+    out["tanh_sinh_scan"] = {"workload": "bench box and radial/arc nodes, 129 tanh-sinh angular nodes",
+                             "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
+                             "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS}
+    return out
 
 
 def fp32c_errors(gf, torch, params, grid, quad):
@@ -182,8 +252,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32c", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=10000)
-    ap.add_argument("--serve-rate", type=float, default=400.0, help="Poisson arrivals per second")
+    ap.add_argument("--skip-extensions", action="store_true",
+                    help="skip the y-plane scan, obstruction map and tanh-sinh measurements")
+    ap.add_argument("--serve-requests", type=int, default=6000)
+    ap.add_argument("--serve-rate", type=float, default=340.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-budget", type=int, default=1 << 30, help="device bytes")
     ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
@@ -240,7 +312,9 @@ def main() -> int:
                      "unit": "TFLOP/s",
                      "frac": t["tflops"] / (FP64_PEAK_TFLOPS if quad.precision == 0
                                             else FP32_PEAK_TFLOPS),
-                     "traffic": None, "kernel": t["kernel"], "flops_per_eval": FLOPS_PER_EVAL},
+                     "traffic": (measured_traffic(t["kernel"])
+                                 if args.config == "c1_fp64_1024sq" else None),
+                     "kernel": t["kernel"], "flops_per_eval": FLOPS_PER_EVAL},
     }
     if not args.skip_fp32c and args.config == "c1_fp64_1024sq":
         p2, g2, q2 = CONFIGS["c2_fp32c_1024sq"]
@@ -252,6 +326,8 @@ def main() -> int:
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
                            "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS,
                            "error_vs_fp64": fp32c_errors(gf, torch, p2, g2, q2)}
+    if not args.skip_extensions and args.config == "c1_fp64_1024sq":
+        result["extensions"] = extensions(gf, torch)
     if not args.skip_serving and args.config == "c1_fp64_1024sq":
         result["serving"] = serve_trace(gf, args.serve_requests, args.serve_rate,
                                         args.serve_budget)

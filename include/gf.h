@@ -62,6 +62,21 @@ extern "C" {
                             coefficients, radial sum, mu^2 subtraction and
                             scaling in FP64 */
 
+/* ---- angular quadrature rule for <f> = (2/pi) int_{-1}^{1} sqrt(1-z^2) f(z) dz
+ * (the z integral of eq. 11; the paper uses tanh-sinh as its main rule and the
+ * two Gauss-Chebyshev rules as checks, section "Numerical Implementation").
+ * Every rule is symmetric in z, so the kernels sum node pairs (z, -z). */
+#define GF_ANG_GC2 0        /* Gauss-Chebyshev, second kind: z_j = cos(j pi/(n+1)),
+                               w_j = 2 sin^2(j pi/(n+1))/(n+1), j = 1..n; exact for
+                               polynomial f of degree <= 2n-1 */
+#define GF_ANG_GC1 1        /* Gauss-Chebyshev, first kind, on f(z) (1 - z^2):
+                               z_j = cos((2j-1) pi/(2n)), w_j = (2/n) sin^2((2j-1) pi/(2n));
+                               exact for degree <= 2n-3 */
+#define GF_ANG_TANH_SINH 2  /* double exponential: z = tanh((pi/2) sinh t) on the
+                               equispaced t_k = (k - (n-1)/2) h, h = 6/(n-1) (t in
+                               [-3, 3]), w_k = h cosh t_k / cosh^3((pi/2) sinh t_k);
+                               n >= 3, weights not renormalised */
+
 /* ---- contour classes (values of the optional class map) ---------------- */
 #define GF_CLASS_R 0         /* real axis [0, Lambda^2] */
 #define GF_CLASS_Y 1         /* ray at arg x + arc |y| = Lambda^2 */
@@ -82,13 +97,15 @@ typedef struct {
 } gf_params;
 
 /* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
- * n_angular Gauss-Chebyshev-II nodes (1..8192), n_arc Gauss-Legendre nodes on
- * the closing arc (0..1024; 0 drops the arc), precision GF_PREC_*. */
+ * n_angular angular nodes (1..8192; >= 3 for tanh-sinh) of the rule
+ * angular_rule (GF_ANG_*), n_arc Gauss-Legendre nodes on the closing arc
+ * (0..1024; 0 drops the arc), precision GF_PREC_*. */
 typedef struct {
     int32_t n_radial;
     int32_t n_angular;
     int32_t n_arc;
     int32_t precision;
+    int32_t angular_rule;
 } gf_quadrature;
 
 /* Cell-centred n_re x n_im box (STEP 4): point (a, b), 0 <= a < n_re,
@@ -174,11 +191,30 @@ int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
 int gf_yscan_plan(const gf_plan_t *plan, double x_re, double x_im, const gf_grid *ygrid, int what,
                   void *out, void *stream);
 
-/* The continuum cut of eq. 25 for the build's first propagator: the y where
+/* The continuum cut of eq. 25 for the first propagator: the y where
  * x + y + m1^2 - 2 sqrt(x) sqrt(y) cos(t) = 0, both roots, for n angles
  * t = pi k/(n-1), k = 0..n-1 (n >= 2).  out: 4n doubles per k as
  * (re y+, im y+, re y-, im y-).  Host only.  Errors: GF_EINVAL. */
 int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, double *out);
+
+/* Obstruction map (the paper's Fig. 2 and the figure that follows it): for
+ * every point x of a cell-centred grid, whether the angular cut -- the y
+ * where x + y + m1^2 - 2 sqrt(x) sqrt(y) z = 0 for some z in [-1, 1], i.e.
+ * where zeta = (x + y + m1^2)^2 / (4xy) is real and in [0, 1] -- crosses
+ *   bit 0: the original contour, the real segment [0, Lambda^2];
+ *   bit 1: the contour the scan uses at x (the contour class rule; for a
+ *          mirror point, the contour of conj x);
+ *   bit 2: x has no contour (class SINGULAR; bit 1 is then 0).
+ * A crossing is detected between consecutive samples of the contour (each
+ * straight part at t = log(1+|y|) = T k/(n-1), k = 1..n-1, T = log(1 +
+ * Lambda^2); the closing arc at n equally spaced angles) where Im zeta changes
+ * sign and the linearly interpolated Re zeta lies in [0, 1].  Points with
+ * bit 0 clear form the region where the real-axis contour is unharmed.  out:
+ * caller-owned device memory, n_re * n_im bytes [n_im][n_re]; asynchronous on
+ * `stream`.  n_samples in [2, 2^20].  Errors: GF_EINVAL (also for the grid
+ * checks of gf_scan_plan), GF_EDEVICE. */
+int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_samples, uint8_t *out,
+                       void *stream);
 
 /* ---- serving: continuous batching of scan requests ----------------------
  *

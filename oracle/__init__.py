@@ -32,7 +32,7 @@ class _Problem(ctypes.Structure):
                 ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("scale", ctypes.c_double),
                 ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
-                ("n_arc", ctypes.c_int)]
+                ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int)]
 
 
 def build(verbose: bool = False) -> None:
@@ -62,6 +62,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_gauss_cheb2.argtypes = [ctypes.c_int, dp, dp]
+        lib.orc_angular_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         lib.orc_angular_sum.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, dp, dp]
         lib.orc_eval_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                         ctypes.c_int, dp, ctypes.c_char_p, dp]
@@ -75,6 +76,8 @@ def _load():
         lib.orc_evals_for_class.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int]
         lib.orc_evals_for_class.restype = ctypes.c_long
         lib.orc_threads.restype = ctypes.c_int
+        lib.orc_obstruction.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                        ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p]
         lib.orc_yscan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_long, dp, dp, ctypes.c_int, dp]
         _lib = lib
@@ -103,7 +106,8 @@ def problem(params, quad) -> _Problem:
     m1, m2 = complex(params.m1sq), complex(params.m2sq)
     return _Problem(m1.real, m1.imag, m2.real, m2.imag, float(params.mu2),
                     float(params.lambda2), float(params.scale),
-                    int(quad.n_radial), int(quad.n_angular), int(quad.n_arc))
+                    int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
+                    int(getattr(quad, "angular_rule", 0)))
 
 
 # ---------------------------------------------------------------- rules
@@ -119,6 +123,16 @@ def gauss_cheb2(n: int):
     z = np.zeros(n)
     w = np.zeros(n)
     _load().orc_gauss_cheb2(n, _dp(z), _dp(w))
+    return z, w
+
+
+def angular_rule(rule: int, n: int):
+    """Nodes and weights of angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh)
+    for the measure (2/pi) sqrt(1-z^2) dz."""
+    z = np.zeros(n)
+    w = np.zeros(n)
+    if _load().orc_angular_rule(int(rule), int(n), _dp(z), _dp(w)) != 0:
+        raise ValueError(f"angular rule {rule} with {n} nodes is not defined")
     return z, w
 
 
@@ -204,7 +218,10 @@ def scan(params, quad, grid, want_cond: bool = False):
 
 
 def eval_points_q(params, quad, x):
-    """Quad-precision brute force of the same quadrature.  Returns (g, cls)."""
+    """Quad-precision brute force of the same quadrature (Gauss-Chebyshev II
+    angular rule only).  Returns (g, cls)."""
+    if getattr(quad, "angular_rule", 0) != 0:
+        raise ValueError("the quad-precision twin implements the GC-II angular rule only")
     lib = _loadq()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
     xr = np.ascontiguousarray(x.real)
@@ -227,6 +244,24 @@ def yscan(params, quad, x: complex, y, what: int = 0) -> np.ndarray:
     _load().orc_yscan(ctypes.byref(pr), complex(x).real, complex(x).imag, y.size, _dp(yr), _dp(yi),
                       int(what), _dp(out))
     return out[0::2] + 1j * out[1::2]
+
+
+def obstruction(params, x, n_samples: int = 4096):
+    """Per point: bit 0 the angular cut crosses the real segment [0, Lambda^2],
+    bit 1 it crosses the contour of the class rule, bit 2 no contour; and a
+    flag where a decision sits within rounding of its threshold."""
+    from types import SimpleNamespace
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    out = ctypes.create_string_buffer(max(x.size, 1))
+    tie = ctypes.create_string_buffer(max(x.size, 1))
+    pr = problem(params, SimpleNamespace(n_radial=1, n_angular=1, n_arc=0))
+    if _load().orc_obstruction(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), int(n_samples), out,
+                               tie) != 0:
+        raise ValueError("n_samples must be >= 2")
+    return (np.frombuffer(out.raw[:x.size], dtype=np.uint8).copy(),
+            np.frombuffer(tie.raw[:x.size], dtype=np.uint8).astype(bool))
 
 
 def threads() -> int:

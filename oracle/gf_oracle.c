@@ -22,8 +22,12 @@
  *
  * Quadrature (section "Numerical Implementation"): non-adaptive Gauss rules.
  *   radial : n_radial-point Gauss-Legendre in t = log(1+y) on [0, log(1+Lambda^2)]
- *   angular: n_angular-point Gauss-Chebyshev of the second kind,
- *            z_j = cos(j pi/(n+1)), w_j = (2/(n+1)) sin^2(j pi/(n+1)), sum w_j = 1
+ *   angular: n_angular points of one of three rules for the measure
+ *            (2/pi) sqrt(1-z^2) dz, chosen by angular_rule:
+ *            0 Gauss-Chebyshev, second kind (default): z_j = cos(j pi/(n+1)),
+ *              w_j = (2/(n+1)) sin^2(j pi/(n+1)), sum w_j = 1
+ *            1 Gauss-Chebyshev, first kind, applied to f(z) (1 - z^2)
+ *            2 tanh-sinh (double exponential), the paper's main angular rule
  *   arc    : n_arc-point Gauss-Legendre in the angle
  *
  * Contour per x (STEP 3; the paper's per-region contours of its worked example
@@ -66,6 +70,7 @@ typedef struct {
     double lambda2;            /* cutoff Lambda^2 of eq. 14 */
     double scale;              /* 1 = eq. 18 units, 1/(16 pi^2) = eq. 17 units */
     int n_radial, n_angular, n_arc;
+    int angular_rule;          /* 0 GC-II, 1 GC-I, 2 tanh-sinh */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -124,6 +129,54 @@ int orc_gauss_cheb2(int n, double *z, double *w)
         w[j - 1] = 2.0 / (n + 1) * s * s;
     }
     return 0;
+}
+
+/* Gauss-Chebyshev of the first kind: int_{-1}^{1} g(z) / sqrt(1-z^2) dz ~
+ * (pi/n) sum_j g(z_j), z_j = cos((2j-1) pi/(2n)).  Our measure is
+ * (2/pi) sqrt(1-z^2) dz = (2/pi)(1-z^2) dz / sqrt(1-z^2), so g = (2/pi)(1-z^2) f
+ * and the weight of f(z_j) is (pi/n)(2/pi)(1-z_j^2). */
+int orc_gauss_cheb1(int n, double *z, double *w)
+{
+    if (n <= 0) return -1;
+    for (int j = 1; j <= n; ++j) {
+        double zj = cos((2 * j - 1) * M_PI / (2.0 * n));
+        z[j - 1] = zj;
+        w[j - 1] = (M_PI / n) * (2.0 / M_PI) * (1.0 - zj * zj);
+    }
+    return 0;
+}
+
+/* Tanh-sinh (Takahasi-Mori double exponential) rule: substitute
+ * z = tanh((pi/2) sinh t), so dz = (pi/2) cosh t / cosh^2((pi/2) sinh t) dt, and
+ * apply the trapezoidal rule with step h on n equispaced t centred on 0,
+ * t_k = (k - (n-1)/2) h.  The paper fixes only the node count (49 in well
+ * behaved regions); reading: h = 6/(n-1), i.e. t in [-3, 3], where the
+ * transformed measure has decayed far below double precision.  The weight of
+ * f(z_k) is h dz/dt (2/pi) sqrt(1 - z_k^2); weights are not renormalised. */
+int orc_tanh_sinh(int n, double *z, double *w)
+{
+    if (n < 3) return -1;
+    double h = 6.0 / (n - 1);
+    for (int k = 0; k < n; ++k) {
+        double t = (k - 0.5 * (n - 1)) * h;
+        double u = 0.5 * M_PI * sinh(t);
+        double zk = tanh(u);
+        double dzdt = 0.5 * M_PI * cosh(t) / (cosh(u) * cosh(u));
+        z[k] = zk;
+        w[k] = h * dzdt * (2.0 / M_PI) * sqrt(fmax(0.0, 1.0 - zk * zk));
+    }
+    return 0;
+}
+
+/* Nodes and weights of the angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh). */
+int orc_angular_rule(int rule, int n, double *z, double *w)
+{
+    switch (rule) {
+    case 0: return orc_gauss_cheb2(n, z, w);
+    case 1: return orc_gauss_cheb1(n, z, w);
+    case 2: return orc_tanh_sinh(n, z, w);
+    default: return -1;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -361,6 +414,8 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
     return cls;
 }
 
+static void orc_ctx_free(orc_ctx *c);
+
 static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
 {
     memset(c, 0, sizeof(*c));
@@ -378,7 +433,10 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     c->w = malloc(sizeof(double) * na);
     orc_gauss_legendre(nr, c->gl_t, c->gl_w);
     if (p->n_arc > 0) orc_gauss_legendre(p->n_arc, c->arc_x, c->arc_w);
-    orc_gauss_cheb2(na, c->z, c->w);
+    if (orc_angular_rule(p->angular_rule, na, c->z, c->w) != 0) {
+        orc_ctx_free(c);
+        return -1;
+    }
     /* t = log(1+y) on [0, T], T = log(1 + Lambda^2): y = e^t - 1, dy = (1+y) dt */
     double T = log1p(p->lambda2);
     for (int i = 0; i < nr; ++i) {
@@ -506,7 +564,11 @@ int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const doub
 {
     if (p->n_angular <= 0) return -1;
     double *z = malloc(sizeof(double) * p->n_angular), *w = malloc(sizeof(double) * p->n_angular);
-    orc_gauss_cheb2(p->n_angular, z, w);
+    if (orc_angular_rule(p->angular_rule, p->n_angular, z, w) != 0) {
+        free(z);
+        free(w);
+        return -1;
+    }
     cplx x = x_re + I * x_im, m1sq = p->m1sq_re + I * p->m1sq_im, m2sq = p->m2sq_re + I * p->m2sq_im;
     cplx sx = csqrt(x), smu = sqrt(p->mu2);
 #pragma omp parallel for schedule(static)
@@ -523,5 +585,122 @@ int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const doub
     }
     free(z);
     free(w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Obstruction of a contour by the angular cut (the paper's Fig. 2)          */
+/* ------------------------------------------------------------------------ */
+
+/* The first propagator x + y + m1^2 - 2 sqrt(x) sqrt(y) z has a zero in z on
+ * [-1, 1] exactly when z0 = (x + y + m1^2) / (2 sqrt(x) sqrt(y)) is real with
+ * |z0| <= 1, i.e. when zeta = z0^2 = (x + y + m1^2)^2 / (4 x y) is real and in
+ * [0, 1].  A contour part is sampled at parameter values u_k; where Im zeta is
+ * positive at one sample and not at the next, the zero of Im zeta between them
+ * is located by 40 bisection steps on u, and the cut crosses the contour if
+ * Re zeta there is in [0, 1].  *tie is raised when that value lies within 1e-9
+ * of 0 or 1, or a sample has |Im zeta| <= 1e-13 |zeta|: there, another
+ * rounding of the same steps may decide the other way. */
+typedef struct {
+    cplx x, m1sq;
+    int arc;          /* 0: y = (e^u - 1) dir; 1: y = Lambda^2 e^{iu} */
+    cplx dir;
+    double lambda2;
+} orc_cut_part;
+
+static cplx orc_zeta(const orc_cut_part *c, double u)
+{
+    cplx y = c->arc ? c->lambda2 * cexp(I * u) : expm1(u) * c->dir;
+    cplx num = (c->x + y + c->m1sq) * (c->x + y + c->m1sq);
+    return num / (4.0 * c->x * y);
+}
+
+/* Walks the samples u[0..n-1] of one part; returns 1 if the cut crosses it. */
+static int orc_cut_walk(const orc_cut_part *c, const double *u, int n, int *tie)
+{
+    int hit = 0;
+    cplx prev = 0.0;
+    for (int k = 0; k < n; ++k) {
+        cplx zeta = orc_zeta(c, u[k]);
+        if (fabs(cimag(zeta)) <= 1e-13 * cabs(zeta)) *tie = 1;
+        if (k > 0 && (cimag(prev) > 0.0) != (cimag(zeta) > 0.0)) {
+            double a = u[k - 1], b = u[k];
+            int a_pos = cimag(prev) > 0.0;
+            for (int it = 0; it < 40; ++it) {
+                double m = 0.5 * (a + b);
+                if ((cimag(orc_zeta(c, m)) > 0.0) == a_pos) a = m;
+                else b = m;
+            }
+            double re = creal(orc_zeta(c, 0.5 * (a + b)));
+            if (re >= 0.0 && re <= 1.0) hit = 1;
+            if (fabs(re) < 1e-9 || fabs(re - 1.0) < 1e-9) *tie = 1;
+        }
+        prev = zeta;
+    }
+    return hit;
+}
+
+/* The real segment: u = T k/(n-1), k = 1..n-1, T = log(1 + Lambda^2). */
+static int orc_cut_real(const orc_problem *p, cplx x, int n, int *tie)
+{
+    orc_cut_part c = {x, p->m1sq_re + I * p->m1sq_im, 0, 1.0, p->lambda2};
+    double T = log1p(p->lambda2);
+    double *u = malloc(sizeof(double) * n);
+    for (int k = 1; k < n; ++k) u[k - 1] = T * k / (n - 1);
+    int hit = orc_cut_walk(&c, u, n - 1, tie);
+    free(u);
+    return hit;
+}
+
+/* The ray at phi = arg x (same u), then the arc from phi back to 0 at
+ * u = phi (1 - k/(n-1)), k = 0..n-1. */
+static int orc_cut_ray_arc(const orc_problem *p, cplx x, int n, int *tie)
+{
+    double phi = carg(x), T = log1p(p->lambda2);
+    orc_cut_part ray = {x, p->m1sq_re + I * p->m1sq_im, 0, cexp(I * phi), p->lambda2};
+    orc_cut_part arc = ray;
+    arc.arc = 1;
+    double *u = malloc(sizeof(double) * n);
+    for (int k = 1; k < n; ++k) u[k - 1] = T * k / (n - 1);
+    int hit = orc_cut_walk(&ray, u, n - 1, tie);
+    for (int k = 0; k < n; ++k) u[k] = phi * (1.0 - (double)k / (n - 1));
+    hit |= orc_cut_walk(&arc, u, n, tie);
+    free(u);
+    return hit;
+}
+
+/* Per point: bit 0 the real segment [0, Lambda^2] is crossed; bit 1 the
+ * contour of the class rule is crossed (for a mirror point, the contour of
+ * conj x); bit 2 no contour (SINGULAR).  tie[k] = 1 where a decision sits
+ * within rounding of its threshold. */
+int orc_obstruction(const orc_problem *p, long n, const double *x_re, const double *x_im,
+                    int n_samples, unsigned char *out, unsigned char *tie)
+{
+    if (n_samples < 2) return -1;
+    orc_geometry g;
+    orc_make_geometry(p, &g);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long k = 0; k < n; ++k) {
+        cplx x = x_re[k] + I * x_im[k];
+        int t = 0, s;
+        int v = orc_cut_real(p, x, n_samples, &t);
+        int cls = orc_classify(&g, x, &s);
+        cplx xe = x;
+        int ecls = cls;
+        if (cls == ORC_MIRROR) {
+            xe = conj(x);
+            ecls = orc_classify(&g, xe, &s);
+            if (ecls == ORC_MIRROR || ecls == ORC_SINGULAR) cls = ORC_SINGULAR;
+        }
+        if (cls == ORC_SINGULAR) {
+            v |= 4;
+        } else {
+            int used = ecls == ORC_R ? orc_cut_real(p, xe, n_samples, &t)
+                                     : orc_cut_ray_arc(p, xe, n_samples, &t);
+            if (used) v |= 2;
+        }
+        out[k] = (unsigned char)v;
+        tie[k] = (unsigned char)t;
+    }
     return 0;
 }

@@ -21,6 +21,7 @@ typedef struct {
     double m1sq_re, m1sq_im, m2sq_re, m2sq_im;
     double mu2, lambda2, scale;
     int n_radial, n_angular, n_arc;
+    int angular_rule;   /* only 0 (Gauss-Chebyshev II) is implemented here */
 } orcq_problem;   /* same layout as the FP64 oracle's problem struct */
 
 #define QPI M_PIq

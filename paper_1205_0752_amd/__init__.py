@@ -9,11 +9,15 @@ The library is loaded on first use; importing this package does not touch the
 GPU.
 """
 from ._binding import (CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
-                       REQ_DONE, REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError,
-                       LIB_PATH, Plan, Server, cache_clear, cut_curve, yscan_plan, empty_result, load, scan, scan_plan,
-                       version)
-from .workloads import CONFIGS, FP32C, FP64, Grid, Params, Quadrature
+                       LIB_PATH, NO_CONTOUR, OBSTRUCTED_CONTOUR, OBSTRUCTED_REAL_AXIS, REQ_DONE,
+                       REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError, Plan,
+                       Server, cache_clear, cut_curve, empty_result, load, obstruction_map, scan,
+                       scan_plan, version, yscan_plan)
+from .workloads import CONFIGS, FP32C, FP64, GC1, GC2, TANH_SINH, Grid, Params, Quadrature
 
 __all__ = ["Params", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_plan", "cache_clear",
-           "empty_result", "yscan_plan", "cut_curve", "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "version", "load", "GFError", "EXPORTS", "LIB_PATH", "FP64", "FP32C",
-           "CONFIGS", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]
+           "empty_result", "yscan_plan", "cut_curve", "obstruction_map", "version", "load", "GFError", "EXPORTS",
+           "LIB_PATH", "FP64", "FP32C", "GC2", "GC1", "TANH_SINH", "CONFIGS",
+           "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "OBSTRUCTED_REAL_AXIS", "OBSTRUCTED_CONTOUR",
+           "NO_CONTOUR", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
+           "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]

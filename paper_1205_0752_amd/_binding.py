@@ -29,7 +29,7 @@ CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
            "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
-           "gf_yscan_plan", "gf_cut_curve",
+           "gf_yscan_plan", "gf_cut_curve", "gf_obstruction_map",
            "gf_server_create", "gf_server_submit", "gf_server_poll", "gf_server_wait",
            "gf_server_wait_any", "gf_server_result", "gf_server_copy_result",
            "gf_server_release", "gf_server_stats_get", "gf_server_destroy")
@@ -52,7 +52,8 @@ class _Params(ctypes.Structure):
 
 class _Quad(ctypes.Structure):
     _fields_ = [("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32),
-                ("n_arc", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("n_arc", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("angular_rule", ctypes.c_int32)]
 
 
 class _Grid(ctypes.Structure):
@@ -106,6 +107,8 @@ def load():
                                       ctypes.POINTER(_Grid), ctypes.c_int, vp, vp]
         lib.gf_cut_curve.argtypes = [ctypes.POINTER(_Params), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        lib.gf_obstruction_map.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
+                                           ctypes.c_int, vp, vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
         lib.gf_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
         lib.gf_server_submit.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
@@ -136,7 +139,8 @@ def c_params(p: Params) -> _Params:
 
 
 def c_quad(q: Quadrature) -> _Quad:
-    return _Quad(int(q.n_radial), int(q.n_angular), int(q.n_arc), int(q.precision))
+    return _Quad(int(q.n_radial), int(q.n_angular), int(q.n_arc), int(q.precision),
+                 int(q.angular_rule))
 
 
 def c_grid(g: Grid) -> _Grid:
@@ -243,6 +247,23 @@ def cut_curve(params: Params, x: complex, n: int = 513):
     return out[0::4] + 1j * out[1::4], out[2::4] + 1j * out[3::4]
 
 
+OBSTRUCTED_REAL_AXIS, OBSTRUCTED_CONTOUR, NO_CONTOUR = 1, 2, 4
+
+
+def obstruction_map(params: Params, grid: Grid, n_samples: int = 4096, out=None, stream=None):
+    """Per grid point, bit 0: the angular cut crosses the real segment
+    [0, Lambda^2]; bit 1: it crosses the contour the scan uses; bit 2: no
+    contour (gf_obstruction_map).  uint8 [n_im, n_re] on the device."""
+    import torch
+    if out is None:
+        out = torch.empty((grid.n_im, grid.n_re), dtype=torch.uint8, device="cuda")
+    _check(load().gf_obstruction_map(ctypes.byref(c_params(params)), ctypes.byref(c_grid(grid)),
+                                     int(n_samples),
+                                     ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
+                                     _stream_handle(stream)))
+    return out
+
+
 def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
     """One-call scan (gf_scan): plan looked up in the library's cache."""
     if out is None:
@@ -337,7 +358,8 @@ def version() -> str:
     return load().gf_version().decode()
 
 
-__all__ = ["Plan", "Server", "scan", "scan_plan", "yscan_plan", "cut_curve", "cache_clear",
+__all__ = ["Plan", "Server", "scan", "scan_plan", "yscan_plan", "cut_curve", "obstruction_map",
+           "cache_clear",
            "version", "load", "GFError",
            "EXPORTS",
            "FP64", "FP32C", "LIB_PATH", "empty_result"]

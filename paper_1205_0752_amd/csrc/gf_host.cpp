@@ -133,23 +133,47 @@ void radial_table(int nr, double lambda2, std::vector<double> &rad)
     }
 }
 
-void angular_tables(int na, std::vector<double> &ang, std::vector<float> &ang32, double *wmid)
+void angular_tables(int na, int rule, std::vector<double> &ang, std::vector<float> &ang32,
+                    double *wmid)
 {
-    // Gauss-Chebyshev of the second kind, weights summing to 1, stored folded
-    // over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j), z_j = cos(j pi/(n+1)),
-    // j = 1..n/2; the middle node of an odd rule is z = 0 with weight 2/(n+1)
+    // Stored folded over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j), j
+    // running over the positive nodes; an odd rule's middle node z = 0 keeps
+    // its weight apart.  Weights follow the normalised measure
+    // (2/pi) sqrt(1 - z^2) dz, so sum_j w_j = 1 for the Gauss rules.
     const int npair = na / 2;
     ang.assign(2 * (size_t)std::max(npair, 1), 0.0);
     ang32.assign(2 * (size_t)std::max(npair, 1), 0.0f);
-    for (int j = 1; j <= npair; ++j) {
-        double th = j * M_PI / (na + 1);
-        double s = std::sin(th), c = std::cos(th);
-        ang[2 * (j - 1)] = c * c;
-        ang[2 * (j - 1) + 1] = 4.0 * s * s / (na + 1);
-        ang32[2 * (j - 1)] = (float)ang[2 * (j - 1)];
-        ang32[2 * (j - 1) + 1] = (float)ang[2 * (j - 1) + 1];
+    *wmid = 0.0;
+    auto put = [&](int j, double zsq, double w) {
+        ang[2 * j] = zsq;
+        ang[2 * j + 1] = 2.0 * w;
+    };
+    if (rule == GF_ANG_GC2) {
+        for (int j = 1; j <= npair; ++j) {
+            const double th = j * M_PI / (na + 1);
+            const double s = std::sin(th), c = std::cos(th);
+            put(j - 1, c * c, 2.0 * s * s / (na + 1));
+        }
+        if (na % 2 == 1) *wmid = 2.0 / (na + 1);
+    } else if (rule == GF_ANG_GC1) {
+        for (int j = 1; j <= npair; ++j) {
+            const double th = (2 * j - 1) * M_PI / (2.0 * na);
+            const double s = std::sin(th), c = std::cos(th);
+            put(j - 1, c * c, 2.0 * s * s / na);
+        }
+        if (na % 2 == 1) *wmid = 2.0 / na;
+    } else {
+        // t_k = (k - (n-1)/2) h; the positive half is t = (m + (n odd ? 1 : 1/2)) h
+        const double h = 6.0 / (na - 1);
+        for (int j = 0; j < npair; ++j) {
+            const double t = (na % 2 == 1) ? (j + 1) * h : (j + 0.5) * h;
+            const double u = M_PI_2 * std::sinh(t);
+            const double z = std::tanh(u), cu = std::cosh(u);
+            put(j, z * z, h * std::cosh(t) / (cu * cu * cu));
+        }
+        if (na % 2 == 1) *wmid = h;
     }
-    *wmid = (na % 2 == 1) ? 2.0 / (na + 1) : 0.0;
+    for (size_t i = 0; i < ang.size(); ++i) ang32[i] = (float)ang[i];
 }
 
 void arc_table(int nc, std::vector<double> &arc)
@@ -204,6 +228,11 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
         return fail(GF_EINVAL, "n_arc must be in [0, 1024], got %d", q->n_arc);
     if (q->precision != GF_PREC_FP64 && q->precision != GF_PREC_FP32C)
         return fail(GF_EINVAL, "precision must be GF_PREC_FP64 or GF_PREC_FP32C");
+    if (q->angular_rule != GF_ANG_GC2 && q->angular_rule != GF_ANG_GC1 &&
+        q->angular_rule != GF_ANG_TANH_SINH)
+        return fail(GF_EINVAL, "angular_rule must be GF_ANG_GC2, GF_ANG_GC1 or GF_ANG_TANH_SINH");
+    if (q->angular_rule == GF_ANG_TANH_SINH && q->n_angular < 3)
+        return fail(GF_EINVAL, "the tanh-sinh rule needs n_angular >= 3, got %d", q->n_angular);
     const double vals[] = {p->m1sq_re, p->m1sq_im, p->m2sq_re, p->m2sq_im,
                            p->mu2,     p->lambda2, p->scale};
     for (double v : vals)
@@ -321,7 +350,7 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     std::vector<float> ang32;
     double wmid = 0.0;
     gf::radial_table(quad->n_radial, params->lambda2, rad);
-    gf::angular_tables(quad->n_angular, ang, ang32, &wmid);
+    gf::angular_tables(quad->n_angular, quad->angular_rule, ang, ang32, &wmid);
     gf::arc_table(quad->n_arc, arc);
 
     const size_t off_rad = 0;
@@ -499,6 +528,26 @@ int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, doubl
         out[4 * k + 2] = ym.real();
         out[4 * k + 3] = ym.imag();
     }
+    return GF_OK;
+}
+
+int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_samples, uint8_t *out,
+                       void *stream)
+{
+    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2};
+    int rc = gf::validate_params(params, &q1);
+    if (rc != GF_OK) return rc;
+    if ((rc = gf::validate_grid(*params, grid)) != GF_OK) return rc;
+    if (n_samples < 2 || n_samples > (1 << 20))
+        return fail(GF_EINVAL, "n_samples must be in [2, 2^20], got %d", n_samples);
+    if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
+    if (!out) return fail(GF_EINVAL, "out must not be NULL");
+    gf::ScanArgs a{};
+    gf::fill_constants(a, *params, q1);
+    if ((rc = gf::set_grid(a, *grid, 1)) != GF_OK) return rc;
+    hipError_t e = gf::launch_obstruction(a, n_samples, std::log1p(params->lambda2), out,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "obstruction-map kernel launch");
     return GF_OK;
 }
 

@@ -72,6 +72,7 @@ hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t 
 // scan): <1/D1>(x, y) (what = 0) or the subtracted y-integrand (what = 1).
 hipError_t launch_yscan(const ScanArgs &a, double xr, double xi, double mu2, int what,
                         hipStream_t s);
+hipError_t launch_obstruction(const ScanArgs &a, int n, double T, uint8_t *out, hipStream_t s);
 
 // Computes the unscaled real-axis sum at x = mu^2 (FP64) into dst[0..1].
 hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s);
@@ -96,7 +97,8 @@ const char *last_error();
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 // radial table [r | sqrt r | W], angular pair tables, arc table [xi | w]
 void radial_table(int n_r, double lambda2, std::vector<double> &rad);
-void angular_tables(int n_a, std::vector<double> &ang, std::vector<float> &ang32, double *wmid);
+void angular_tables(int n_a, int rule, std::vector<double> &ang, std::vector<float> &ang32,
+                    double *wmid);
 void arc_table(int n_arc, std::vector<double> &arc);
 // masses, cutoff, scale and contour geometry of a (params, quadrature)
 void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q);

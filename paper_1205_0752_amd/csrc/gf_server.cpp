@@ -199,7 +199,10 @@ std::string key_radial(const gf_quadrature &q, const gf_params &p)
     k.append(reinterpret_cast<const char *>(&p.lambda2), sizeof(double));
     return k;
 }
-std::string key_angular(const gf_quadrature &q) { return "a" + std::to_string(q.n_angular); }
+std::string key_angular(const gf_quadrature &q)
+{
+    return "a" + std::to_string(q.n_angular) + ":" + std::to_string(q.angular_rule);
+}
 std::string key_arc(const gf_quadrature &q) { return "c" + std::to_string(q.n_arc); }
 
 double nominal_evals_per_point(const gf_quadrature &q)
@@ -235,7 +238,7 @@ Table *gf_server::ensure_table(const std::string &key, const Request &r, bool *f
     } else if (key[0] == 'a') {
         std::vector<double> ang;
         std::vector<float> ang32;
-        gf::angular_tables(r.q.n_angular, ang, ang32, &t.wmid);
+        gf::angular_tables(r.q.n_angular, r.q.angular_rule, ang, ang32, &t.wmid);
         const size_t b64 = gf::align256(ang.size() * sizeof(double));
         t.host.assign(b64 + ang32.size() * sizeof(float), 0);
         std::memcpy(t.host.data(), ang.data(), ang.size() * sizeof(double));

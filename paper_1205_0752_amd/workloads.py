@@ -18,6 +18,10 @@ import numpy as np
 # precision codes of the quadrature record
 FP64 = 0
 FP32C = 1
+#: angular rules (GF_ANG_*)
+GC2 = 0
+GC1 = 1
+TANH_SINH = 2
 
 
 @dataclasses.dataclass(frozen=True)
@@ -51,13 +55,15 @@ class Grid:
 
 @dataclasses.dataclass(frozen=True)
 class Quadrature:
-    """Node counts: Gauss-Legendre radial nodes in t = log(1+y), Gauss-Chebyshev
-    (second kind) angular nodes, Gauss-Legendre arc nodes; precision FP64 or
-    FP32C (FP32 bulk, FP64 at the sensitive steps)."""
+    """Node counts: Gauss-Legendre radial nodes in t = log(1+y), angular nodes
+    of the rule `angular_rule` (GC2: Gauss-Chebyshev second kind, the default;
+    GC1: first kind; TANH_SINH: double exponential), Gauss-Legendre arc nodes;
+    precision FP64 or FP32C (FP32 bulk, FP64 at the sensitive steps)."""
     n_radial: int = 64
     n_angular: int = 32
     n_arc: int = 16
     precision: int = FP64
+    angular_rule: int = 0
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,156 @@
+"""Obstruction map (the paper's Fig. 2): where the angular cut crosses the
+original real-axis contour, and whether it crosses the contour the scan uses.
+
+CPU pins of the oracle's map: the real-axis bit against the closed-form
+region |Im sqrt(x)| >= Re sqrt(m1^2) (for real m1 the paper's parabola),
+against an independent brute-force walk along the eq. 25 cut curve, and the
+class rule never choosing a crossed contour.  GPU: the kernel against the
+oracle bit for bit (away from rounding ties) and, at the bench box size, the
+same closed-form properties."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_0752_amd.workloads import Grid, Params, Quadrature
+
+MASSES = [Params(1.0, 1.0, 1.0, 1e6), Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6),
+          Params(-0.5j, 0.5j, 0.0, 1e6), Params(2.0, 0.7, 1.5, 1e6)]
+IDS = ["real", "conj", "paper", "unequal"]
+
+
+def _closed_form_obstructed(p, x):
+    """|Im sqrt x| >= Re sqrt(m1^2): the real segment meets the angular cut
+    (as Lambda^2 -> infinity)."""
+    return np.abs(np.sqrt(x).imag) >= np.sqrt(complex(p.m1sq)).real
+
+
+def _near_boundary(p, x, rel=2e-3):
+    vs = np.sqrt(complex(p.m1sq)).real
+    return np.abs(np.abs(np.sqrt(x).imag) / vs - 1.0) < rel
+
+
+@pytest.mark.parametrize("p", MASSES, ids=IDS)
+def test_real_axis_bit_matches_closed_form_region(p):
+    grid = Grid(96, 80, -12.0, 6.0, -6.0, 6.0)
+    x = oracle.grid_points(grid)
+    o, tie = oracle.obstruction(p, x, 4096)
+    want = _closed_form_obstructed(p, x)
+    got = (o & 1) > 0
+    bad = (got != want) & ~_near_boundary(p, x)
+    assert not bad.any(), x[bad][:5]
+    assert 0.2 < want.mean() < 0.95  # both kinds of points are present
+
+
+def test_real_masses_region_is_the_parabola():
+    """For real m1 the unobstructed region is Re x > (Im x)^2/(4 m1^2) - m1^2."""
+    p = Params(1.5, 1.0, 1.0, 1e6)
+    grid = Grid(64, 64, -8.0, 4.0, -4.0, 4.0)
+    x = oracle.grid_points(grid)
+    o, _ = oracle.obstruction(p, x, 4096)
+    parabola = x.real > x.imag ** 2 / (4 * 1.5) - 1.5
+    margin = np.abs(x.real - (x.imag ** 2 / 6.0 - 1.5)) > 0.01
+    assert np.array_equal(((o & 1) == 0)[margin], parabola[margin])
+
+
+def _brute_force_cut_meets_real_segment(x, m1sq, lam2, nz=20001):
+    """Walks the eq. 25 curve: for z on a fine grid of [-1, 1] the two roots
+    s = sqrt(x) z +- sqrt(x z^2 - x - m1^2) of the first propagator's zero in
+    s = sqrt(y), with the inner square root continued along z (no branch
+    jumps); y = s^2 meets the real segment [0, Lambda^2] where Im y changes sign
+    along a branch with 0 <= Re y <= Lambda^2 there."""
+    z = np.linspace(-1.0, 1.0, nz)
+    sx = np.sqrt(x)
+    root = np.sqrt(x * z * z - x - m1sq)
+    flip = np.abs(root[1:] - root[:-1]) > np.abs(root[1:] + root[:-1])
+    root = root * np.concatenate([[1.0], np.cumprod(np.where(flip, -1.0, 1.0))])
+    for y in ((sx * z + root) ** 2, (sx * z - root) ** 2):
+        im = y.imag
+        ch = np.nonzero((im[:-1] > 0) != (im[1:] > 0))[0]
+        for k in ch:
+            f = im[k] / (im[k] - im[k + 1])
+            re = y.real[k] + f * (y.real[k + 1] - y.real[k])
+            if 0 <= re <= lam2:
+                return True
+    return False
+
+
+@pytest.mark.parametrize("p", MASSES, ids=IDS)
+def test_real_axis_bit_matches_brute_force_cut_walk(p):
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-12, 6, 300) + 1j * rng.uniform(-6, 6, 300)
+    x = x[~_near_boundary(p, x, 2e-2)]
+    o, _ = oracle.obstruction(p, x, 4096)
+    bf = np.array([_brute_force_cut_meets_real_segment(xx, complex(p.m1sq), p.lambda2) for xx in x])
+    assert np.array_equal((o & 1) > 0, bf), x[((o & 1) > 0) != bf][:5]
+
+
+@pytest.mark.parametrize("p", MASSES, ids=IDS)
+def test_class_rule_contours_are_never_crossed(p):
+    """Bit 1 (the contour the class rule picks) is never set; real-axis points
+    are exactly the unobstructed ones the rule prefers."""
+    grid = Grid(96, 80, -12.0, 6.0, -6.0, 6.0)
+    x = oracle.grid_points(grid)
+    o, _ = oracle.obstruction(p, x, 4096)
+    cls = oracle.classify(p, Quadrature(), x)
+    assert not np.any(o & 2)
+    assert np.array_equal((o & 4) > 0, cls == oracle.SINGULAR)
+    assert not np.any((o[cls == oracle.R] & 1) > 0)
+
+
+def test_a_crossed_contour_is_detected():
+    """Forcing the real axis where the cut crosses it: every such point whose
+    crossing lies inside [0, Lambda^2] is reported on bit 0 (the detector fires,
+    so bit 1 being clear above is informative)."""
+    p = Params(1.0, 1.0, 1.0, 1e2)
+    x = np.array([-3.0 + 3.0j, -5.0 - 1.0j, 0.5 + 4.0j])
+    o, _ = oracle.obstruction(p, x, 2048)
+    assert np.all(o & 1)
+    # the crossing sits at y = |x| - m1^2; past the cutoff nothing is crossed
+    far = np.array([-200.0 + 30.0j])
+    o, _ = oracle.obstruction(p, far, 2048)
+    assert not (o[0] & 1)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", MASSES, ids=IDS)
+def test_gpu_obstruction_matches_oracle(p):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1205_0752_amd as gf
+    for grid, n in ((Grid(133, 97, -12.0, 6.0, -6.0, 6.0), 2048), (Grid(64, 64, -8.0, 4.0, -4.0, 4.0), 4096)):
+        got = gf.obstruction_map(p, grid, n)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().ravel()
+        want, tie = oracle.obstruction(p, oracle.grid_points(grid), n)
+        diff = (got != want) & ~tie
+        assert not diff.any(), (grid, np.nonzero(diff)[0][:5], got[diff][:5], want[diff][:5])
+        assert (got != want).sum() <= max(2, got.size // 1000)
+
+
+@pytest.mark.gpu
+def test_gpu_obstruction_full_box_properties():
+    """1024^2 bench box, 4096 samples per contour part: bit 0 equals the
+    closed-form region away from its boundary, bit 1 is never set, bit 2 marks
+    exactly the singular points of the scan's own class map."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1205_0752_amd as gf
+
+    p = Params(1.0, 1.0, 1.0, 1e6)
+    grid = Grid(1024, 1024, -16.0, 8.0, -8.0, 8.0)
+    o = gf.obstruction_map(p, grid, 4096).cpu().numpy().ravel()
+    plan = gf.Plan(p, Quadrature(16, 8, 4))
+    cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
+    gf.scan_plan(plan, grid, cls=cls)
+    torch.cuda.synchronize()
+    plan.close()
+    cls = cls.cpu().numpy().ravel()
+    x = oracle.grid_points(grid)
+    want = _closed_form_obstructed(p, x)
+    bad = (((o & 1) > 0) != want) & ~_near_boundary(p, x)
+    assert not bad.any()
+    assert not np.any(o & 2)
+    assert np.array_equal((o & 4) > 0, cls == gf.CLASS_SINGULAR)
+    assert not np.any((o[cls == gf.CLASS_R] & 1) > 0)
