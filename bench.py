@@ -31,20 +31,29 @@ FLOPS_PER_EVAL = 6.5
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_kernel_fp64_bench_workload_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1205_0752_amd", "csrc", "gf_kernels.hip")
+# the sources that define the scan kernels' machine code
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1205_0752_amd", "csrc", name)
+                  for name in ("gf_internal.h", "gf_device.h", "gf_kernels.hip")]
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
-    when there is none for this kernel or the kernel source has changed since
-    the counters were taken (the summary records the source's sha256)."""
-    import hashlib
+    when there is none for this kernel or the kernel sources have changed since
+    the counters were taken (the summary records their sha256)."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_source_sha256()
     except (OSError, ValueError):
         return None
     if rec.get("kernel") != kernel or rec.get("kernels_source_sha256") != sha:

@@ -1,0 +1,360 @@
+// Device-side building blocks shared by the gfx950 kernels: complex FP64
+// arithmetic, the hardware reciprocal with one Newton step, reads through the
+// constant address space, the contour-class rule, per-point set-up and
+// per-node coefficients, and the folded angular sums in FP64 and FP32C.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "gf_internal.h"
+
+namespace gf {
+namespace {
+
+struct cd {
+    double r, i;
+};
+
+__device__ __forceinline__ cd mk(double r, double i)
+{
+    cd z;
+    z.r = r;
+    z.i = i;
+    return z;
+}
+__device__ __forceinline__ cd cadd(cd a, cd b) { return mk(a.r + b.r, a.i + b.i); }
+__device__ __forceinline__ cd cmul(cd a, cd b)
+{
+    return mk(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
+}
+__device__ __forceinline__ cd cscale(cd a, double s) { return mk(a.r * s, a.i * s); }
+__device__ __forceinline__ double rcp64(double q)
+{
+    // hardware reciprocal estimate (24 bits on gfx950) + one Newton-Raphson step
+    double r = __builtin_amdgcn_rcp(q);
+    return fma(fma(-q, r, 1.0), r, r);
+}
+// a / b = a conj(b) / |b|^2 with the refined reciprocal
+__device__ __forceinline__ cd cdiv(cd a, cd b)
+{
+    double inv = rcp64(b.r * b.r + b.i * b.i);
+    return mk((a.r * b.r + a.i * b.i) * inv, (a.i * b.r - a.r * b.i) * inv);
+}
+
+// Plan tables and argument tables are read-only while a kernel runs.  Reading
+// them through the constant address space tells the compiler so: wave-uniform
+// reads then become scalar loads into SGPR operands even in the serving
+// kernel, whose stores of earlier work items would otherwise count as
+// possible clobbers.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *ro(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)(uintptr_t)p;
+}
+
+// principal square root; follows the sign of a zero imaginary part
+__device__ cd csqrt_principal(double a, double b)
+{
+    if (a == 0.0 && b == 0.0) return mk(0.0, b);
+    double r = hypot(a, b);
+    if (a >= 0.0) {
+        double t = sqrt(0.5 * (r + a));
+        return mk(t, b / (2.0 * t));
+    }
+    double t = sqrt(0.5 * (r - a));
+    return mk(fabs(b) / (2.0 * t), copysign(t, b));
+}
+
+__device__ __forceinline__ double angle_between(double a, double b)
+{
+    double d = fabs(a - b);
+    return d > M_PI ? 2.0 * M_PI - d : d;
+}
+
+// Contour class of x (STEP 3).  Rotating the ray from angle 0 to phi = arg x
+// is free inside (lo, hi); sweeping across the k-leg pole ray arg(-m2^2) adds
+// its residue (sign of phi); across the ray arg(-m1^2) the conjugate point is
+// used instead.  The real axis is preferred where it is valid (|Im sqrt x| <
+// v*) and either comfortably inside (v < kRNear v*) or closer to its own edge
+// than the ray is to a bad ray.
+template <class Args>
+__device__ int classify(const Args &a, double xr, double xi, int *res_sign)
+{
+    cd sx = csqrt_principal(xr, xi);
+    double v = fabs(sx.i);
+    double phi = atan2(xi, xr);
+    int rot;
+    *res_sign = 0;
+    if (phi > a.lo && phi < a.hi) {
+        rot = kY;
+    } else {
+        bool past1, past2;
+        if (phi > 0.0) {
+            past1 = a.beta1 > 0.0 && a.beta1 < phi;
+            past2 = a.beta2 > 0.0 && a.beta2 < phi;
+        } else {
+            past1 = a.beta1 <= 0.0 && a.beta1 > phi;
+            past2 = a.beta2 <= 0.0 && a.beta2 > phi;
+        }
+        bool on_bad = angle_between(phi, a.beta1) == 0.0 || angle_between(phi, a.beta2) == 0.0;
+        if (on_bad) {
+            rot = kSingular;
+        } else if (past2 && !past1) {
+            rot = kYRes;
+            *res_sign = phi > 0.0 ? 1 : -1;
+        } else if (past1 && !past2 && a.mirror_ok) {
+            rot = kMirror;
+        } else {
+            rot = kSingular;
+        }
+    }
+    if (v < a.vstar) {
+        double delta = fmin(angle_between(phi, a.beta1), angle_between(phi, a.beta2));
+        if (v < kRNear * a.vstar || 1.0 - v / a.vstar >= kRSlope * delta || rot == kSingular) {
+            *res_sign = 0;
+            return kR;
+        }
+    }
+    return rot;
+}
+
+// Per-point quantities hoisted out of the node loop.  V^2 = 4 x y for every
+// node whatever the branches of sqrt(x) sqrt(y), and the angular sum depends
+// on V only through V^2 (symmetric rule), so no square root of y is needed.
+struct PointCtx {
+    cd x1;   // x + m1^2
+    cd dir;  // e^{i phi} (ray) or 1 (real axis)
+    double phi;
+    int nodes;  // contour nodes of this point
+    int res_sign;
+};
+
+template <class Args>
+__device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign)
+{
+    PointCtx P;
+    P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
+    P.res_sign = res_sign;
+    if (cls == kY || cls == kYRes) {
+        double phi = atan2(xi, xr);
+        double s, c;
+        sincos(phi, &s, &c);
+        P.dir = mk(c, s);
+        P.phi = phi;
+        P.nodes = a.n_r + a.n_arc + (cls == kYRes ? 1 : 0);
+    } else {
+        P.dir = mk(1.0, 0.0);
+        P.phi = 0.0;
+        P.nodes = cls == kR ? a.n_r : 0;
+    }
+    return P;
+}
+
+// Coefficients of contour node k -- radial (ray or real axis), closing arc,
+// or residue of the k-leg pole: U = x + y + m1^2, V^2 = 4 x y and the node's
+// weight omega (dy-weight times y / (y + m2^2), or +-2 pi i y0).
+template <class Args>
+__device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
+                                            cd &V2, cd &w)
+{
+    const cd m2 = mk(a.m2_re, a.m2_im);
+    // 4 x, recovered from x + m1^2 (recomputing it per node keeps fewer
+    // registers live across the node loop than carrying it)
+    const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
+    if (k < a.n_r) {
+        const auto *rad = ro(a.rad);
+        const double r = rad[k];
+        const double wr = rad[2 * a.n_r + k];
+        const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
+        U = cadd(P.x1, y);
+        V2 = cmul(x4, y);                                      // 4 x y
+        w = cdiv(cscale(cmul(P.dir, P.dir), wr * r), cadd(y, m2));  // e^{i phi} dr y/(y + m2^2)
+    } else if (k < a.n_r + a.n_arc) {
+        const int q = k - a.n_r;
+        const auto *arc = ro(a.arc);
+        const double xi = arc[q];
+        const double wa = arc[a.n_arc + q];
+        const double psi = 0.5 * P.phi * (1.0 - xi);     // from phi back to 0
+        double s, c;
+        sincos(psi, &s, &c);
+        const cd y = mk(a.lam2 * c, a.lam2 * s);
+        U = cadd(P.x1, y);
+        V2 = cmul(x4, y);
+        const double h = 0.5 * P.phi * wa;
+        const cd dy = mk(y.i * h, -y.r * h);              // dy = -i y (phi/2) dxi
+        w = cdiv(cmul(dy, y), cadd(y, m2));
+    } else {
+        const cd y0 = mk(-a.m2_re, -a.m2_im);
+        U = cadd(P.x1, y0);
+        V2 = cmul(x4, y0);
+        const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i Res
+        w = mk(-y0.i * f, y0.r * f);
+    }
+}
+
+// Angular sum A = sum_j w_j / (U - V z_j) over the GC-II rule.  The rule is
+// symmetric (z_{n+1-j} = -z_j, equal weights), so each node pair is folded:
+//   w/(U - V z) + w/(U + V z) = 2 w U / (U^2 - V^2 z^2),
+// one complex denominator per two integrand evaluations; the middle node of an
+// odd rule (z = 0) adds w/U.  U^2 and V^2 are scaled by an exact power of two
+// 2^-e (e = exponent of their largest component), which changes no rounding
+// and keeps every |D|^2 near 1, so four denominators can share one reciprocal
+// (1/q0 = q1 q2 q3 / (q0 q1 q2 q3)) without overflow.  Table: (z^2, 2w) per
+// pair, FP64.
+__device__ __forceinline__ int scale_exponent(cd U2, cd V2)
+{
+    const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
+    int e = 0;
+    frexp(big, &e);
+    return e;
+}
+
+__device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
+                                            cd V2in)
+{
+    const auto *tab = ro(table);
+    const cd U2in = cmul(U, U);
+    const int e = scale_exponent(U2in, V2in);
+    const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
+    const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
+    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+    int p = 0;
+    for (; p + 4 <= npair; p += 4) {
+        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        const double zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
+        const double zz2 = tab[2 * p + 4], ww2 = tab[2 * p + 5];
+        const double zz3 = tab[2 * p + 6], ww3 = tab[2 * p + 7];
+        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
+        const double dr1 = fma(-v2r, zz1, u2r), di1 = fma(-v2i, zz1, u2i);
+        const double dr2 = fma(-v2r, zz2, u2r), di2 = fma(-v2i, zz2, u2i);
+        const double dr3 = fma(-v2r, zz3, u2r), di3 = fma(-v2i, zz3, u2i);
+        const double q0 = fma(dr0, dr0, di0 * di0);
+        const double q1 = fma(dr1, dr1, di1 * di1);
+        const double q2 = fma(dr2, dr2, di2 * di2);
+        const double q3 = fma(dr3, dr3, di3 * di3);
+        const double p01 = q0 * q1, p23 = q2 * q3;
+        const double inv = rcp64(p01 * p23);
+        const double i01 = p23 * inv, i23 = p01 * inv;
+        const double t0 = ww0 * (q1 * i01);
+        const double t1 = ww1 * (q0 * i01);
+        const double t2 = ww2 * (q3 * i23);
+        const double t3 = ww3 * (q2 * i23);
+        ar0 = fma(t0, dr0, ar0);
+        ai0 = fma(t0, di0, ai0);
+        ar1 = fma(t1, dr1, ar1);
+        ai1 = fma(t1, di1, ai1);
+        ar0 = fma(t2, dr2, ar0);
+        ai0 = fma(t2, di2, ai0);
+        ar1 = fma(t3, dr3, ar1);
+        ai1 = fma(t3, di3, ai1);
+    }
+    for (; p < npair; ++p) {
+        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
+        const double t0 = ww0 * rcp64(fma(dr0, dr0, di0 * di0));
+        ar0 = fma(t0, dr0, ar0);
+        ai0 = fma(t0, di0, ai0);
+    }
+    // sum 2w / D = sum 2w conj(D) / |D|^2 (scaled by 2^e), then times U
+    cd A = cmul(U, mk(ldexp(ar0 + ar1, -e), -ldexp(ai0 + ai1, -e)));
+    if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    return A;
+}
+
+// Knuth's two-sum: s + e == a + b exactly (round-to-nearest, no contraction).
+__device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
+{
+    const float s = hi + b;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (b - bb);
+    hi = s;
+    lo += e;
+}
+
+// FP32 angular sum with compensated accumulation.  U^2 and V^2 are formed in
+// FP64 and scaled by an exact power of two 2^-e (e = exponent of their largest
+// component) before rounding to FP32, so every FP32 denominator is O(1) and the
+// shared-reciprocal product q0 q1 stays in range.  Terms are summed in FP32
+// blocks of kBlock pairs; block sums enter a (hi, lo) two-sum accumulator; the
+// node's sum leaves in FP64 as U 2^-e (hi + lo).
+constexpr int kBlock = 16;
+
+__device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
+                                             cd V2)
+{
+    const auto *tab = ro(table);
+    const cd U2 = cmul(U, U);
+    const int e = scale_exponent(U2, V2);
+    const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
+    const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
+    float hr = 0.0f, lr = 0.0f, hi = 0.0f, li = 0.0f;
+    int p = 0;
+    while (p < npair) {
+        const int pe = min(p + kBlock, npair);
+        float br0 = 0.0f, bi0 = 0.0f, br1 = 0.0f, bi1 = 0.0f;
+        for (; p + 2 <= pe; p += 2) {
+            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+            const float zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
+            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
+            const float dr1 = fmaf(-v2r, zz1, u2r), di1 = fmaf(-v2i, zz1, u2i);
+            const float q0 = fmaf(dr0, dr0, di0 * di0);
+            const float q1 = fmaf(dr1, dr1, di1 * di1);
+            const float inv = __builtin_amdgcn_rcpf(q0 * q1);
+            const float t0 = ww0 * (q1 * inv);
+            const float t1 = ww1 * (q0 * inv);
+            br0 = fmaf(t0, dr0, br0);
+            bi0 = fmaf(t0, di0, bi0);
+            br1 = fmaf(t1, dr1, br1);
+            bi1 = fmaf(t1, di1, bi1);
+        }
+        if (p < pe) {
+            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
+            const float t0 = ww0 * __builtin_amdgcn_rcpf(fmaf(dr0, dr0, di0 * di0));
+            br0 = fmaf(t0, dr0, br0);
+            bi0 = fmaf(t0, di0, bi0);
+            ++p;
+        }
+        two_sum(hr, lr, br0 + br1);
+        two_sum(hi, li, bi0 + bi1);
+    }
+    const double sr = ldexp((double)hr + (double)lr, -e);
+    const double si = ldexp((double)hi + (double)li, -e);
+    cd A = cmul(U, mk(sr, -si));
+    if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    return A;
+}
+
+// FP32C keeps a node's angular sum in FP64 when the node lies close to the
+// angular cut.  The folded denominators are U^2 - V^2 s with s = z^2 in (0, 1);
+// rounding U^2, V^2 and s to FP32 perturbs them by ~eps32 (|U^2| + |V^2|),
+// relative to their smallest size, the distance d from U^2 to the segment
+// [0, V^2].  Nodes with (|U^2| + |V^2|) > kFp32Sensitivity d (tested in
+// squares, in FP64) take the FP64 sum.  The test depends on the node alone, so
+// results stay reproducible.
+constexpr double kFp32Sensitivity = 16.0;
+
+__device__ __forceinline__ bool near_angular_cut(cd U, cd V2)
+{
+    const cd U2 = cmul(U, U);
+    const double vv = V2.r * V2.r + V2.i * V2.i;
+    const double uu = U2.r * U2.r + U2.i * U2.i;
+    if (vv == 0.0) return false;  // sum is exactly 1/U
+    // closest point of the segment s V^2, s in [0, 1], to U^2
+    double s = (U2.r * V2.r + U2.i * V2.i) / vv;
+    s = fmin(fmax(s, 0.0), 1.0);
+    const double dr = U2.r - s * V2.r, di = U2.i - s * V2.i;
+    const double dd = dr * dr + di * di;
+    return 2.0 * (uu + vv) > kFp32Sensitivity * kFp32Sensitivity * dd;
+}
+
+template <int PREC, class Args>
+__device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
+{
+    if (PREC == 0 || near_angular_cut(U, V2)) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+    return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V2);
+}
+
+}  // namespace
+}  // namespace gf

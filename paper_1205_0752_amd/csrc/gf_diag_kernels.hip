@@ -1,0 +1,174 @@
+// gfx950 diagnostic kernels: the y-plane scan at fixed x (the paper's Fig. 1)
+// and the obstruction map of the original contour (Fig. 2).  Both reuse the
+// device building blocks of the scan kernels.
+#include "gf_device.h"
+
+namespace gf {
+namespace {
+
+// y-plane diagnostic (the paper's Fig. 1): at fixed x, the angular average
+// <1/D1>(x, y) over a cell-centred grid of complex y (what = 0), or the
+// subtracted y-integrand y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)) of eq. 14
+// (what = 1).  One lane per y point, 8 x 8 tiles, FP64.
+__global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, double xi, double mu2,
+                                                    int what)
+{
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int ia = (wave % a.tiles_a) * 8 + lane % 8;
+    const int ib = (wave / a.tiles_a) * 8 + lane / 8;
+    if (ia >= a.n_re || ib >= a.n_im) return;
+    const cd y = mk(fma((double)ia + 0.5, a.d_re, a.re_lo), fma((double)ib + 0.5, a.d_im, a.im_lo));
+    const cd x = mk(xr, xi);
+    const cd m1 = mk(a.m1_re, a.m1_im);
+    cd A = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(cadd(x, y), m1), cmul(mk(4.0 * xr, 4.0 * xi), y));
+    if (what == 1) {
+        const cd Amu = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(mk(mu2 + y.r, y.i), m1),
+                                     cscale(y, 4.0 * mu2));
+        A = cdiv(cmul(y, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
+    }
+    const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
+    reinterpret_cast<double2 *>(a.out)[idx] = make_double2(A.r, A.i);
+}
+
+// Obstruction map (the paper's Fig. 2).  The first propagator
+// x + y + m1^2 - 2 sqrt(x) sqrt(y) z vanishes for some z in [-1, 1] exactly when
+// zeta(y) = (x + y + m1^2)^2 / (4 x y) is real and lies in [0, 1].  Each straight
+// part of a contour is sampled at y = (e^t - 1) dir, the closing arc at
+// y = Lambda^2 e^{i psi}; where Im zeta changes sign between two consecutive
+// samples, 40 bisection steps on the part's parameter locate the zero of
+// Im zeta, and the cut crosses the contour there if Re zeta lies in [0, 1].
+struct CutWalk {
+    cd x1, x4;  // x + m1^2, 4x
+    cd dir;     // direction of a straight part
+    double lam2;
+    bool arc;   // current part: false = straight, true = arc
+    double pu, pi;
+    bool started, hit;
+};
+
+__device__ __forceinline__ cd cut_zeta(const CutWalk &w, double u)
+{
+    cd y;
+    if (w.arc) {
+        double s, c;
+        sincos(u, &s, &c);
+        y = mk(w.lam2 * c, w.lam2 * s);
+    } else {
+        y = cscale(w.dir, expm1(u));
+    }
+    const cd U = cadd(w.x1, y);
+    return cdiv(cmul(U, U), cmul(w.x4, y));
+}
+
+__device__ void cut_step(CutWalk &w, double u)
+{
+    const cd z = cut_zeta(w, u);
+    if (w.started && ((w.pi > 0.0) != (z.i > 0.0))) {
+        double lo = w.pu, hi = u;
+        const bool lo_pos = w.pi > 0.0;
+        for (int it = 0; it < 40; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if ((cut_zeta(w, mid).i > 0.0) == lo_pos)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const cd zc = cut_zeta(w, 0.5 * (lo + hi));
+        if (zc.r >= 0.0 && zc.r <= 1.0) w.hit = true;
+    }
+    w.pu = u;
+    w.pi = z.i;
+    w.started = true;
+}
+
+__device__ CutWalk cut_walk_begin(const ScanArgs &a, double xr, double xi)
+{
+    CutWalk w;
+    w.x1 = mk(xr + a.m1_re, xi + a.m1_im);
+    w.x4 = mk(4.0 * xr, 4.0 * xi);
+    w.dir = mk(1.0, 0.0);
+    w.lam2 = a.lam2;
+    w.arc = false;
+    w.pu = 0.0;
+    w.pi = 0.0;
+    w.started = false;
+    w.hit = false;
+    return w;
+}
+
+// Real segment: t = T k/(n-1), k = 1..n-1, T = log(1 + Lambda^2).
+__device__ bool cut_hits_real_axis(const ScanArgs &a, double xr, double xi, int n, double T)
+{
+    CutWalk w = cut_walk_begin(a, xr, xi);
+    for (int k = 1; k < n; ++k) cut_step(w, T * k / (n - 1));
+    return w.hit;
+}
+
+// Ray at phi = arg x (same t samples), then the arc psi = phi (1 - k/(n-1)),
+// k = 0..n-1, which starts where the ray ends.
+__device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n, double T)
+{
+    CutWalk w = cut_walk_begin(a, xr, xi);
+    const double phi = atan2(xi, xr);
+    double s, c;
+    sincos(phi, &s, &c);
+    w.dir = mk(c, s);
+    for (int k = 1; k < n; ++k) cut_step(w, T * k / (n - 1));
+    w.arc = true;
+    w.started = false;
+    for (int k = 0; k < n; ++k) cut_step(w, phi * (1.0 - (double)k / (n - 1)));
+    return w.hit;
+}
+
+__global__ void __launch_bounds__(256) obstruction_kernel(ScanArgs a, int n, double T, uint8_t *out)
+{
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= a.n_tiles) return;
+    const int lane = threadIdx.x & 63;
+    const int ia = (wave % a.tiles_a) * 8 + lane % 8;
+    const int ib = (wave / a.tiles_a) * 8 + lane / 8;
+    if (ia >= a.n_re || ib >= a.n_im) return;
+    const double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
+    const double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
+    const bool real_hit = cut_hits_real_axis(a, xr, xi, n, T);
+    int sign = 0;
+    int cls = classify(a, xr, xi, &sign);
+    double ei = xi;
+    int ecls = cls;
+    if (cls == kMirror) {  // the scan evaluates the conjugate point
+        ei = -xi;
+        ecls = classify(a, xr, ei, &sign);
+        if (ecls == kMirror || ecls == kSingular) cls = kSingular;
+    }
+    int v = real_hit ? 1 : 0;
+    if (cls == kSingular) {
+        v |= 4;
+    } else {
+        const bool used_hit = ecls == kR ? (ei == xi ? real_hit : cut_hits_real_axis(a, xr, ei, n, T))
+                                         : cut_hits_ray_arc(a, xr, ei, n, T);
+        if (used_hit) v |= 2;
+    }
+    out[(size_t)ib * (size_t)a.n_re + (size_t)ia] = (uint8_t)v;
+}
+
+}  // namespace
+
+hipError_t launch_yscan(const ScanArgs &a, double xr, double xi, double mu2, int what,
+                        hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(yscan_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a, xr, xi, mu2,
+                       what);
+    return hipGetLastError();
+}
+
+hipError_t launch_obstruction(const ScanArgs &a, int n, double T, uint8_t *out, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(obstruction_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a, n, T, out);
+    return hipGetLastError();
+}
+
+}  // namespace gf
