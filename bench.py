@@ -126,7 +126,8 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
     return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
-            "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}>"}
+            "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}, "
+                      f"{'true' if getattr(params, 'taylor_order', 0) > 0 else 'false'}>"}
 
 
 def time_launches(torch, fn, reps):
@@ -150,7 +151,9 @@ def extensions(gf, torch):
     y-plane scan (1024^2 y points at x = 2 + 1.5i, 128 angular nodes, the
     subtracted integrand: two angular sums per point), the obstruction map
     (1024^2 x points of the bench box, 4096 samples per contour part) and the
-    bench scan with the tanh-sinh angular rule (129 nodes)."""
+    bench scan with the tanh-sinh angular rule (129 nodes) and with the Taylor
+    subtraction t^2."""
+    import dataclasses
     from paper_1205_0752_amd.workloads import CONFIGS, Grid, Quadrature
     p, g, q = CONFIGS["c1_fp64_1024sq"]
     out = {}
@@ -174,6 +177,11 @@ def extensions(gf, torch):
     out["tanh_sinh_scan"] = {"workload": "bench box and radial/arc nodes, 129 tanh-sinh angular nodes",
                              "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
                              "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS}
+    t = time_scan(gf, torch, dataclasses.replace(p, taylor_order=2), g, q, 5, 1, 0)
+    out["taylor2_scan"] = {"workload": "bench workload with the subtraction t^2 about mu^2",
+                           "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
+                           "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS,
+                           "kernel": t["kernel"]}
     return out
 
 

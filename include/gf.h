@@ -87,13 +87,23 @@ extern "C" {
 /* Integrand parameters (eq. 14-16).  m1^2 sits on the (p-k) leg, m2^2 on the
  * k leg; neither may lie on the non-positive real axis.  mu2 is the real
  * subtraction point (>= 0), lambda2 the cutoff Lambda^2 (> 0), scale the
- * output multiplier. */
+ * output multiplier.  taylor_order n (0..GF_MAX_TAYLOR) is the order of the
+ * Taylor subtraction operator t^n of eq. 12-13, taken about x = mu2 (eq. 13
+ * expands about x = 0, i.e. mu2 = 0): the result is
+ *   scale * ( S(x) - sum_{i=0}^{n} (x - mu2)^i K_i ),
+ * S the contour sum of <F(x, y, .)>, K_i = (1/i!) d^i/dx^i of the real-axis
+ * sum at x = mu2 (K_0 is the subtraction sum of order 0).  The angular
+ * average is an analytic function of x (V^2 = 4xy enters, not sqrt(x)), so
+ * its derivatives exist at x = 0.  reserved must be 0. */
+#define GF_MAX_TAYLOR 8
 typedef struct {
     double m1sq_re, m1sq_im;
     double m2sq_re, m2sq_im;
     double mu2;
     double lambda2;
     double scale;
+    int32_t taylor_order;
+    int32_t reserved;
 } gf_params;
 
 /* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
@@ -168,9 +178,12 @@ void gf_free(gf_plan_t *plan);
 /* Frees every plan cached by gf_scan.  Same synchronisation rule. */
 void gf_cache_clear(void);
 
-/* Plan introspection: the unscaled subtraction sum at mu^2 and the lanes per
- * point the automatic choice would use for a grid.  Errors: GF_EINVAL. */
+/* Plan introspection: the unscaled subtraction sum at mu^2 (K_0), all
+ * taylor_order + 1 Taylor coefficients K_0..K_n of the subtraction
+ * (coeffs: 2(n+1) doubles, re/im interleaved), and the lanes per point the
+ * automatic choice would use for a grid.  Errors: GF_EINVAL. */
 int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im);
+int gf_plan_taylor(const gf_plan_t *plan, double *coeffs);
 int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
 
 /* ---- y-plane diagnostics (the paper's Fig. 1 and eq. 23-25) -------------

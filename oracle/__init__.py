@@ -32,7 +32,8 @@ class _Problem(ctypes.Structure):
                 ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("scale", ctypes.c_double),
                 ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
-                ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int)]
+                ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int),
+                ("taylor_order", ctypes.c_int)]
 
 
 def build(verbose: bool = False) -> None:
@@ -78,6 +79,8 @@ def _load():
         lib.orc_threads.restype = ctypes.c_int
         lib.orc_obstruction.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                         ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p]
+        lib.orc_taylor.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, dp,
+                                   ctypes.POINTER(ctypes.c_double)]
         lib.orc_yscan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_long, dp, dp, ctypes.c_int, dp]
         _lib = lib
@@ -107,7 +110,8 @@ def problem(params, quad) -> _Problem:
     return _Problem(m1.real, m1.imag, m2.real, m2.imag, float(params.mu2),
                     float(params.lambda2), float(params.scale),
                     int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
-                    int(getattr(quad, "angular_rule", 0)))
+                    int(getattr(quad, "angular_rule", 0)),
+                    int(getattr(params, "taylor_order", 0)))
 
 
 # ---------------------------------------------------------------- rules
@@ -220,8 +224,8 @@ def scan(params, quad, grid, want_cond: bool = False):
 def eval_points_q(params, quad, x):
     """Quad-precision brute force of the same quadrature (Gauss-Chebyshev II
     angular rule only).  Returns (g, cls)."""
-    if getattr(quad, "angular_rule", 0) != 0:
-        raise ValueError("the quad-precision twin implements the GC-II angular rule only")
+    if getattr(quad, "angular_rule", 0) != 0 or getattr(params, "taylor_order", 0) != 0:
+        raise ValueError("the quad-precision twin implements the GC-II rule and t^0 only")
     lib = _loadq()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
     xr = np.ascontiguousarray(x.real)
@@ -262,6 +266,17 @@ def obstruction(params, x, n_samples: int = 4096):
         raise ValueError("n_samples must be >= 2")
     return (np.frombuffer(out.raw[:x.size], dtype=np.uint8).copy(),
             np.frombuffer(tie.raw[:x.size], dtype=np.uint8).astype(bool))
+
+
+def taylor(params, quad, n: int):
+    """K_0..K_n of the subtraction at mu^2 by the Cauchy formula, and the
+    radius rho of the circle (rounding error of K_i ~ eps max|S| rho^-i)."""
+    out = np.zeros(2 * (n + 1))
+    rho = ctypes.c_double()
+    if _load().orc_taylor(ctypes.byref(problem(params, quad)), int(n), _dp(out),
+                          ctypes.byref(rho)) != 0:
+        raise ValueError("bad problem or order")
+    return out[0::2] + 1j * out[1::2], rho.value
 
 
 def threads() -> int:

@@ -67,6 +67,32 @@ def feynman(x: complex, m1sq: complex, m2sq: complex, mu2: float) -> complex:
     return complex(mp.quad(f, pts))
 
 
+def feynman_taylor(mu2: float, m1sq: complex, m2sq: complex, i: int) -> complex:
+    """(1/i!) d^i G/dx^i at x = mu^2 (i >= 1) of the Feynman form: with
+    b = a(1-a), d/dx log Delta(a, x) = b/Delta, so the coefficient is
+    -((-1)^(i-1)/i) int_0^1 b^i / Delta(a, mu^2)^i da."""
+    m1 = mp.mpc(m1sq)
+    m2 = mp.mpc(m2sq)
+    mu = mp.mpf(mu2)
+
+    def f(a):
+        b = a * (1 - a)
+        return b ** i / delta(a, mu, m1, m2) ** i
+
+    return complex(-((-1) ** (i - 1)) * mp.quad(f, [0, 0.5, 1]) / i)
+
+
+def feynman_subtracted(x: complex, m1sq: complex, m2sq: complex, mu2: float, n: int) -> complex:
+    """G after the Taylor subtraction t^n about mu^2 (eq. 12-13): the Feynman
+    form minus its Taylor polynomial of degree n at mu^2 (whose constant term
+    is G(mu^2) = 0)."""
+    g = feynman(x, m1sq, m2sq, mu2)
+    d = complex(x) - mu2
+    for i in range(1, n + 1):
+        g -= d ** i * feynman_taylor(mu2, m1sq, m2sq, i)
+    return g
+
+
 def feynman_principal_ok(x: complex, m1sq: complex, m2sq: complex, mu2: float,
                          n: int = 4001) -> bool:
     """True when neither Delta(a, x) nor Delta(a, mu^2) crosses the negative real

@@ -71,7 +71,10 @@ typedef struct {
     double scale;              /* 1 = eq. 18 units, 1/(16 pi^2) = eq. 17 units */
     int n_radial, n_angular, n_arc;
     int angular_rule;          /* 0 GC-II, 1 GC-I, 2 tanh-sinh */
+    int taylor_order;          /* n of the subtraction operator t^n (eq. 13), 0..8 */
 } orc_problem;
+
+#define ORC_MAX_TAYLOR 8
 
 /* ------------------------------------------------------------------------ */
 /* Quadrature rules                                                          */
@@ -316,6 +319,8 @@ typedef struct {
     double *r, *wr;          /* radial nodes y = r_i, dy weights (incl. Jacobian) */
     cplx jmu;                /* subtraction term: real-axis sum at x = mu^2 */
     double jmu_abs;
+    cplx taylor[ORC_MAX_TAYLOR + 1]; /* K_i, i >= 1: (1/i!) d^i/dx^i of that sum at mu^2 */
+    double taylor_rho;               /* radius of the Cauchy circle the K_i come from */
 } orc_ctx;
 
 /* sum over the contour of dy y/(y + m2^2) <1/D1>, for class cls (R, Y, YRES) */
@@ -376,6 +381,23 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
     return s;
 }
 
+/* The subtracted polynomial of t^n (eq. 12-13, about x = mu^2):
+ * sum_{i=0}^{n} (x - mu^2)^i K_i, K_0 the real-axis sum at mu^2.  If absum is
+ * given, adds for i >= 1 |x - mu^2|^i (|K_i| + |K_0| rho^-i): each term's own
+ * size, and the rounding of the Cauchy sum that K_i comes from (about
+ * eps |S| rho^-i), in units of eps. */
+static cplx orc_subtraction(const orc_ctx *c, cplx x, double *absum)
+{
+    cplx sub = c->jmu, d = x - c->p->mu2, dp = 1.0;
+    for (int i = 1; i <= c->p->taylor_order; ++i) {
+        dp *= d;
+        sub += dp * c->taylor[i];
+        if (absum)
+            *absum += cabs(dp) * (cabs(c->taylor[i]) + cabs(c->jmu) * pow(c->taylor_rho, -i));
+    }
+    return sub;
+}
+
 /* G at one point; returns the class; *cond as described at orc_eval_points. */
 static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double *cond)
 {
@@ -403,18 +425,49 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
             return ORC_SINGULAR;
         }
         s = orc_contour_sum(c, xb, cb, sb, pab);
-        cplx gb = c->p->scale * (s - c->jmu);
+        cplx gb = c->p->scale * (s - orc_subtraction(c, xb, pab));
         *g = conj(gb);
         if (cond) *cond = c->p->scale * absum / cabs(gb);
         return cls;
     }
     s = orc_contour_sum(c, x, cls, sign, pab);
-    *g = c->p->scale * (s - c->jmu);
+    *g = c->p->scale * (s - orc_subtraction(c, x, pab));
     if (cond) *cond = c->p->scale * absum / cabs(*g);
     return cls;
 }
 
 static void orc_ctx_free(orc_ctx *c);
+
+/* Taylor coefficients K_i = (1/i!) d^i S/dx^i at x = mu^2, i = 0..n, of the
+ * real-axis sum S(x) = sum over the radial nodes of W y/(y + m2^2) <1/D1>(x, y),
+ * by Cauchy's integral formula: K_i = (1/(2 pi i)) contour integral of
+ * S(x) / (x - mu^2)^(i+1) over |x - mu^2| = rho, with the trapezoidal rule on
+ * 64 equally spaced points (exact up to (rho/R)^64 for S analytic in the disc
+ * of radius R).  S is a sum of terms rational in x whose poles are the x where
+ * some node's first propagator vanishes, x = (sqrt(y) z +- sqrt(y z^2 - y -
+ * m1^2))^2; rho is half the distance from mu^2 to the nearest of them. */
+static double orc_taylor_cauchy(const orc_ctx *c, int n, cplx *K)
+{
+    const orc_problem *p = c->p;
+    double dmin = INFINITY;
+    for (int i = 0; i < p->n_radial; ++i) {
+        cplx sy = sqrt(c->r[i]);
+        for (int j = 0; j < p->n_angular; ++j) {
+            cplx root = csqrt(c->r[i] * c->z[j] * c->z[j] - c->r[i] - c->geo.m1sq);
+            cplx s1 = sy * c->z[j] + root, s2 = sy * c->z[j] - root;
+            dmin = fmin(dmin, fmin(cabs(s1 * s1 - p->mu2), cabs(s2 * s2 - p->mu2)));
+        }
+    }
+    double rho = 0.5 * dmin;
+    const int N = 64;
+    for (int i = 0; i <= n; ++i) K[i] = 0.0;
+    for (int k = 0; k < N; ++k) {
+        cplx e = cexp(I * 2.0 * M_PI * k / N);
+        cplx S = orc_contour_sum(c, p->mu2 + rho * e, ORC_R, 0, NULL);
+        for (int i = 0; i <= n; ++i) K[i] += S * cpow(rho * e, -i) / N;
+    }
+    return rho;
+}
 
 static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
 {
@@ -448,6 +501,11 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     double a = 0.0;
     c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, ORC_R, 0, &a);
     c->jmu_abs = a;
+    if (p->taylor_order < 0 || p->taylor_order > ORC_MAX_TAYLOR) {
+        orc_ctx_free(c);
+        return -1;
+    }
+    if (p->taylor_order > 0) c->taylor_rho = orc_taylor_cauchy(c, p->taylor_order, c->taylor);
     return 0;
 }
 
@@ -528,6 +586,25 @@ int orc_jmu(const orc_problem *p, double *re, double *im)
 }
 
 /* Class of each point without evaluating (for tests). */
+/* All Taylor coefficients K_0..K_n of the subtraction by the Cauchy formula
+ * (K_0 also by the direct sum, as orc_jmu): out 2(n+1) doubles; *rho the
+ * radius of the circle used. */
+int orc_taylor(const orc_problem *p, int n, double *out, double *rho)
+{
+    orc_ctx c;
+    orc_problem q = *p;
+    q.taylor_order = 0;
+    if (n < 0 || n > ORC_MAX_TAYLOR || orc_ctx_init(&c, &q) != 0) return -1;
+    cplx K[ORC_MAX_TAYLOR + 1];
+    *rho = orc_taylor_cauchy(&c, n, K);
+    for (int i = 0; i <= n; ++i) {
+        out[2 * i] = creal(K[i]);
+        out[2 * i + 1] = cimag(K[i]);
+    }
+    orc_ctx_free(&c);
+    return 0;
+}
+
 int orc_classify_points(const orc_problem *p, long n, const double *x_re, const double *x_im,
                         signed char *cls)
 {

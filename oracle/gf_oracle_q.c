@@ -22,6 +22,7 @@ typedef struct {
     double mu2, lambda2, scale;
     int n_radial, n_angular, n_arc;
     int angular_rule;   /* only 0 (Gauss-Chebyshev II) is implemented here */
+    int taylor_order;   /* only 0 is implemented here */
 } orcq_problem;   /* same layout as the FP64 oracle's problem struct */
 
 #define QPI M_PIq

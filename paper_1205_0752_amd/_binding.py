@@ -28,7 +28,7 @@ CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
-           "gf_plan_jmu", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
+           "gf_plan_jmu", "gf_plan_taylor", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
            "gf_yscan_plan", "gf_cut_curve", "gf_obstruction_map",
            "gf_server_create", "gf_server_submit", "gf_server_poll", "gf_server_wait",
            "gf_server_wait_any", "gf_server_result", "gf_server_copy_result",
@@ -47,7 +47,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("m1sq_re", ctypes.c_double), ("m1sq_im", ctypes.c_double),
                 ("m2sq_re", ctypes.c_double), ("m2sq_im", ctypes.c_double),
                 ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
-                ("scale", ctypes.c_double)]
+                ("scale", ctypes.c_double), ("taylor_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Quad(ctypes.Structure):
@@ -101,6 +102,7 @@ def load():
         lib.gf_plan_jmu.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
         lib.gf_plan_auto_lanes.argtypes = [vp, ctypes.POINTER(_Grid)]
+        lib.gf_plan_taylor.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         lib.gf_last_error.restype = ctypes.c_char_p
         lib.gf_version.restype = ctypes.c_char_p
         lib.gf_yscan_plan.argtypes = [vp, ctypes.c_double, ctypes.c_double,
@@ -135,7 +137,7 @@ def _check(rc: int) -> int:
 def c_params(p: Params) -> _Params:
     m1, m2 = complex(p.m1sq), complex(p.m2sq)
     return _Params(m1.real, m1.imag, m2.real, m2.imag, float(p.mu2), float(p.lambda2),
-                   float(p.scale))
+                   float(p.scale), int(getattr(p, "taylor_order", 0)), 0)
 
 
 def c_quad(q: Quadrature) -> _Quad:
@@ -179,6 +181,13 @@ class Plan:
         re, im = ctypes.c_double(), ctypes.c_double()
         _check(load().gf_plan_jmu(self.handle, ctypes.byref(re), ctypes.byref(im)))
         return complex(re.value, im.value)
+
+    def taylor(self):
+        """K_0..K_n, the Taylor coefficients of the subtraction at mu^2."""
+        n = int(getattr(self.params, "taylor_order", 0))
+        buf = (ctypes.c_double * (2 * (n + 1)))()
+        _check(load().gf_plan_taylor(self.handle, buf))
+        return [complex(buf[2 * i], buf[2 * i + 1]) for i in range(n + 1)]
 
     def auto_lanes(self, grid: Grid) -> int:
         return _check(load().gf_plan_auto_lanes(self.handle, ctypes.byref(c_grid(grid))))

@@ -23,7 +23,7 @@ struct gf_plan {
     gf_quadrature quad{};
     void *d_mem = nullptr;       // one allocation holding every table
     gf::ScanArgs base{};         // kernel arguments minus the grid and outputs
-    double jmu[2] = {0.0, 0.0};  // host copy of the subtraction sum
+    double jmu[2 * (GF_MAX_TAYLOR + 1)] = {};  // host copy of K_0..K_n
 };
 
 namespace gf {
@@ -202,6 +202,8 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
     a.sy0_re = sy0.real();
     a.sy0_im = sy0.imag();
     a.scale = p.scale;
+    a.n_taylor = p.taylor_order;
+    a.mu2 = p.mu2;
     // bad rays arg(-m1^2), arg(-m2^2) and the open sector (lo, hi) around the
     // positive real axis that the ray can sweep without crossing one
     a.beta1 = bad_ray(p.m1sq_re, p.m1sq_im);
@@ -241,6 +243,10 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     if (!(p->lambda2 <= 1e30)) return fail(GF_EINVAL, "lambda2 must be <= 1e30");
     if (!(p->mu2 >= 0.0)) return fail(GF_EINVAL, "mu2 must be >= 0");
     if (!(p->mu2 < p->lambda2)) return fail(GF_EINVAL, "mu2 must be below lambda2");
+    if (p->taylor_order < 0 || p->taylor_order > GF_MAX_TAYLOR)
+        return fail(GF_EINVAL, "taylor_order must be in [0, %d], got %d", GF_MAX_TAYLOR,
+                    p->taylor_order);
+    if (p->reserved != 0) return fail(GF_EINVAL, "reserved must be 0");
     if (p->m1sq_im == 0.0 && p->m1sq_re <= 0.0)
         return fail(GF_EINVAL, "m1^2 must not lie on the non-positive real axis");
     if (p->m2sq_im == 0.0 && p->m2sq_re <= 0.0)
@@ -395,7 +401,7 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     a.ang32 = reinterpret_cast<const float *>(base + off_a32);
     a.wmid = wmid;
 
-    // subtraction sum at mu^2 (FP64, real axis), computed once per plan
+    // Taylor coefficients of the subtraction at mu^2 (FP64, real axis), once per plan
     double *d_jmu = reinterpret_cast<double *>(base + off_jmu);
     a.jmu = d_jmu;
     hipStream_t s;
@@ -406,7 +412,8 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     }
     e = gf::launch_jmu(a, params->mu2, d_jmu, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(plan->jmu, d_jmu, sizeof(plan->jmu), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(plan->jmu, d_jmu, 2 * sizeof(double) * (params->taylor_order + 1),
+                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
     if (e != hipSuccess) {
@@ -435,6 +442,13 @@ int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im)
     if (!plan || !re || !im) return fail(GF_EINVAL, "NULL argument");
     *re = plan->jmu[0];
     *im = plan->jmu[1];
+    return GF_OK;
+}
+
+int gf_plan_taylor(const gf_plan_t *plan, double *coeffs)
+{
+    if (!plan || !coeffs) return fail(GF_EINVAL, "NULL argument");
+    for (int i = 0; i < 2 * (plan->params.taylor_order + 1); ++i) coeffs[i] = plan->jmu[i];
     return GF_OK;
 }
 

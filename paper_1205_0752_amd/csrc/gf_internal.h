@@ -38,7 +38,10 @@ struct ScanArgs {
     double m1_re, m1_im, m2_re, m2_im;  // m1^2, m2^2
     double lam2, lam;                    // Lambda^2, Lambda
     double sy0_re, sy0_im;               // sqrt(-m2^2) (residue node)
-    const double *jmu;                   // device: unscaled subtraction sum at mu^2 (re, im)
+    const double *jmu;                   // device: Taylor coefficients K_0..K_n of the
+                                         // subtraction at mu^2, (re, im) interleaved
+    int n_taylor;                        // n of t^n
+    double mu2;
     double scale;
 
     // contour geometry

@@ -22,7 +22,9 @@ namespace {
 // One wave's tile of grid points: STEP 4 (the point) and STEP 5 (eq. 15 on
 // the point's contour), shared by the one-grid scan and the serving kernel so a
 // point's result does not depend on which launch computes it.
-template <int PREC, int L, class Args>
+// TAYLOR = false compiles out the t^n (n >= 1) epilogue, so the order-0 scan
+// carries no extra live values; both forms compute order 0 identically.
+template <int PREC, int L, bool TAYLOR, class Args>
 __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 {
     constexpr int P = 64 / L;
@@ -69,8 +71,21 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
             gr = __builtin_nan("");
             gi = __builtin_nan("");
         } else {
-            gr = a.scale * (sr - a.jmu[0]);
-            gi = a.scale * (si - a.jmu[1]);
+            double kr = a.jmu[0], ki = a.jmu[1];
+            if (TAYLOR && a.n_taylor > 0) {
+                // t^n: subtract sum_i (x - mu^2)^i K_i at the evaluated point
+                // (conj x for a mirror point), by Horner's rule
+                const double er = fma((double)ia + 0.5, a.d_re, a.re_lo) - a.mu2;
+                const double yi = fma((double)ib + 0.5, a.d_im, a.im_lo);
+                const cd d = mk(er, cls == kMirror ? -yi : yi);
+                cd sub = mk(a.jmu[2 * a.n_taylor], a.jmu[2 * a.n_taylor + 1]);
+                for (int i = a.n_taylor - 1; i >= 0; --i)
+                    sub = cadd(cmul(sub, d), mk(a.jmu[2 * i], a.jmu[2 * i + 1]));
+                kr = sub.r;
+                ki = sub.i;
+            }
+            gr = a.scale * (sr - kr);
+            gi = a.scale * (si - ki);
             if (cls == kMirror) gi = -gi;
         }
         const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
@@ -81,22 +96,22 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
 // Register budgets: the FP64 kernel runs best at 5 waves per SIMD, the FP32C
 // kernel at 6 (measured; the few spills this costs sit outside the inner loop).
-template <int L>
+template <int L, bool TAYLOR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<0, L>(a, wave, threadIdx.x & 63);
+    process_tile<0, L, TAYLOR>(a, wave, threadIdx.x & 63);
 }
 
-template <int L>
+template <int L, bool TAYLOR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<1, L>(a, wave, threadIdx.x & 63);
+    process_tile<1, L, TAYLOR>(a, wave, threadIdx.x & 63);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
@@ -114,7 +129,7 @@ __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem 
         if (w >= (unsigned)n_items) break;
         const int req = ro(items)[w].req;
         const int tile = ro(items)[w].tile;
-        process_tile<PREC, L>(ro(reqs)[req], tile, lane);
+        process_tile<PREC, L, true>(ro(reqs)[req], tile, lane);
     }
 }
 
@@ -135,11 +150,53 @@ serve_kernel_fp32c(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict
 }
 
 // Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
+// Higher Taylor coefficients of one folded angular sum about x = mu^2 on the
+// real axis (y = r real): with delta = x - mu^2, each symmetric pair
+// contributes 2w U(delta) / D(delta), U = U0 + delta, D = U^2 - 4 x y z^2 =
+// D0 + D1 delta + delta^2, whose power series q_i follows from
+// D q = 2w U term by term; the middle node w_mid / (U0 + delta) has
+// q_i = w_mid (-1)^i / U0^(i+1).  acc[i] += omega q_i for i = 1..n.
+template <class Args>
+__device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd *acc)
+{
+    const double *tab = a.ang;
+    for (int j = 0; j < a.n_a / 2; ++j) {
+        const double z2 = ro(tab)[2 * j], w2 = ro(tab)[2 * j + 1];
+        const cd D0 = mk(U0.r * U0.r - U0.i * U0.i - 4.0 * a.mu2 * y * z2, 2.0 * U0.r * U0.i);
+        const cd D1 = mk(2.0 * U0.r - 4.0 * y * z2, 2.0 * U0.i);
+        const cd rD = cdiv(mk(1.0, 0.0), D0);
+        cd qm2 = mk(0.0, 0.0);
+        cd qm1 = cmul(cscale(U0, w2), rD);  // q_0
+        for (int i = 1; i <= n; ++i) {
+            cd rhs = mk(-(D1.r * qm1.r - D1.i * qm1.i) - qm2.r, -(D1.r * qm1.i + D1.i * qm1.r) - qm2.i);
+            if (i == 1) rhs = cadd(rhs, mk(w2, 0.0));
+            const cd q = cmul(rhs, rD);
+            acc[i] = cadd(acc[i], cmul(omega, q));
+            qm2 = qm1;
+            qm1 = q;
+        }
+    }
+    if (a.wmid != 0.0) {
+        const cd rU = cdiv(mk(1.0, 0.0), U0);
+        cd p = cscale(rU, a.wmid);
+        for (int i = 1; i <= n; ++i) {
+            p = cscale(cmul(p, rU), -1.0);
+            acc[i] = cadd(acc[i], cmul(omega, p));
+        }
+    }
+}
+
+// Subtraction coefficients at the real point mu^2 on the real axis, by one
+// wavefront: K_0 = the subtraction sum of eq. 14 (the order-0 operator t^0),
+// and for t^n with n >= 1 the Taylor coefficients K_i = (1/i!) d^i/dx^i of the
+// same sum (eq. 13 about x = mu^2).
 template <class Args>
 __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
 {
     const PointCtx pc = point_setup(a, mu2, 0.0, kR, 0);
     double sr = 0.0, si = 0.0;
+    cd acc[GF_MAX_TAYLOR + 1];
+    for (int i = 0; i <= GF_MAX_TAYLOR; ++i) acc[i] = mk(0.0, 0.0);
     for (int k = lane; k < pc.nodes; k += 64) {
         cd U, V2, w;
         node_coeffs(a, pc, k, U, V2, w);
@@ -147,11 +204,23 @@ __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst,
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
+        if (a.n_taylor > 0) taylor_node(a, U, ro(a.rad)[k], w, a.n_taylor, acc);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         sr += __shfl_xor(sr, off);
         si += __shfl_xor(si, off);
+    }
+    for (int i = 1; i <= a.n_taylor; ++i) {
+        double ar = acc[i].r, ai = acc[i].i;
+        for (int off = 32; off > 0; off >>= 1) {
+            ar += __shfl_xor(ar, off);
+            ai += __shfl_xor(ai, off);
+        }
+        if (lane == 0) {
+            dst[2 * i] = ar;
+            dst[2 * i + 1] = ai;
+        }
     }
     if (lane == 0) {
         dst[0] = sr;
@@ -179,10 +248,17 @@ template <int L>
 hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
     const int blocks = (a.n_tiles + 3) / 4;
+    const bool taylor = a.n_taylor > 0;
     if (precision == 0) {
-        hipLaunchKernelGGL(scan_kernel_fp64<L>, dim3(blocks), dim3(256), 0, s, a);
+        if (taylor)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((scan_kernel_fp64<L, false>), dim3(blocks), dim3(256), 0, s, a);
     } else if (precision == 1) {
-        hipLaunchKernelGGL(scan_kernel_fp32c<L>, dim3(blocks), dim3(256), 0, s, a);
+        if (taylor)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, false>), dim3(blocks), dim3(256), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }

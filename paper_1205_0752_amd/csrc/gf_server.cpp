@@ -321,7 +321,7 @@ bool gf_server::admit_one(Request *r, Stage &st, std::vector<Request *> &fresh,
     a.ang32 = reinterpret_cast<const float *>(d_arena + tb[1]->off + tb[1]->off32);
     a.wmid = tb[1]->wmid;
     a.arc = reinterpret_cast<const double *>(d_arena + tb[2]->off);
-    a.jmu = d_jmu + 2 * r->slot;
+    a.jmu = d_jmu + 2 * (GF_MAX_TAYLOR + 1) * (size_t)r->slot;
     gf::set_grid(a, r->g, r->lanes);
     a.out = reinterpret_cast<double *>(d_arena + out_off);
     a.cls = nullptr;
@@ -539,7 +539,8 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out)
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->d_arena, cfg->device_budget_bytes);
     if (e == hipSuccess) e = hipMalloc(&s->d_args, sizeof(gf::ScanArgs) * cfg->max_inflight);
-    if (e == hipSuccess) e = hipMalloc(&s->d_jmu, 2 * sizeof(double) * cfg->max_inflight);
+    if (e == hipSuccess)
+        e = hipMalloc(&s->d_jmu, 2 * sizeof(double) * (GF_MAX_TAYLOR + 1) * cfg->max_inflight);
     for (int k = 0; e == hipSuccess && k < kStages; ++k) {
         s->stage[k].bytes = kStageBytes;
         e = hipHostMalloc(reinterpret_cast<void **>(&s->stage[k].h), kStageBytes, 0);

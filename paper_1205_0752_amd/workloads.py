@@ -27,14 +27,16 @@ TANH_SINH = 2
 @dataclasses.dataclass(frozen=True)
 class Params:
     """Integrand parameters: masses on the (p-k) leg (m1sq) and the k leg
-    (m2sq), the real subtraction point mu2 >= 0, the cutoff Lambda^2 of eq. 14
-    and the output scale (1.0 = rescaled units of eq. 18, 1/(16 pi^2) =
-    eq. 17)."""
+    (m2sq), the real subtraction point mu2 >= 0, the cutoff Lambda^2 of eq. 14,
+    the output scale (1.0 = rescaled units of eq. 18, 1/(16 pi^2) =
+    eq. 17) and the order n of the Taylor subtraction t^n (eq. 12-13, about
+    x = mu2)."""
     m1sq: complex = 1.0
     m2sq: complex = 1.0
     mu2: float = 1.0
     lambda2: float = 1e4
     scale: float = 1.0
+    taylor_order: int = 0
 
 
 @dataclasses.dataclass(frozen=True)

@@ -1,0 +1,172 @@
+"""Taylor subtraction t^n of order n >= 1 (eq. 12-13, expanded about the real
+point mu^2; eq. 13's expansion point x = 0 is mu^2 = 0).
+
+CPU pins of the oracle (which takes the coefficients K_i = (1/i!) d^i S/dx^i
+of the real-axis sum by Cauchy's integral formula): K_0 equal to the direct
+subtraction sum; K_i equal to the Feynman-form coefficients, which for
+m1 = m2 = 1, mu^2 = 0 are the Beta-function values -((-1)^(i-1)/i) (i!)^2/(2i+1)!;
+G_n against the Feynman form minus its Taylor polynomial; G_n and its first n
+derivatives vanishing at mu^2; the mirror symmetry.  GPU: the library's K_i
+(exact power-series arithmetic on the folded angular sum, a different method)
+against the oracle's, scans with n = 1, 2, 4 against the oracle in FP64 and
+FP32C, and served results equal to standalone scans bit for bit."""
+import dataclasses
+from math import factorial
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_1205_0752_amd.workloads import Grid, Params, Quadrature
+
+EPS = 2.0 ** -53
+
+
+def test_cauchy_k0_equals_direct_subtraction_sum():
+    for p in (Params(1.0, 1.0, 1.0, 1e6), Params(2.0, 0.7, 1.5, 1e6),
+              Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Params(-0.5j, 0.5j, 0.0, 1e6)):
+        q = Quadrature(256, 128, 16)
+        K, _ = oracle.taylor(p, q, 3)
+        j = oracle.jmu(p, q)
+        assert abs(K[0] - j) <= 1e-13 * abs(j), (p, K[0], j)
+
+
+def test_coefficients_equal_beta_function_values():
+    """m1 = m2 = 1, mu^2 = 0: Delta = 1 and K_i -> -((-1)^(i-1)/i) B(i+1, i+1);
+    the cutoff changes K_1 by m1^2/(2 Lambda^4) only.  Tolerance: 1e-11
+    relative plus the Cauchy sum's rounding, ~64 eps |K_0| rho^-i."""
+    p = Params(1.0, 1.0, 0.0, 1e6)
+    K, rho = oracle.taylor(p, Quadrature(512, 256, 16), 5)
+    for i in range(1, 6):
+        exact = -((-1) ** (i - 1)) / i * factorial(i) ** 2 / factorial(2 * i + 1)
+        tol = 1e-11 * abs(exact) + 64 * EPS * abs(K[0]) * rho ** -i
+        assert abs(K[i] - exact) <= tol, (i, K[i], exact)
+
+
+@pytest.mark.parametrize("m1,m2,mu2", [(1.0, 1.0, 1.0), (2.0, 0.7, 1.5), (1.0, 1.0, 0.0)])
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_subtracted_g_matches_feynman_form(m1, m2, mu2, n):
+    """The Lambda^-4 cutoff bias is linear in x, so every t^n with n >= 1
+    removes it: G_n matches the Feynman form minus its degree-n Taylor
+    polynomial to the quadrature's accuracy."""
+    p = Params(m1, m2, mu2, 1e6, 1.0, n)
+    xs = [2 + 1j, -3 + 4j, 0.5 - 2j, -6 + 6j, 5 + 0.5j]
+    g, _ = oracle.eval_points(p, Quadrature(512, 256, 16), xs)
+    for x, gx in zip(xs, g):
+        ref = cf.feynman_subtracted(x, m1, m2, mu2, n)
+        assert abs(gx - ref) <= 1e-9 * abs(ref), (x, gx, ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_subtracted_g_vanishes_to_order_n_at_mu2(n):
+    """G_n(mu^2) = 0 exactly, and G_n(mu^2 + d) = K_(n+1) d^(n+1) (1 + O(d))
+    for small d in any direction: the first n derivatives vanish."""
+    p = Params(2.0, 0.7, 1.5, 1e6, 1.0, n)
+    q = Quadrature(256, 128, 16)
+    g0, _ = oracle.eval_points(p, q, [1.5 + 0j])
+    assert g0[0] == 0
+    K, _ = oracle.taylor(p, q, n + 1)
+    for d in (1e-2, -1e-2, 1e-2j, 0.7e-2 - 0.7e-2j):
+        g, _ = oracle.eval_points(p, q, [1.5 + d])
+        lead = K[n + 1] * d ** (n + 1)
+        assert abs(g[0] - lead) <= 0.05 * abs(lead) + 1e-14, (d, g[0], lead)
+
+
+def test_mirror_symmetry_with_taylor_subtraction():
+    p = Params(1.0, 1.0, 1.0, 1e6, 1.0, 2)
+    xs = np.array([-4 + 2j, 1.5 + 3j, -0.5 + 0.7j])
+    q = Quadrature(128, 64, 16)
+    g, _ = oracle.eval_points(p, q, xs)
+    gb, _ = oracle.eval_points(p, q, np.conj(xs))
+    assert np.allclose(gb, np.conj(g), rtol=1e-12, atol=0)
+
+
+def test_library_rejects_bad_orders():
+    import paper_1205_0752_amd as gf
+    for p in (Params(1.0, 1.0, 1.0, 1e6, 1.0, 9), Params(1.0, 1.0, 1.0, 1e6, 1.0, -1)):
+        with pytest.raises(gf.GFError) as e:
+            gf.Plan(p, Quadrature(32, 16, 8))
+        assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- GPU
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1205_0752_amd as gf
+    return torch, gf
+
+
+MASSES = [Params(1.0, 1.0, 0.0, 1e6), Params(2.0, 0.7, 1.5, 1e6),
+          Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Params(-0.5j, 0.5j, 0.0, 1e6)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", MASSES, ids=["real0", "unequal", "conj", "paper"])
+def test_gpu_taylor_coefficients_match_oracle(p):
+    """Power-series arithmetic on the device against the Cauchy formula."""
+    torch, gf = _gpu()
+    n = 4
+    q = Quadrature(256, 128, 16)
+    plan = gf.Plan(dataclasses.replace(p, taylor_order=n), q)
+    K = np.array(plan.taylor())
+    plan.close()
+    Ko, rho = oracle.taylor(p, q, n)
+    for i in range(n + 1):
+        tol = 1e-12 * abs(Ko[i]) + 64 * EPS * abs(Ko[0]) * rho ** -i
+        assert abs(K[i] - Ko[i]) <= tol, (i, K[i], Ko[i], tol)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [1, 2, 4])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32c"])
+def test_gpu_scan_with_taylor_order_matches_oracle(n, prec):
+    """Ragged grids, real and conjugate-pair masses (all four classes), against
+    the oracle with the same order; the bars of the order-0 parity tests with
+    the subtracted polynomial's terms counted in kappa."""
+    torch, gf = _gpu()
+    cases = [(Params(2.0, 0.7, 1.5, 1e6, 1.0, n), Grid(37, 29, -8.0, 4.0, -4.0, 4.0)),
+             (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0, n), Grid(21, 17, -12.0, 6.0, -6.0, 6.0))]
+    for p, grid in cases:
+        q = Quadrature(64, 32, 16, prec)
+        plan = gf.Plan(p, q)
+        out = gf.empty_result(grid)
+        cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
+        gf.scan_plan(plan, grid, out, cls)
+        torch.cuda.synchronize()
+        plan.close()
+        g = out.cpu().numpy().ravel()
+        c = cls.cpu().numpy().ravel()
+        go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+        keep = (c == co) & (co != oracle.SINGULAR)
+        assert (c != co).sum() <= 1
+        err = np.abs(g[keep] - go[keep])
+        mag = np.abs(go[keep])
+        kap = cond[keep]
+        if prec == 0:
+            assert np.all(err <= np.maximum(1e-12 * mag, 64 * EPS * kap * mag)), np.max(err / mag)
+        else:
+            lim = np.maximum(16 * 2.0 ** -24 * kap * mag, 1e-6 * np.maximum(mag, 1.0))
+            assert np.all(err <= lim), np.max(err / lim)
+
+
+@pytest.mark.gpu
+def test_gpu_served_taylor_requests_equal_standalone():
+    torch, gf = _gpu()
+    reqs = [(Params(1.0, 1.0, 1.0, 1e6, 1.0, n), Grid(40, 24, -8.0, 4.0, -4.0, 4.0),
+             Quadrature(64, 32, 16, prec)) for n in (0, 1, 3) for prec in (0, 1)]
+    with gf.Server(budget_bytes=64 << 20, max_inflight=16, batch_evals=1e7) as srv:
+        ts = [srv.submit(*r) for r in reqs]
+        for t in ts:
+            assert srv.wait(t, 120000.0)
+        got = [srv.result(t) for t in ts]
+    for (p, grid, q), g in zip(reqs, got):
+        plan = gf.Plan(p, q)
+        ref = gf.scan_plan(plan, grid, lanes=1)
+        torch.cuda.synchronize()
+        plan.close()
+        ref = ref.cpu().numpy().ravel()
+        assert np.array_equal(g.view(np.float64), ref.view(np.float64)), (p, q)
