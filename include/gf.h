@@ -62,20 +62,25 @@ extern "C" {
                             coefficients, radial sum, mu^2 subtraction and
                             scaling in FP64 */
 
-/* ---- angular quadrature rule for <f> = (2/pi) int_{-1}^{1} sqrt(1-z^2) f(z) dz
- * (the z integral of eq. 11; the paper uses tanh-sinh as its main rule and the
- * two Gauss-Chebyshev rules as checks, section "Numerical Implementation").
- * Every rule is symmetric in z, so the kernels sum node pairs (z, -z). */
-#define GF_ANG_GC2 0        /* Gauss-Chebyshev, second kind: z_j = cos(j pi/(n+1)),
-                               w_j = 2 sin^2(j pi/(n+1))/(n+1), j = 1..n; exact for
-                               polynomial f of degree <= 2n-1 */
-#define GF_ANG_GC1 1        /* Gauss-Chebyshev, first kind, on f(z) (1 - z^2):
-                               z_j = cos((2j-1) pi/(2n)), w_j = (2/n) sin^2((2j-1) pi/(2n));
-                               exact for degree <= 2n-3 */
+/* ---- angular quadrature rule for the normalised angular average
+ * <f> = int_{-1}^{1} (1-z^2)^{(D-3)/2} f(z) dz / N_D (the z integral of eq. 11
+ * in D dimensions; N_D = pi, 2, pi/2 for D = 2, 3, 4).  The paper uses
+ * tanh-sinh as its main rule and the two Gauss-Chebyshev rules as checks,
+ * choosing between them by dimension (section "Numerical Implementation").
+ * Each rule integrates g against its own weight omega(z) and is applied to
+ * g = f (1-z^2)^{(D-3)/2} / omega; every rule is symmetric in z, so the kernels
+ * sum node pairs (z, -z). */
+#define GF_ANG_GC2 0        /* Gauss-Chebyshev, second kind, omega = sqrt(1-z^2):
+                               z_j = cos(j pi/(n+1)); natural for D = 4 (exact for
+                               polynomial f of degree <= 2n-1) */
+#define GF_ANG_GC1 1        /* Gauss-Chebyshev, first kind, omega = 1/sqrt(1-z^2):
+                               z_j = cos((2j-1) pi/(2n)); natural for D = 2 */
 #define GF_ANG_TANH_SINH 2  /* double exponential: z = tanh((pi/2) sinh t) on the
-                               equispaced t_k = (k - (n-1)/2) h, h = 6/(n-1) (t in
-                               [-3, 3]), w_k = h cosh t_k / cosh^3((pi/2) sinh t_k);
-                               n >= 3, weights not renormalised */
+                               equispaced t_k = (k - (n-1)/2) h, h = 2 t_max/(n-1),
+                               t_max = 3, 3.5, 4 for D = 4, 3, 2, weight
+                               h dz/dt (1-z^2)^{(D-3)/2} / N_D; n >= 3, weights not
+                               renormalised */
+#define GF_ANG_GL 3         /* Gauss-Legendre, omega = 1; natural for D = 3 */
 
 /* ---- contour classes (values of the optional class map) ---------------- */
 #define GF_CLASS_R 0         /* real axis [0, Lambda^2] */
@@ -87,14 +92,18 @@ extern "C" {
 /* Integrand parameters (eq. 14-16).  m1^2 sits on the (p-k) leg, m2^2 on the
  * k leg; neither may lie on the non-positive real axis.  mu2 is the real
  * subtraction point (>= 0), lambda2 the cutoff Lambda^2 (> 0), scale the
- * output multiplier.  taylor_order n (0..GF_MAX_TAYLOR) is the order of the
+ * output multiplier.  taylor_order n (-1..GF_MAX_TAYLOR) is the order of the
  * Taylor subtraction operator t^n of eq. 12-13, taken about x = mu2 (eq. 13
  * expands about x = 0, i.e. mu2 = 0): the result is
  *   scale * ( S(x) - sum_{i=0}^{n} (x - mu2)^i K_i ),
- * S the contour sum of <F(x, y, .)>, K_i = (1/i!) d^i/dx^i of the real-axis
- * sum at x = mu2 (K_0 is the subtraction sum of order 0).  The angular
- * average is an analytic function of x (V^2 = 4xy enters, not sqrt(x)), so
- * its derivatives exist at x = 0.  reserved must be 0. */
+ * S the contour sum of y^{(D-2)/2} <F(x, y, .)>, K_i = (1/i!) d^i/dx^i of the
+ * real-axis sum at x = mu2 (K_0 is the subtraction sum of order 0); n = -1
+ * subtracts nothing (for integrals that converge without it, D < 4).  The
+ * angular average is an analytic function of x (V^2 = 4xy enters, not
+ * sqrt(x)), so its derivatives exist at x = 0.  dimension D (2, 3 or 4; 0
+ * means 4) sets the hyperspherical measure of eq. 5-9 in D dimensions:
+ * dy y^{(D-2)/2} (1-z^2)^{(D-3)/2} dz, the angular part normalised (see
+ * GF_ANG_*). */
 #define GF_MAX_TAYLOR 8
 typedef struct {
     double m1sq_re, m1sq_im;
@@ -103,7 +112,7 @@ typedef struct {
     double lambda2;
     double scale;
     int32_t taylor_order;
-    int32_t reserved;
+    int32_t dimension;
 } gf_params;
 
 /* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
@@ -194,9 +203,10 @@ int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid);
  * the contour (STEP 3).  gf_yscan_plan evaluates, with the plan's angular rule
  * in FP64, at every point of a cell-centred grid of complex y:
  *   GF_YSCAN_ANGULAR    <1/D1>(x, y) = sum_j w_j / (x + y + m1^2 - 2 sqrt(x) sqrt(y) z_j)
- *   GF_YSCAN_INTEGRAND  y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)), the
- *                       subtracted y-integrand of eq. 14 (eq. 22 in the
- *                       worked example, up to the factor 2/pi)
+ *   GF_YSCAN_INTEGRAND  y^{(D-2)/2}/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)),
+ *                       the order-0 subtracted y-integrand of eq. 14 (eq. 22
+ *                       in the worked example, up to the factor 2/pi; D = 4
+ *                       gives y, D = 3 the principal sqrt(y))
  * into `out` (complex128 [n_im][n_re], caller-owned device memory),
  * asynchronously on `stream`.  Errors: GF_EINVAL, GF_EDEVICE. */
 #define GF_YSCAN_ANGULAR 0

@@ -33,7 +33,7 @@ class _Problem(ctypes.Structure):
                 ("scale", ctypes.c_double),
                 ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
                 ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int),
-                ("taylor_order", ctypes.c_int)]
+                ("taylor_order", ctypes.c_int), ("dimension", ctypes.c_int)]
 
 
 def build(verbose: bool = False) -> None:
@@ -64,6 +64,7 @@ def _load():
         lib.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_gauss_cheb2.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_angular_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        lib.orc_angular_rule_dim.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         lib.orc_angular_sum.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, dp, dp]
         lib.orc_eval_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                         ctypes.c_int, dp, ctypes.c_char_p, dp]
@@ -111,7 +112,8 @@ def problem(params, quad) -> _Problem:
                     float(params.lambda2), float(params.scale),
                     int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
                     int(getattr(quad, "angular_rule", 0)),
-                    int(getattr(params, "taylor_order", 0)))
+                    int(getattr(params, "taylor_order", 0)),
+                    int(getattr(params, "dimension", 4)))
 
 
 # ---------------------------------------------------------------- rules
@@ -130,13 +132,17 @@ def gauss_cheb2(n: int):
     return z, w
 
 
-def angular_rule(rule: int, n: int):
-    """Nodes and weights of angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh)
-    for the measure (2/pi) sqrt(1-z^2) dz."""
+def angular_rule(rule: int, n: int, dim: int = 4):
+    """Nodes and weights of angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh,
+    3 Gauss-Legendre) for the normalised D-dimensional angular measure
+    (1-z^2)^{(D-3)/2} dz / N_D (D = 4: (2/pi) sqrt(1-z^2) dz)."""
     z = np.zeros(n)
     w = np.zeros(n)
-    if _load().orc_angular_rule(int(rule), int(n), _dp(z), _dp(w)) != 0:
-        raise ValueError(f"angular rule {rule} with {n} nodes is not defined")
+    lib = _load()
+    rc = (lib.orc_angular_rule(int(rule), int(n), _dp(z), _dp(w)) if dim == 4 and rule != 3
+          else lib.orc_angular_rule_dim(int(rule), int(dim), int(n), _dp(z), _dp(w)))
+    if rc != 0:
+        raise ValueError(f"angular rule {rule} with {n} nodes in D = {dim} is not defined")
     return z, w
 
 

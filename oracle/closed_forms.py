@@ -93,6 +93,60 @@ def feynman_subtracted(x: complex, m1sq: complex, m2sq: complex, mu2: float, n: 
     return g
 
 
+def loop_sum(x: complex, m1sq: complex, m2sq: complex, dim: int) -> complex:
+    """The unsubtracted rescaled loop sum S_D(x) = int_0^inf dy y^{(D-2)/2} <F>_D
+    for D = 2, 3 (convergent), from the Feynman parametrisation of
+    int d^D k / ((k^2 + m2^2)((p-k)^2 + m1^2)): with the normalised angular
+    averages, int d^2k F = pi S_2 and int d^3k F = 2 pi S_3, so
+    S_2 = int_0^1 da / Delta(a, x) and S_3 = (pi/2) int_0^1 da Delta(a, x)^(-1/2)
+    (principal branch; valid off the real axis for real masses)."""
+    x = mp.mpc(x)
+    m1 = mp.mpc(m1sq)
+    m2 = mp.mpc(m2sq)
+    if dim == 2:
+        return complex(mp.quad(lambda a: 1 / delta(a, x, m1, m2), [0, 0.5, 1]))
+    if dim == 3:
+        return complex(mp.pi / 2 * mp.quad(lambda a: delta(a, x, m1, m2) ** -0.5, [0, 0.5, 1]))
+    raise ValueError("dim must be 2 or 3")
+
+
+def loop_sum_cutoff_bias(x: complex, m1sq: complex, m2sq: complex, mu2: float, lambda2: float,
+                         dim: int, subtracted: bool) -> complex:
+    """G_Lambda - G_infinity for D = 2, 3 from the large-y expansion of the
+    angular averages, <1/D1>_2 = 1/y + (x - m1^2)/y^2 + ..., <1/D1>_3 = 1/y +
+    (x/3 - m1^2)/y^2 + ...: the cutoff drops the tail of y^{(D-2)/2} <F>."""
+    x = complex(x)
+    m1 = complex(m1sq)
+    m2 = complex(m2sq)
+    L = lambda2 ** 0.5
+    if dim == 3:
+        if subtracted:
+            return -(2.0 / 9.0) * (x - mu2) / L ** 3
+        return -2.0 / L - (2.0 / 3.0) * (x / 3.0 - m1 - m2) / L ** 3
+    if dim == 2:
+        if subtracted:
+            return -(x - mu2) / (2.0 * lambda2 ** 2)
+        return -1.0 / lambda2 - (x - m1 - m2) / (2.0 * lambda2 ** 2)
+    raise ValueError("dim must be 2 or 3")
+
+
+def angular_moment(k: int, dim: int) -> float:
+    """<z^2k> under the normalised D-dimensional measure (1-z^2)^{(D-3)/2} dz / N_D:
+    Gamma(k + 1/2) Gamma(D/2) / (sqrt(pi) Gamma(k + D/2))."""
+    return float(mp.gamma(k + 0.5) * mp.gamma(dim / 2) / (mp.sqrt(mp.pi) * mp.gamma(k + dim / 2)))
+
+
+def angular_average_dim(u: complex, v: complex, dim: int) -> complex:
+    """<1/(u - v z)> under the normalised D-dimensional measure, by direct
+    quadrature in the angle (z = cos t, sin^{D-2} t dt): an independent
+    reference for the node rules."""
+    u = mp.mpc(u)
+    v = mp.mpc(v)
+    norm = mp.quad(lambda t: mp.sin(t) ** (dim - 2), [0, mp.pi])
+    val = mp.quad(lambda t: mp.sin(t) ** (dim - 2) / (u - v * mp.cos(t)), [0, mp.pi / 2, mp.pi])
+    return complex(val / norm)
+
+
 def feynman_principal_ok(x: complex, m1sq: complex, m2sq: complex, mu2: float,
                          n: int = 4001) -> bool:
     """True when neither Delta(a, x) nor Delta(a, mu^2) crosses the negative real

@@ -71,10 +71,13 @@ typedef struct {
     double scale;              /* 1 = eq. 18 units, 1/(16 pi^2) = eq. 17 units */
     int n_radial, n_angular, n_arc;
     int angular_rule;          /* 0 GC-II, 1 GC-I, 2 tanh-sinh */
-    int taylor_order;          /* n of the subtraction operator t^n (eq. 13), 0..8 */
+    int taylor_order;          /* n of the subtraction operator t^n (eq. 13), -1..8 */
+    int dimension;             /* D = 2, 3 or 4 (0 means 4) */
 } orc_problem;
 
 #define ORC_MAX_TAYLOR 8
+
+static int orc_dim(const orc_problem *p) { return p->dimension == 0 ? 4 : p->dimension; }
 
 /* ------------------------------------------------------------------------ */
 /* Quadrature rules                                                          */
@@ -171,7 +174,8 @@ int orc_tanh_sinh(int n, double *z, double *w)
     return 0;
 }
 
-/* Nodes and weights of the angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh). */
+/* Nodes and weights of the angular rule `rule` (0 GC-II, 1 GC-I, 2 tanh-sinh)
+ * for the four-dimensional measure (2/pi) sqrt(1-z^2) dz. */
 int orc_angular_rule(int rule, int n, double *z, double *w)
 {
     switch (rule) {
@@ -180,6 +184,54 @@ int orc_angular_rule(int rule, int n, double *z, double *w)
     case 2: return orc_tanh_sinh(n, z, w);
     default: return -1;
     }
+}
+
+/* The angular measure in D dimensions (eq. 5 generalised: the polar angle
+ * carries sin^{D-2}(theta) d theta = (1-z^2)^{(D-3)/2} dz), normalised by
+ * N_D = int_{-1}^{1} (1-z^2)^{(D-3)/2} dz = pi, 2, pi/2 for D = 2, 3, 4.  Each
+ * rule approximates int g(z) omega(z) dz for its own weight function omega
+ * (GC-II sqrt(1-z^2), GC-I 1/sqrt(1-z^2), Gauss-Legendre and tanh-sinh 1), so
+ * the weight of f(z_j) is its plain weight times (1-z_j^2)^{(D-3)/2} /
+ * omega(z_j) / N_D.  Rule 3 is Gauss-Legendre. */
+int orc_angular_rule_dim(int rule, int dim, int n, double *z, double *w)
+{
+    if (n <= 0 || dim < 2 || dim > 4) return -1;
+    double ND = dim == 2 ? M_PI : (dim == 3 ? 2.0 : M_PI / 2.0);
+    double e = 0.5 * (dim - 3);
+    if (rule == 0) {
+        for (int j = 1; j <= n; ++j) {
+            double th = j * M_PI / (n + 1), zj = cos(th), s2 = sin(th) * sin(th);
+            z[j - 1] = zj;
+            w[j - 1] = (M_PI / (n + 1)) * s2 * pow(s2, e) / sqrt(s2) / ND;
+        }
+    } else if (rule == 1) {
+        for (int j = 1; j <= n; ++j) {
+            double th = (2 * j - 1) * M_PI / (2.0 * n), s2 = sin(th) * sin(th);
+            z[j - 1] = cos(th);
+            w[j - 1] = (M_PI / n) * pow(s2, e) * sqrt(s2) / ND;
+        }
+    } else if (rule == 2) {
+        /* the trapezoidal grid spans t in [-t_max, t_max] with t_max = 3, 3.5,
+         * 4 for D = 4, 3, 2: there the transformed weight h dz/dt (1-z^2)^{(D-3)/2}
+         * ~ cosh(t) / cosh^{D-1}((pi/2) sinh t) has fallen below 1e-16 */
+        if (n < 3) return -1;
+        double tmax = dim == 4 ? 3.0 : (dim == 3 ? 3.5 : 4.0);
+        double h = 2.0 * tmax / (n - 1);
+        for (int k = 0; k < n; ++k) {
+            double t = (k - 0.5 * (n - 1)) * h;
+            double u = 0.5 * M_PI * sinh(t);
+            double dzdt = 0.5 * M_PI * cosh(t) / (cosh(u) * cosh(u));
+            z[k] = tanh(u);
+            /* 1 - z^2 = 1/cosh^2(u), exactly, without cancellation near |z| = 1 */
+            w[k] = h * dzdt * pow(1.0 / (cosh(u) * cosh(u)), e) / ND;
+        }
+    } else if (rule == 3) {
+        orc_gauss_legendre(n, z, w);
+        for (int j = 0; j < n; ++j) w[j] = w[j] * pow(1.0 - z[j] * z[j], e) / ND;
+    } else {
+        return -1;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -324,8 +376,16 @@ typedef struct {
 } orc_ctx;
 
 /* sum over the contour of dy y/(y + m2^2) <1/D1>, for class cls (R, Y, YRES) */
+/* The radial measure y^{(D-2)/2} of D dimensions (dy y for D = 4), given y
+ * and sqrt(y) on the branch continued along the contour. */
+static cplx orc_measure(int dim, cplx y, cplx sy)
+{
+    return dim == 4 ? y : (dim == 3 ? sy : 1.0);
+}
+
 static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, double *absum)
 {
+    const int dim = orc_dim(c->p);
     const orc_problem *p = c->p;
     cplx m1sq = c->geo.m1sq, m2sq = c->geo.m2sq;
     cplx sx = csqrt(x);
@@ -336,7 +396,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
             cplx sy = sqrt(c->r[i]);
             double a = 0.0;
             cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-            cplx pre = c->wr[i] * y / (y + m2sq);
+            cplx pre = c->wr[i] * orc_measure(dim, y, sy) / (y + m2sq);
             s += pre * ang;
             if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
         }
@@ -351,7 +411,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
         cplx sy = eh * sqrt(c->r[i]);
         double a = 0.0;
         cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx pre = e * c->wr[i] * y / (y + m2sq);
+        cplx pre = e * c->wr[i] * orc_measure(dim, y, sy) / (y + m2sq);
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
     }
@@ -365,16 +425,17 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
         double a = 0.0;
         cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
         cplx dy = -I * y * (0.5 * phi) * c->arc_w[k];
-        cplx pre = dy * y / (y + m2sq);
+        cplx pre = dy * orc_measure(dim, y, sy) / (y + m2sq);
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
     }
     if (cls == ORC_YRES) {
-        /* residue of y/(y + m2^2) <1/D1>(y) at y0 = -m2^2 is y0 <1/D1>(y0) */
+        /* residue of y^{(D-2)/2}/(y + m2^2) <1/D1>(y) at y0 = -m2^2 is
+         * y0^{(D-2)/2} <1/D1>(y0) */
         cplx y0 = -m2sq;
         double a = 0.0;
         cplx ang = angular_d1(x, y0, sx * csqrt(y0), m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx pre = res_sign * 2.0 * M_PI * I * y0;
+        cplx pre = res_sign * 2.0 * M_PI * I * orc_measure(dim, y0, csqrt(y0));
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a;
     }
@@ -388,6 +449,7 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
  * eps |S| rho^-i), in units of eps. */
 static cplx orc_subtraction(const orc_ctx *c, cplx x, double *absum)
 {
+    if (c->p->taylor_order < 0) return 0.0;  /* t^-1: nothing subtracted */
     cplx sub = c->jmu, d = x - c->p->mu2, dp = 1.0;
     for (int i = 1; i <= c->p->taylor_order; ++i) {
         dp *= d;
@@ -407,7 +469,7 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
         cls = force_class;
         if (cls == ORC_YRES) sign = carg(x) > 0.0 ? 1 : -1;
     }
-    double absum = c->jmu_abs;
+    double absum = c->p->taylor_order < 0 ? 0.0 : c->jmu_abs;
     double *pab = cond ? &absum : NULL;
     cplx s;
     if (cls == ORC_SINGULAR) {
@@ -486,7 +548,7 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     c->w = malloc(sizeof(double) * na);
     orc_gauss_legendre(nr, c->gl_t, c->gl_w);
     if (p->n_arc > 0) orc_gauss_legendre(p->n_arc, c->arc_x, c->arc_w);
-    if (orc_angular_rule(p->angular_rule, na, c->z, c->w) != 0) {
+    if (orc_angular_rule_dim(p->angular_rule, orc_dim(p), na, c->z, c->w) != 0) {
         orc_ctx_free(c);
         return -1;
     }
@@ -501,7 +563,7 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     double a = 0.0;
     c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, ORC_R, 0, &a);
     c->jmu_abs = a;
-    if (p->taylor_order < 0 || p->taylor_order > ORC_MAX_TAYLOR) {
+    if (p->taylor_order < -1 || p->taylor_order > ORC_MAX_TAYLOR) {
         orc_ctx_free(c);
         return -1;
     }
@@ -594,6 +656,7 @@ int orc_taylor(const orc_problem *p, int n, double *out, double *rho)
     orc_ctx c;
     orc_problem q = *p;
     q.taylor_order = 0;
+    if (orc_dim(p) < 2 || orc_dim(p) > 4) return -1;
     if (n < 0 || n > ORC_MAX_TAYLOR || orc_ctx_init(&c, &q) != 0) return -1;
     cplx K[ORC_MAX_TAYLOR + 1];
     *rho = orc_taylor_cauchy(&c, n, K);
@@ -634,14 +697,15 @@ long orc_evals_for_class(const orc_problem *p, int cls)
 int orc_threads(void) { return omp_get_max_threads(); }
 
 /* y-plane diagnostic at fixed x (the paper's Fig. 1): for each y_k,
- * what = 0: <1/D1>(x, y_k); what = 1: y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)),
- * the subtracted y-integrand of eq. 14.  out: 2n doubles. */
+ * what = 0: <1/D1>(x, y_k); what = 1: y^{(D-2)/2}/(y + m2^2) (<1/D1>(x, y) -
+ * <1/D1>(mu^2, y)), the order-0 subtracted y-integrand of eq. 14 (principal
+ * sqrt(y) for D = 3).  out: 2n doubles. */
 int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const double *y_re,
               const double *y_im, int what, double *out)
 {
     if (p->n_angular <= 0) return -1;
     double *z = malloc(sizeof(double) * p->n_angular), *w = malloc(sizeof(double) * p->n_angular);
-    if (orc_angular_rule(p->angular_rule, p->n_angular, z, w) != 0) {
+    if (orc_angular_rule_dim(p->angular_rule, orc_dim(p), p->n_angular, z, w) != 0) {
         free(z);
         free(w);
         return -1;
@@ -655,7 +719,7 @@ int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const doub
         cplx a = angular_d1(x, y, sx * sy, m1sq, p->n_angular, z, w, NULL);
         if (what == 1) {
             cplx amu = angular_d1(p->mu2 + 0.0 * I, y, smu * sy, m1sq, p->n_angular, z, w, NULL);
-            a = y / (y + m2sq) * (a - amu);
+            a = orc_measure(orc_dim(p), y, csqrt(y)) / (y + m2sq) * (a - amu);
         }
         out[2 * k] = creal(a);
         out[2 * k + 1] = cimag(a);

@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("m2sq_re", ctypes.c_double), ("m2sq_im", ctypes.c_double),
                 ("mu2", ctypes.c_double), ("lambda2", ctypes.c_double),
                 ("scale", ctypes.c_double), ("taylor_order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("dimension", ctypes.c_int32)]
 
 
 class _Quad(ctypes.Structure):
@@ -137,7 +137,8 @@ def _check(rc: int) -> int:
 def c_params(p: Params) -> _Params:
     m1, m2 = complex(p.m1sq), complex(p.m2sq)
     return _Params(m1.real, m1.imag, m2.real, m2.imag, float(p.mu2), float(p.lambda2),
-                   float(p.scale), int(getattr(p, "taylor_order", 0)), 0)
+                   float(p.scale), int(getattr(p, "taylor_order", 0)),
+                   int(getattr(p, "dimension", 4)))
 
 
 def c_quad(q: Quadrature) -> _Quad:
@@ -184,7 +185,7 @@ class Plan:
 
     def taylor(self):
         """K_0..K_n, the Taylor coefficients of the subtraction at mu^2."""
-        n = int(getattr(self.params, "taylor_order", 0))
+        n = max(int(getattr(self.params, "taylor_order", 0)), 0)
         buf = (ctypes.c_double * (2 * (n + 1)))()
         _check(load().gf_plan_taylor(self.handle, buf))
         return [complex(buf[2 * i], buf[2 * i + 1]) for i in range(n + 1)]

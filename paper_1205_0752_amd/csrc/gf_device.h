@@ -123,8 +123,9 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign)
 // node whatever the branches of sqrt(x) sqrt(y), and the angular sum depends
 // on V only through V^2 (symmetric rule), so no square root of y is needed.
 struct PointCtx {
-    cd x1;   // x + m1^2
-    cd dir;  // e^{i phi} (ray) or 1 (real axis)
+    cd x1;    // x + m1^2
+    cd dir;   // e^{i phi} (ray) or 1 (real axis)
+    cd dirD;  // e^{i phi D/2}: the phase of dy y^{(D-2)/2} along the ray
     double phi;
     int nodes;  // contour nodes of this point
     int res_sign;
@@ -141,10 +142,19 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
         double s, c;
         sincos(phi, &s, &c);
         P.dir = mk(c, s);
+        if (a.dim == 4) {
+            P.dirD = cmul(P.dir, P.dir);
+        } else if (a.dim == 3) {
+            sincos(0.5 * phi, &s, &c);
+            P.dirD = cmul(P.dir, mk(c, s));
+        } else {
+            P.dirD = P.dir;
+        }
         P.phi = phi;
         P.nodes = a.n_r + a.n_arc + (cls == kYRes ? 1 : 0);
     } else {
         P.dir = mk(1.0, 0.0);
+        P.dirD = P.dir;
         P.phi = 0.0;
         P.nodes = cls == kR ? a.n_r : 0;
     }
@@ -153,7 +163,10 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
 
 // Coefficients of contour node k -- radial (ray or real axis), closing arc,
 // or residue of the k-leg pole: U = x + y + m1^2, V^2 = 4 x y and the node's
-// weight omega (dy-weight times y / (y + m2^2), or +-2 pi i y0).
+// weight omega = dy y^{(D-2)/2} / (y + m2^2) (the D-dimensional radial measure;
+// y for D = 4), or +-2 pi i y0^{(D-2)/2} at the residue.  Along the ray
+// y = e^{i phi} r, dy y^{(D-2)/2} = e^{i phi D/2} dr r^{(D-2)/2}; the table holds
+// the real weight dr r^{(D-2)/2}.
 template <class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V2, cd &w)
@@ -165,11 +178,11 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
     if (k < a.n_r) {
         const auto *rad = ro(a.rad);
         const double r = rad[k];
-        const double wr = rad[2 * a.n_r + k];
+        const double g = rad[2 * a.n_r + k];
         const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
         U = cadd(P.x1, y);
         V2 = cmul(x4, y);                                      // 4 x y
-        w = cdiv(cscale(cmul(P.dir, P.dir), wr * r), cadd(y, m2));  // e^{i phi} dr y/(y + m2^2)
+        w = cdiv(cscale(P.dirD, g), cadd(y, m2));
     } else if (k < a.n_r + a.n_arc) {
         const int q = k - a.n_r;
         const auto *arc = ro(a.arc);
@@ -183,13 +196,21 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
         V2 = cmul(x4, y);
         const double h = 0.5 * P.phi * wa;
         const cd dy = mk(y.i * h, -y.r * h);              // dy = -i y (phi/2) dxi
-        w = cdiv(cmul(dy, y), cadd(y, m2));
+        cd f = y;                                         // y^{(D-2)/2}
+        if (a.dim == 3) {
+            sincos(0.5 * psi, &s, &c);
+            f = mk(a.lam * c, a.lam * s);
+        } else if (a.dim == 2) {
+            f = mk(1.0, 0.0);
+        }
+        w = cdiv(cmul(dy, f), cadd(y, m2));
     } else {
         const cd y0 = mk(-a.m2_re, -a.m2_im);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
         const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i Res
-        w = mk(-y0.i * f, y0.r * f);
+        const cd fy = a.dim == 4 ? y0 : (a.dim == 3 ? mk(a.sy0_re, a.sy0_im) : mk(1.0, 0.0));
+        w = mk(-fy.i * f, fy.r * f);
     }
 }
 

@@ -8,8 +8,9 @@ namespace {
 
 // y-plane diagnostic (the paper's Fig. 1): at fixed x, the angular average
 // <1/D1>(x, y) over a cell-centred grid of complex y (what = 0), or the
-// subtracted y-integrand y/(y + m2^2) (<1/D1>(x, y) - <1/D1>(mu^2, y)) of eq. 14
-// (what = 1).  One lane per y point, 8 x 8 tiles, FP64.
+// order-0 subtracted y-integrand y^{(D-2)/2}/(y + m2^2) (<1/D1>(x, y) -
+// <1/D1>(mu^2, y)) of eq. 14 (what = 1).  One lane per y point, 8 x 8 tiles,
+// FP64.
 __global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, double xi, double mu2,
                                                     int what)
 {
@@ -26,7 +27,9 @@ __global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, doubl
     if (what == 1) {
         const cd Amu = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(mk(mu2 + y.r, y.i), m1),
                                      cscale(y, 4.0 * mu2));
-        A = cdiv(cmul(y, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
+        // the radial measure y^{(D-2)/2} (principal sqrt(y) for D = 3)
+        const cd f = a.dim == 4 ? y : (a.dim == 3 ? csqrt_principal(y.r, y.i) : mk(1.0, 0.0));
+        A = cdiv(cmul(f, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
     }
     const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
     reinterpret_cast<double2 *>(a.out)[idx] = make_double2(A.r, A.i);

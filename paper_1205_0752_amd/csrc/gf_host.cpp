@@ -117,9 +117,10 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     if (n % 2 == 1) x[n / 2] = 0.0;  // exact centre node
 }
 
-void radial_table(int nr, double lambda2, std::vector<double> &rad)
+void radial_table(int nr, double lambda2, int dim, std::vector<double> &rad)
 {
-    // GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt
+    // GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt; the weight
+    // column carries the radial measure y^{(D-2)/2} of D dimensions
     std::vector<double> gx, gw;
     gauss_legendre(nr, gx, gw);
     const double T = std::log1p(lambda2);
@@ -127,51 +128,74 @@ void radial_table(int nr, double lambda2, std::vector<double> &rad)
     for (int i = 0; i < nr; ++i) {
         double t = 0.5 * T * (gx[i] + 1.0);
         double y = std::expm1(t);
+        double dy = 0.5 * T * gw[i] * (1.0 + y);
         rad[i] = y;
         rad[nr + i] = std::sqrt(y);
-        rad[2 * nr + i] = 0.5 * T * gw[i] * (1.0 + y);
+        rad[2 * nr + i] = dim == 4 ? dy * y : (dim == 3 ? dy * std::sqrt(y) : dy);
     }
 }
 
-void angular_tables(int na, int rule, std::vector<double> &ang, std::vector<float> &ang32,
-                    double *wmid)
+void angular_tables(int na, int rule, int dim, std::vector<double> &ang,
+                    std::vector<float> &ang32, double *wmid)
 {
     // Stored folded over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j), j
     // running over the positive nodes; an odd rule's middle node z = 0 keeps
-    // its weight apart.  Weights follow the normalised measure
-    // (2/pi) sqrt(1 - z^2) dz, so sum_j w_j = 1 for the Gauss rules.
+    // its weight apart.  Weights follow the normalised D-dimensional angular
+    // measure (1 - z^2)^{(D-3)/2} dz / N_D, N_D = pi (D = 2), 2 (D = 3),
+    // pi/2 (D = 4).  Each rule integrates g(z) against its own weight function
+    // omega(z) and is applied to g = f (1 - z^2)^{(D-3)/2} / omega.
     const int npair = na / 2;
     ang.assign(2 * (size_t)std::max(npair, 1), 0.0);
     ang32.assign(2 * (size_t)std::max(npair, 1), 0.0f);
     *wmid = 0.0;
+    const double norm = dim == 2 ? M_PI : (dim == 3 ? 2.0 : M_PI_2);
     auto put = [&](int j, double zsq, double w) {
         ang[2 * j] = zsq;
         ang[2 * j + 1] = 2.0 * w;
     };
+    // s^{D-2} for s = sin(theta) = sqrt(1 - z^2)
+    auto sinpow = [&](double s) { return dim == 4 ? s * s : (dim == 3 ? s : 1.0); };
     if (rule == GF_ANG_GC2) {
+        // omega = sqrt(1 - z^2): weights (pi/(n+1)) sin^2(theta) sin^{D-4}(theta)
         for (int j = 1; j <= npair; ++j) {
             const double th = j * M_PI / (na + 1);
             const double s = std::sin(th), c = std::cos(th);
-            put(j - 1, c * c, 2.0 * s * s / (na + 1));
+            put(j - 1, c * c, M_PI / (na + 1) * sinpow(s) / norm);
         }
-        if (na % 2 == 1) *wmid = 2.0 / (na + 1);
+        if (na % 2 == 1) *wmid = M_PI / (na + 1) / norm;
     } else if (rule == GF_ANG_GC1) {
+        // omega = 1/sqrt(1 - z^2): weights (pi/n) sin^{D-2}(theta)
         for (int j = 1; j <= npair; ++j) {
             const double th = (2 * j - 1) * M_PI / (2.0 * na);
             const double s = std::sin(th), c = std::cos(th);
-            put(j - 1, c * c, 2.0 * s * s / na);
+            put(j - 1, c * c, M_PI / na * sinpow(s) / norm);
         }
-        if (na % 2 == 1) *wmid = 2.0 / na;
+        if (na % 2 == 1) *wmid = M_PI / na / norm;
+    } else if (rule == GF_ANG_GL) {
+        // omega = 1: Gauss-Legendre weights times (1 - z^2)^{(D-3)/2}
+        std::vector<double> gx, gw;
+        gauss_legendre(na, gx, gw);
+        for (int j = 0; j < npair; ++j) {
+            const double z = gx[na - 1 - j];  // positive nodes, descending
+            const double s2 = 1.0 - z * z;
+            const double m = dim == 4 ? std::sqrt(s2) : (dim == 3 ? 1.0 : 1.0 / std::sqrt(s2));
+            put(j, z * z, gw[na - 1 - j] * m / norm);
+        }
+        if (na % 2 == 1) *wmid = gw[na / 2] / norm;
     } else {
-        // t_k = (k - (n-1)/2) h; the positive half is t = (m + (n odd ? 1 : 1/2)) h
-        const double h = 6.0 / (na - 1);
+        // tanh-sinh: z = tanh(u), u = (pi/2) sinh t, dz = (pi/2) cosh t / cosh^2 u dt,
+        // (1 - z^2)^{(D-3)/2} = cosh^{3-D} u; t_k = (k - (n-1)/2) h, h = 2 t_max/(n-1),
+        // t_max = 3, 3.5, 4 for D = 4, 3, 2 (the weight at t_max is below 1e-16)
+        const double tmax = dim == 4 ? 3.0 : (dim == 3 ? 3.5 : 4.0);
+        const double h = 2.0 * tmax / (na - 1);
         for (int j = 0; j < npair; ++j) {
             const double t = (na % 2 == 1) ? (j + 1) * h : (j + 0.5) * h;
             const double u = M_PI_2 * std::sinh(t);
             const double z = std::tanh(u), cu = std::cosh(u);
-            put(j, z * z, h * std::cosh(t) / (cu * cu * cu));
+            const double meas = dim == 4 ? 1.0 / (cu * cu * cu) : (dim == 3 ? 1.0 / (cu * cu) : 1.0 / cu);
+            put(j, z * z, h * M_PI_2 * std::cosh(t) * meas / norm);
         }
-        if (na % 2 == 1) *wmid = h;
+        if (na % 2 == 1) *wmid = h * M_PI_2 / norm;
     }
     for (size_t i = 0; i < ang.size(); ++i) ang32[i] = (float)ang[i];
 }
@@ -203,6 +227,7 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
     a.sy0_im = sy0.imag();
     a.scale = p.scale;
     a.n_taylor = p.taylor_order;
+    a.dim = p.dimension == 0 ? 4 : p.dimension;
     a.mu2 = p.mu2;
     // bad rays arg(-m1^2), arg(-m2^2) and the open sector (lo, hi) around the
     // positive real axis that the ray can sweep without crossing one
@@ -231,8 +256,9 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     if (q->precision != GF_PREC_FP64 && q->precision != GF_PREC_FP32C)
         return fail(GF_EINVAL, "precision must be GF_PREC_FP64 or GF_PREC_FP32C");
     if (q->angular_rule != GF_ANG_GC2 && q->angular_rule != GF_ANG_GC1 &&
-        q->angular_rule != GF_ANG_TANH_SINH)
-        return fail(GF_EINVAL, "angular_rule must be GF_ANG_GC2, GF_ANG_GC1 or GF_ANG_TANH_SINH");
+        q->angular_rule != GF_ANG_TANH_SINH && q->angular_rule != GF_ANG_GL)
+        return fail(GF_EINVAL,
+                    "angular_rule must be GF_ANG_GC2, GF_ANG_GC1, GF_ANG_TANH_SINH or GF_ANG_GL");
     if (q->angular_rule == GF_ANG_TANH_SINH && q->n_angular < 3)
         return fail(GF_EINVAL, "the tanh-sinh rule needs n_angular >= 3, got %d", q->n_angular);
     const double vals[] = {p->m1sq_re, p->m1sq_im, p->m2sq_re, p->m2sq_im,
@@ -243,10 +269,11 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     if (!(p->lambda2 <= 1e30)) return fail(GF_EINVAL, "lambda2 must be <= 1e30");
     if (!(p->mu2 >= 0.0)) return fail(GF_EINVAL, "mu2 must be >= 0");
     if (!(p->mu2 < p->lambda2)) return fail(GF_EINVAL, "mu2 must be below lambda2");
-    if (p->taylor_order < 0 || p->taylor_order > GF_MAX_TAYLOR)
-        return fail(GF_EINVAL, "taylor_order must be in [0, %d], got %d", GF_MAX_TAYLOR,
+    if (p->taylor_order < -1 || p->taylor_order > GF_MAX_TAYLOR)
+        return fail(GF_EINVAL, "taylor_order must be in [-1, %d], got %d", GF_MAX_TAYLOR,
                     p->taylor_order);
-    if (p->reserved != 0) return fail(GF_EINVAL, "reserved must be 0");
+    if (p->dimension != 0 && (p->dimension < 2 || p->dimension > 4))
+        return fail(GF_EINVAL, "dimension must be 2, 3, 4 or 0 (= 4), got %d", p->dimension);
     if (p->m1sq_im == 0.0 && p->m1sq_re <= 0.0)
         return fail(GF_EINVAL, "m1^2 must not lie on the non-positive real axis");
     if (p->m2sq_im == 0.0 && p->m2sq_re <= 0.0)
@@ -355,8 +382,9 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     std::vector<double> rad, ang, arc;
     std::vector<float> ang32;
     double wmid = 0.0;
-    gf::radial_table(quad->n_radial, params->lambda2, rad);
-    gf::angular_tables(quad->n_angular, quad->angular_rule, ang, ang32, &wmid);
+    const int dim = params->dimension == 0 ? 4 : params->dimension;
+    gf::radial_table(quad->n_radial, params->lambda2, dim, rad);
+    gf::angular_tables(quad->n_angular, quad->angular_rule, dim, ang, ang32, &wmid);
     gf::arc_table(quad->n_arc, arc);
 
     const size_t off_rad = 0;
@@ -412,7 +440,8 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     }
     e = gf::launch_jmu(a, params->mu2, d_jmu, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(plan->jmu, d_jmu, 2 * sizeof(double) * (params->taylor_order + 1),
+        e = hipMemcpyAsync(plan->jmu, d_jmu,
+                           2 * sizeof(double) * (std::max(params->taylor_order, 0) + 1),
                            hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
@@ -448,7 +477,8 @@ int gf_plan_jmu(const gf_plan_t *plan, double *re, double *im)
 int gf_plan_taylor(const gf_plan_t *plan, double *coeffs)
 {
     if (!plan || !coeffs) return fail(GF_EINVAL, "NULL argument");
-    for (int i = 0; i < 2 * (plan->params.taylor_order + 1); ++i) coeffs[i] = plan->jmu[i];
+    for (int i = 0; i < 2 * (std::max(plan->params.taylor_order, 0) + 1); ++i)
+        coeffs[i] = plan->jmu[i];
     return GF_OK;
 }
 
@@ -548,7 +578,7 @@ int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, doubl
 int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_samples, uint8_t *out,
                        void *stream)
 {
-    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2};
+    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2};  // the map needs no nodes
     int rc = gf::validate_params(params, &q1);
     if (rc != GF_OK) return rc;
     if ((rc = gf::validate_grid(*params, grid)) != GF_OK) return rc;

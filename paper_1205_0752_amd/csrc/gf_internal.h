@@ -24,7 +24,8 @@ constexpr double kRSlope = 0.45;
 // Everything a scan kernel needs, passed by value.
 struct ScanArgs {
     // Device tables:
-    //   rad: r[n_r], sqrt_r[n_r], w[n_r]   (y nodes of GL in log(1+y), dy weights), FP64
+    //   rad: r[n_r], sqrt_r[n_r], g[n_r]   (y nodes of GL in log(1+y), dy r^{(D-2)/2}
+    //                                       weights), FP64
     //   ang: (z^2, 2w) for the n_a/2 symmetric pairs of the GC-II rule, FP64
     //   arc: xi[n_arc], w[n_arc]           (GL on [-1, 1]), FP64
     //   ang32: the pair table rounded to FP32
@@ -40,7 +41,8 @@ struct ScanArgs {
     double sy0_re, sy0_im;               // sqrt(-m2^2) (residue node)
     const double *jmu;                   // device: Taylor coefficients K_0..K_n of the
                                          // subtraction at mu^2, (re, im) interleaved
-    int n_taylor;                        // n of t^n
+    int n_taylor;                        // n of t^n (-1: no subtraction)
+    int dim;                             // space-time dimension D (2, 3 or 4)
     double mu2;
     double scale;
 
@@ -99,9 +101,9 @@ const char *last_error();
 
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 // radial table [r | sqrt r | W], angular pair tables, arc table [xi | w]
-void radial_table(int n_r, double lambda2, std::vector<double> &rad);
-void angular_tables(int n_a, int rule, std::vector<double> &ang, std::vector<float> &ang32,
-                    double *wmid);
+void radial_table(int n_r, double lambda2, int dim, std::vector<double> &rad);
+void angular_tables(int n_a, int rule, int dim, std::vector<double> &ang,
+                    std::vector<float> &ang32, double *wmid);
 void arc_table(int n_arc, std::vector<double> &arc);
 // masses, cutoff, scale and contour geometry of a (params, quadrature)
 void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q);

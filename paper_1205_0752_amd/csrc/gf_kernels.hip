@@ -223,8 +223,9 @@ __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst,
         }
     }
     if (lane == 0) {
-        dst[0] = sr;
-        dst[1] = si;
+        // t^-1 (no subtraction) leaves K_0 = 0
+        dst[0] = a.n_taylor < 0 ? 0.0 : sr;
+        dst[1] = a.n_taylor < 0 ? 0.0 : si;
     }
 }
 

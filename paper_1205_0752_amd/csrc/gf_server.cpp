@@ -195,13 +195,15 @@ namespace {
 
 std::string key_radial(const gf_quadrature &q, const gf_params &p)
 {
-    std::string k = "r" + std::to_string(q.n_radial) + ":";
+    std::string k = "r" + std::to_string(q.n_radial) + ":" +
+                    std::to_string(p.dimension == 0 ? 4 : p.dimension) + ":";
     k.append(reinterpret_cast<const char *>(&p.lambda2), sizeof(double));
     return k;
 }
-std::string key_angular(const gf_quadrature &q)
+std::string key_angular(const gf_quadrature &q, const gf_params &p)
 {
-    return "a" + std::to_string(q.n_angular) + ":" + std::to_string(q.angular_rule);
+    return "a" + std::to_string(q.n_angular) + ":" + std::to_string(q.angular_rule) + ":" +
+           std::to_string(p.dimension == 0 ? 4 : p.dimension);
 }
 std::string key_arc(const gf_quadrature &q) { return "c" + std::to_string(q.n_arc); }
 
@@ -232,13 +234,14 @@ Table *gf_server::ensure_table(const std::string &key, const Request &r, bool *f
     Table t;
     if (key[0] == 'r') {
         std::vector<double> rad;
-        gf::radial_table(r.q.n_radial, r.p.lambda2, rad);
+        gf::radial_table(r.q.n_radial, r.p.lambda2, r.p.dimension == 0 ? 4 : r.p.dimension, rad);
         t.host.resize(rad.size() * sizeof(double));
         std::memcpy(t.host.data(), rad.data(), t.host.size());
     } else if (key[0] == 'a') {
         std::vector<double> ang;
         std::vector<float> ang32;
-        gf::angular_tables(r.q.n_angular, r.q.angular_rule, ang, ang32, &t.wmid);
+        gf::angular_tables(r.q.n_angular, r.q.angular_rule, r.p.dimension == 0 ? 4 : r.p.dimension,
+                           ang, ang32, &t.wmid);
         const size_t b64 = gf::align256(ang.size() * sizeof(double));
         t.host.assign(b64 + ang32.size() * sizeof(float), 0);
         std::memcpy(t.host.data(), ang.data(), ang.size() * sizeof(double));
@@ -584,7 +587,7 @@ int gf_server_submit(gf_server_t *s, const gf_params *params, const gf_grid *gri
                     r->out_bytes, s->arena.size());
     }
     r->keys[0] = key_radial(*quad, *params);
-    r->keys[1] = key_angular(*quad);
+    r->keys[1] = key_angular(*quad, *params);
     r->keys[2] = key_arc(*quad);
     // one lane per point: the batch already fills the GPU with many requests,
     // and whole 64-point tiles waste no lanes on short node lists

@@ -22,6 +22,7 @@ FP32C = 1
 GC2 = 0
 GC1 = 1
 TANH_SINH = 2
+GL = 3
 
 
 @dataclasses.dataclass(frozen=True)
@@ -29,14 +30,16 @@ class Params:
     """Integrand parameters: masses on the (p-k) leg (m1sq) and the k leg
     (m2sq), the real subtraction point mu2 >= 0, the cutoff Lambda^2 of eq. 14,
     the output scale (1.0 = rescaled units of eq. 18, 1/(16 pi^2) =
-    eq. 17) and the order n of the Taylor subtraction t^n (eq. 12-13, about
-    x = mu2)."""
+    eq. 17), the order n of the Taylor subtraction t^n (eq. 12-13, about
+    x = mu2; -1 subtracts nothing) and the dimension D of the integral (2, 3
+    or 4)."""
     m1sq: complex = 1.0
     m2sq: complex = 1.0
     mu2: float = 1.0
     lambda2: float = 1e4
     scale: float = 1.0
     taylor_order: int = 0
+    dimension: int = 4
 
 
 @dataclasses.dataclass(frozen=True)
@@ -59,7 +62,8 @@ class Grid:
 class Quadrature:
     """Node counts: Gauss-Legendre radial nodes in t = log(1+y), angular nodes
     of the rule `angular_rule` (GC2: Gauss-Chebyshev second kind, the default;
-    GC1: first kind; TANH_SINH: double exponential), Gauss-Legendre arc nodes;
+    GC1: first kind; TANH_SINH: double exponential; GL: Gauss-Legendre),
+    Gauss-Legendre arc nodes;
     precision FP64 or FP32C (FP32 bulk, FP64 at the sensitive steps)."""
     n_radial: int = 64
     n_angular: int = 32

@@ -84,7 +84,8 @@ def test_mirror_symmetry_with_taylor_subtraction():
 
 def test_library_rejects_bad_orders():
     import paper_1205_0752_amd as gf
-    for p in (Params(1.0, 1.0, 1.0, 1e6, 1.0, 9), Params(1.0, 1.0, 1.0, 1e6, 1.0, -1)):
+    for p in (Params(1.0, 1.0, 1.0, 1e6, 1.0, 9), Params(1.0, 1.0, 1.0, 1e6, 1.0, -2),
+              Params(1.0, 1.0, 1.0, 1e6, 1.0, 0, 5)):
         with pytest.raises(gf.GFError) as e:
             gf.Plan(p, Quadrature(32, 16, 8))
         assert e.value.code == -1
