@@ -127,7 +127,8 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
             "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}, "
-                      f"{'true' if getattr(params, 'taylor_order', 0) > 0 else 'false'}>"}
+                      f"{'true' if getattr(params, 'taylor_order', 0) > 0 else 'false'}, "
+                      f"{'true' if getattr(quad, 'radial_split', 0) else 'false'}>"}
 
 
 def time_launches(torch, fn, reps):
@@ -177,6 +178,13 @@ def extensions(gf, torch):
     out["tanh_sinh_scan"] = {"workload": "bench box and radial/arc nodes, 129 tanh-sinh angular nodes",
                              "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
                              "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS}
+    t = time_scan(gf, torch, p, g, dataclasses.replace(q, radial_split=1), 5, 1, 0)
+    out["split_radial_scan"] = {"workload": "bench workload with the split radial rule "
+                                            "(4 pieces of 64 nodes per point)",
+                                "ms": t["ms"], "evals_per_s": t["evals_per_s"],
+                                "tflops": t["tflops"],
+                                "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS,
+                                "kernel": t["kernel"]}
     t = time_scan(gf, torch, dataclasses.replace(p, taylor_order=2), g, q, 5, 1, 0)
     out["taylor2_scan"] = {"workload": "bench workload with the subtraction t^2 about mu^2",
                            "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],

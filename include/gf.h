@@ -118,13 +118,23 @@ typedef struct {
 /* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
  * n_angular angular nodes (1..8192; >= 3 for tanh-sinh) of the rule
  * angular_rule (GF_ANG_*), n_arc Gauss-Legendre nodes on the closing arc
- * (0..1024; 0 drops the arc), precision GF_PREC_*. */
+ * (0..1024; 0 drops the arc), precision GF_PREC_*.  radial_split = 1 uses,
+ * like the paper's several sub-contour node arrays (section "Numerical
+ * Implementation"), four Gauss-Legendre pieces of n_radial/4 nodes each
+ * (n_radial a multiple of 4) along the straight part of every point's
+ * contour, cut in t = log(1+|y|) at the point's near-singular radii: the
+ * moduli |(sqrt(x) +- sqrt(-m1^2))^2| of the angular cut's end points (eq. 25
+ * at z = +-1) and |m2^2| of the k-leg pole, those inside (0, Lambda^2), cuts
+ * within 1e-9 T (T = log(1 + Lambda^2)) of each other counted once; while
+ * fewer than three cuts exist, the longest piece (by more than 1e-12 T, the
+ * first on ties) is halved.  The subtraction sums use the cuts of x = mu^2. */
 typedef struct {
     int32_t n_radial;
     int32_t n_angular;
     int32_t n_arc;
     int32_t precision;
     int32_t angular_rule;
+    int32_t radial_split;
 } gf_quadrature;
 
 /* Cell-centred n_re x n_im box (STEP 4): point (a, b), 0 <= a < n_re,

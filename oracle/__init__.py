@@ -33,7 +33,8 @@ class _Problem(ctypes.Structure):
                 ("scale", ctypes.c_double),
                 ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
                 ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int),
-                ("taylor_order", ctypes.c_int), ("dimension", ctypes.c_int)]
+                ("taylor_order", ctypes.c_int), ("dimension", ctypes.c_int),
+                ("radial_split", ctypes.c_int)]
 
 
 def build(verbose: bool = False) -> None:
@@ -82,6 +83,8 @@ def _load():
                                         ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p]
         lib.orc_taylor.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, dp,
                                    ctypes.POINTER(ctypes.c_double)]
+        lib.orc_radial_nodes_at.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double,
+                                            ctypes.c_double, dp, dp]
         lib.orc_yscan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_long, dp, dp, ctypes.c_int, dp]
         _lib = lib
@@ -113,7 +116,8 @@ def problem(params, quad) -> _Problem:
                     int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
                     int(getattr(quad, "angular_rule", 0)),
                     int(getattr(params, "taylor_order", 0)),
-                    int(getattr(params, "dimension", 4)))
+                    int(getattr(params, "dimension", 4)),
+                    int(getattr(quad, "radial_split", 0)))
 
 
 # ---------------------------------------------------------------- rules
@@ -230,8 +234,9 @@ def scan(params, quad, grid, want_cond: bool = False):
 def eval_points_q(params, quad, x):
     """Quad-precision brute force of the same quadrature (Gauss-Chebyshev II
     angular rule only).  Returns (g, cls)."""
-    if getattr(quad, "angular_rule", 0) != 0 or getattr(params, "taylor_order", 0) != 0:
-        raise ValueError("the quad-precision twin implements the GC-II rule and t^0 only")
+    if (getattr(quad, "angular_rule", 0) != 0 or getattr(params, "taylor_order", 0) != 0
+            or getattr(params, "dimension", 4) not in (0, 4) or getattr(quad, "radial_split", 0)):
+        raise ValueError("the quad-precision twin implements GC-II, t^0, D = 4, unsplit only")
     lib = _loadq()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
     xr = np.ascontiguousarray(x.real)
@@ -283,6 +288,17 @@ def taylor(params, quad, n: int):
                           ctypes.byref(rho)) != 0:
         raise ValueError("bad problem or order")
     return out[0::2] + 1j * out[1::2], rho.value
+
+
+def radial_nodes(params, quad, x: complex):
+    """Radial nodes r_i and dy weights of the straight part of x's contour."""
+    r = np.zeros(quad.n_radial)
+    w = np.zeros(quad.n_radial)
+    x = complex(x)
+    if _load().orc_radial_nodes_at(ctypes.byref(problem(params, quad)), x.real, x.imag, _dp(r),
+                                   _dp(w)) != 0:
+        raise ValueError("bad problem")
+    return r, w
 
 
 def threads() -> int:

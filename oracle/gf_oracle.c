@@ -73,6 +73,7 @@ typedef struct {
     int angular_rule;          /* 0 GC-II, 1 GC-I, 2 tanh-sinh */
     int taylor_order;          /* n of the subtraction operator t^n (eq. 13), -1..8 */
     int dimension;             /* D = 2, 3 or 4 (0 means 4) */
+    int radial_split;          /* 1: split the radial rule at the near-singular radii */
 } orc_problem;
 
 #define ORC_MAX_TAYLOR 8
@@ -369,6 +370,7 @@ typedef struct {
     double *arc_x, *arc_w;   /* arc GL on [-1,1] */
     double *z, *w;           /* GC-II */
     double *r, *wr;          /* radial nodes y = r_i, dy weights (incl. Jacobian) */
+    double *seg_x, *seg_w;   /* split rule: GL of order n_radial/4 on [-1,1] */
     cplx jmu;                /* subtraction term: real-axis sum at x = mu^2 */
     double jmu_abs;
     cplx taylor[ORC_MAX_TAYLOR + 1]; /* K_i, i >= 1: (1/i!) d^i/dx^i of that sum at mu^2 */
@@ -383,23 +385,91 @@ static cplx orc_measure(int dim, cplx y, cplx sy)
     return dim == 4 ? y : (dim == 3 ? sy : 1.0);
 }
 
-static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, double *absum)
+/* Radial nodes r_i and dy weights (Jacobian included) along the straight part
+ * of the contour of the point xn.  Without splitting: the plan's GL rule in
+ * t = log(1+r) on [0, T], T = log(1 + Lambda^2).  Split (the paper's several
+ * sub-contours, section "Numerical Implementation"): [0, T] is cut at
+ * t = log(1 + rho) for the radii rho in (0, Lambda^2) where the integrand has
+ * near-singularities -- the moduli of the angular cut's end points
+ * y(z = +-1) = (sqrt(xn) +- sqrt(-m1^2))^2 (eq. 25 at theta = 0, pi) and of
+ * the k-leg pole y = -m2^2 -- and, while fewer than three cuts exist, at the
+ * midpoint of the longest piece; each of the four pieces gets n_radial/4 GL
+ * nodes.  Tolerances (duplicates within 1e-9 T, "longest" by more than
+ * 1e-12 T) keep near-ties decided alike under any rounding. */
+static void orc_radial_nodes(const orc_ctx *c, cplx xn, double *r, double *wr)
+{
+    const orc_problem *p = c->p;
+    if (!p->radial_split) {
+        memcpy(r, c->r, sizeof(double) * p->n_radial);
+        memcpy(wr, c->wr, sizeof(double) * p->n_radial);
+        return;
+    }
+    double T = log1p(p->lambda2);
+    cplx sm = csqrt(-c->geo.m1sq), sx = csqrt(xn);
+    double cand[3] = {cabs((sx + sm) * (sx + sm)), cabs((sx - sm) * (sx - sm)), cabs(c->geo.m2sq)};
+    double b[5];
+    int nb = 0;
+    b[nb++] = 0.0;
+    b[nb++] = T;
+    /* cuts within 1e-9 T of one another count once */
+    for (int k = 0; k < 3; ++k) {
+        if (!(cand[k] > 0.0 && cand[k] < p->lambda2)) continue;
+        double t = log1p(cand[k]);
+        int dup = 0;
+        for (int q = 0; q < nb; ++q) dup |= fabs(b[q] - t) <= 1e-9 * T;
+        if (!dup) b[nb++] = t;
+    }
+    /* sort the boundaries (at most five) */
+    for (int i = 1; i < nb; ++i)
+        for (int j = i; j > 0 && b[j - 1] > b[j]; --j) {
+            double tmp = b[j];
+            b[j] = b[j - 1];
+            b[j - 1] = tmp;
+        }
+    while (nb < 5) {
+        int wide = 0;
+        /* the longest piece, the first one unless another is longer by 1e-12 T */
+        for (int i = 1; i < nb - 1; ++i)
+            if (b[i + 1] - b[i] > b[wide + 1] - b[wide] + 1e-12 * T) wide = i;
+        double mid = 0.5 * (b[wide] + b[wide + 1]);
+        for (int j = nb; j > wide + 1; --j) b[j] = b[j - 1];
+        b[wide + 1] = mid;
+        ++nb;
+    }
+    int m = p->n_radial / 4;
+    for (int s = 0; s < 4; ++s)
+        for (int i = 0; i < m; ++i) {
+            double h = 0.5 * (b[s + 1] - b[s]);
+            double t = b[s] + h * (c->seg_x[i] + 1.0);
+            r[s * m + i] = expm1(t);
+            wr[s * m + i] = h * c->seg_w[i] * (1.0 + r[s * m + i]);
+        }
+}
+
+/* The contour sum of the point x (class cls); the straight part's nodes are
+ * those of the point xn (x itself, or mu^2 for the subtraction sums). */
+static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_sign,
+                            double *absum)
 {
     const int dim = orc_dim(c->p);
     const orc_problem *p = c->p;
     cplx m1sq = c->geo.m1sq, m2sq = c->geo.m2sq;
     cplx sx = csqrt(x);
     cplx s = 0.0;
+    double *rn = malloc(sizeof(double) * p->n_radial), *wn = malloc(sizeof(double) * p->n_radial);
+    orc_radial_nodes(c, xn, rn, wn);
     if (cls == ORC_R) {
         for (int i = 0; i < p->n_radial; ++i) {
-            cplx y = c->r[i];
-            cplx sy = sqrt(c->r[i]);
+            cplx y = rn[i];
+            cplx sy = sqrt(rn[i]);
             double a = 0.0;
             cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-            cplx pre = c->wr[i] * orc_measure(dim, y, sy) / (y + m2sq);
+            cplx pre = wn[i] * orc_measure(dim, y, sy) / (y + m2sq);
             s += pre * ang;
             if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
         }
+        free(rn);
+        free(wn);
         return s;
     }
     /* ray at the angle of x: y = r e^{i phi}, dy = e^{i phi} dr */
@@ -407,11 +477,11 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
     cplx e = cexp(I * phi);
     cplx eh = cexp(I * 0.5 * phi);
     for (int i = 0; i < p->n_radial; ++i) {
-        cplx y = e * c->r[i];
-        cplx sy = eh * sqrt(c->r[i]);
+        cplx y = e * rn[i];
+        cplx sy = eh * sqrt(rn[i]);
         double a = 0.0;
         cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx pre = e * c->wr[i] * orc_measure(dim, y, sy) / (y + m2sq);
+        cplx pre = e * wn[i] * orc_measure(dim, y, sy) / (y + m2sq);
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
     }
@@ -439,6 +509,8 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, int cls, int res_sign, dou
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a;
     }
+    free(rn);
+    free(wn);
     return s;
 }
 
@@ -486,13 +558,13 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
             if (cond) *cond = NAN;
             return ORC_SINGULAR;
         }
-        s = orc_contour_sum(c, xb, cb, sb, pab);
+        s = orc_contour_sum(c, xb, xb, cb, sb, pab);
         cplx gb = c->p->scale * (s - orc_subtraction(c, xb, pab));
         *g = conj(gb);
         if (cond) *cond = c->p->scale * absum / cabs(gb);
         return cls;
     }
-    s = orc_contour_sum(c, x, cls, sign, pab);
+    s = orc_contour_sum(c, x, x, cls, sign, pab);
     *g = c->p->scale * (s - orc_subtraction(c, x, pab));
     if (cond) *cond = c->p->scale * absum / cabs(*g);
     return cls;
@@ -512,20 +584,24 @@ static double orc_taylor_cauchy(const orc_ctx *c, int n, cplx *K)
 {
     const orc_problem *p = c->p;
     double dmin = INFINITY;
+    double *rn = malloc(sizeof(double) * p->n_radial), *wn = malloc(sizeof(double) * p->n_radial);
+    orc_radial_nodes(c, p->mu2, rn, wn);
     for (int i = 0; i < p->n_radial; ++i) {
-        cplx sy = sqrt(c->r[i]);
+        cplx sy = sqrt(rn[i]);
         for (int j = 0; j < p->n_angular; ++j) {
-            cplx root = csqrt(c->r[i] * c->z[j] * c->z[j] - c->r[i] - c->geo.m1sq);
+            cplx root = csqrt(rn[i] * c->z[j] * c->z[j] - rn[i] - c->geo.m1sq);
             cplx s1 = sy * c->z[j] + root, s2 = sy * c->z[j] - root;
             dmin = fmin(dmin, fmin(cabs(s1 * s1 - p->mu2), cabs(s2 * s2 - p->mu2)));
         }
     }
+    free(rn);
+    free(wn);
     double rho = 0.5 * dmin;
     const int N = 64;
     for (int i = 0; i <= n; ++i) K[i] = 0.0;
     for (int k = 0; k < N; ++k) {
         cplx e = cexp(I * 2.0 * M_PI * k / N);
-        cplx S = orc_contour_sum(c, p->mu2 + rho * e, ORC_R, 0, NULL);
+        cplx S = orc_contour_sum(c, p->mu2 + rho * e, p->mu2, ORC_R, 0, NULL);
         for (int i = 0; i <= n; ++i) K[i] += S * cpow(rho * e, -i) / N;
     }
     return rho;
@@ -548,6 +624,15 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     c->w = malloc(sizeof(double) * na);
     orc_gauss_legendre(nr, c->gl_t, c->gl_w);
     if (p->n_arc > 0) orc_gauss_legendre(p->n_arc, c->arc_x, c->arc_w);
+    if (p->radial_split) {
+        if (nr % 4 != 0) {
+            orc_ctx_free(c);
+            return -1;
+        }
+        c->seg_x = malloc(sizeof(double) * (nr / 4));
+        c->seg_w = malloc(sizeof(double) * (nr / 4));
+        orc_gauss_legendre(nr / 4, c->seg_x, c->seg_w);
+    }
     if (orc_angular_rule_dim(p->angular_rule, orc_dim(p), na, c->z, c->w) != 0) {
         orc_ctx_free(c);
         return -1;
@@ -561,7 +646,7 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     }
     /* subtraction term (eq. 14 at x = mu^2, real axis) */
     double a = 0.0;
-    c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, ORC_R, 0, &a);
+    c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, p->mu2, ORC_R, 0, &a);
     c->jmu_abs = a;
     if (p->taylor_order < -1 || p->taylor_order > ORC_MAX_TAYLOR) {
         orc_ctx_free(c);
@@ -575,6 +660,7 @@ static void orc_ctx_free(orc_ctx *c)
 {
     free(c->gl_t); free(c->gl_w); free(c->r); free(c->wr);
     free(c->arc_x); free(c->arc_w); free(c->z); free(c->w);
+    free(c->seg_x); free(c->seg_w);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -843,5 +929,18 @@ int orc_obstruction(const orc_problem *p, long n, const double *x_re, const doub
         out[k] = (unsigned char)v;
         tie[k] = (unsigned char)t;
     }
+    return 0;
+}
+
+/* The radial nodes and dy weights the straight part of the contour of x uses
+ * (exported for the pin tests of the split rule). */
+int orc_radial_nodes_at(const orc_problem *p, double x_re, double x_im, double *r, double *w)
+{
+    orc_ctx c;
+    orc_problem q = *p;
+    q.taylor_order = 0;
+    if (orc_ctx_init(&c, &q) != 0) return -1;
+    orc_radial_nodes(&c, x_re + I * x_im, r, w);
+    orc_ctx_free(&c);
     return 0;
 }

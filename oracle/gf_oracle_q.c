@@ -23,6 +23,8 @@ typedef struct {
     int n_radial, n_angular, n_arc;
     int angular_rule;   /* only 0 (Gauss-Chebyshev II) is implemented here */
     int taylor_order;   /* only 0 is implemented here */
+    int dimension;      /* only 4 (or 0) is implemented here */
+    int radial_split;   /* only 0 is implemented here */
 } orcq_problem;   /* same layout as the FP64 oracle's problem struct */
 
 #define QPI M_PIq

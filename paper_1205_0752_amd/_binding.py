@@ -54,7 +54,7 @@ class _Params(ctypes.Structure):
 class _Quad(ctypes.Structure):
     _fields_ = [("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32),
                 ("n_arc", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("angular_rule", ctypes.c_int32)]
+                ("angular_rule", ctypes.c_int32), ("radial_split", ctypes.c_int32)]
 
 
 class _Grid(ctypes.Structure):
@@ -143,7 +143,7 @@ def c_params(p: Params) -> _Params:
 
 def c_quad(q: Quadrature) -> _Quad:
     return _Quad(int(q.n_radial), int(q.n_angular), int(q.n_arc), int(q.precision),
-                 int(q.angular_rule))
+                 int(q.angular_rule), int(getattr(q, "radial_split", 0)))
 
 
 def c_grid(g: Grid) -> _Grid:

@@ -129,14 +129,64 @@ struct PointCtx {
     double phi;
     int nodes;  // contour nodes of this point
     int res_sign;
+    double tb[5];  // split radial rule: piece boundaries in t = log(1+r)
 };
 
+// Split radial rule: the straight part [0, T] in t = log(1+r) is cut at the
+// radii where the integrand is nearly singular -- |(sqrt x +- sqrt(-m1^2))^2|,
+// the moduli of the angular cut's end points (eq. 25 at z = +-1), and |m2^2|,
+// the k-leg pole's -- then, while fewer than three cuts exist, at the middle
+// of the longest piece; each of the four pieces carries n_r/4 GL nodes.  Cuts
+// within 1e-9 T of one another count once, and a piece only replaces the
+// longest one found so far if longer by 1e-12 T, so near-ties are decided the
+// same way whatever the rounding.
 template <class Args>
+__device__ void split_boundaries(const Args &a, double xr, double xi, double *b)
+{
+    const cd sx = csqrt_principal(xr, xi);
+    const cd sp = cadd(sx, mk(a.sm1_re, a.sm1_im)), sn = mk(sx.r - a.sm1_re, sx.i - a.sm1_im);
+    const double cand[3] = {sp.r * sp.r + sp.i * sp.i, sn.r * sn.r + sn.i * sn.i,
+                            sqrt(a.m2_re * a.m2_re + a.m2_im * a.m2_im)};
+    const double T = a.T, tol = 1e-9 * T;
+    int nb = 2;
+    b[0] = 0.0;
+    b[1] = T;
+    for (int k = 0; k < 3; ++k) {
+        if (!(cand[k] > 0.0 && cand[k] < a.lam2)) continue;
+        const double t = log1p(cand[k]);
+        bool dup = false;
+        for (int q = 0; q < nb; ++q) dup = dup || fabs(b[q] - t) <= tol;
+        if (!dup) {
+            int j = nb++;
+            while (j > 0 && b[j - 1] > t) {  // insertion keeps b sorted
+                b[j] = b[j - 1];
+                --j;
+            }
+            b[j] = t;
+        }
+    }
+    while (nb < 5) {
+        int wide = 0;
+        for (int i = 1; i < nb - 1; ++i)
+            if (b[i + 1] - b[i] > b[wide + 1] - b[wide] + 1e-12 * T) wide = i;
+        for (int j = nb; j > wide + 1; --j) b[j] = b[j - 1];
+        b[wide + 1] = 0.5 * (b[wide] + b[wide + 2]);
+        ++nb;
+    }
+}
+
+template <bool SPLIT = false, class Args>
 __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign)
 {
     PointCtx P;
     P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
     P.res_sign = res_sign;
+    if (SPLIT) {
+        double b[5];
+        split_boundaries(a, xr, xi, b);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) P.tb[i] = b[i];
+    }
     if (cls == kY || cls == kYRes) {
         double phi = atan2(xi, xr);
         double s, c;
@@ -167,7 +217,34 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
 // y for D = 4), or +-2 pi i y0^{(D-2)/2} at the residue.  Along the ray
 // y = e^{i phi} r, dy y^{(D-2)/2} = e^{i phi D/2} dr r^{(D-2)/2}; the table holds
 // the real weight dr r^{(D-2)/2}.
-template <class Args>
+// Radial node k of the straight part: r and the real weight dr r^{(D-2)/2}.
+// Unsplit, from the plan's table; split, from the base GL rule of order n_r/4
+// (table: xi[m], w[m]) mapped onto piece k / m of the point's boundaries.
+template <bool SPLIT, class Args>
+__device__ __forceinline__ void radial_node(const Args &a, const PointCtx &P, int k, double &r,
+                                            double &g)
+{
+    const auto *rad = ro(a.rad);
+    if (!SPLIT) {
+        r = rad[k];
+        g = rad[2 * a.n_r + k];
+        return;
+    }
+    const int m = a.n_r >> 2;
+    const int s = k / m, i = k - s * m;
+    double lo = P.tb[0], hi = P.tb[1];
+    for (int q = 1; q <= 3; ++q)  // select piece s without indexing registers dynamically
+        if (s == q) {
+            lo = P.tb[q];
+            hi = P.tb[q + 1];
+        }
+    const double h = 0.5 * (hi - lo);
+    r = expm1(fma(h, rad[i] + 1.0, lo));
+    const double dr = h * rad[m + i] * (1.0 + r);
+    g = a.dim == 4 ? dr * r : (a.dim == 3 ? dr * sqrt(r) : dr);
+}
+
+template <bool SPLIT = false, class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V2, cd &w)
 {
@@ -176,9 +253,8 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
     // registers live across the node loop than carrying it)
     const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
     if (k < a.n_r) {
-        const auto *rad = ro(a.rad);
-        const double r = rad[k];
-        const double g = rad[2 * a.n_r + k];
+        double r, g;
+        radial_node<SPLIT>(a, P, k, r, g);
         const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
         U = cadd(P.x1, y);
         V2 = cmul(x4, y);                                      // 4 x y

@@ -117,8 +117,20 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     if (n % 2 == 1) x[n / 2] = 0.0;  // exact centre node
 }
 
-void radial_table(int nr, double lambda2, int dim, std::vector<double> &rad)
+void radial_table(int nr, double lambda2, int dim, int split, std::vector<double> &rad)
 {
+    if (split) {
+        // base rule of the four pieces: GL of order n_r/4 on [-1, 1], (xi | w)
+        std::vector<double> gx, gw;
+        const int m = nr / 4;
+        gauss_legendre(m, gx, gw);
+        rad.assign(3 * (size_t)nr, 0.0);
+        for (int i = 0; i < m; ++i) {
+            rad[i] = gx[i];
+            rad[m + i] = gw[i];
+        }
+        return;
+    }
     // GL in t = log(1+y) on [0, T], y = e^t - 1, dy = (1 + y) dt; the weight
     // column carries the radial measure y^{(D-2)/2} of D dimensions
     std::vector<double> gx, gw;
@@ -228,6 +240,11 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
     a.scale = p.scale;
     a.n_taylor = p.taylor_order;
     a.dim = p.dimension == 0 ? 4 : p.dimension;
+    a.split = q.radial_split;
+    a.T = std::log1p(p.lambda2);
+    const std::complex<double> sm1 = std::sqrt(std::complex<double>(-p.m1sq_re, -p.m1sq_im));
+    a.sm1_re = sm1.real();
+    a.sm1_im = sm1.imag();
     a.mu2 = p.mu2;
     // bad rays arg(-m1^2), arg(-m2^2) and the open sector (lo, hi) around the
     // positive real axis that the ray can sweep without crossing one
@@ -259,6 +276,10 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
         q->angular_rule != GF_ANG_TANH_SINH && q->angular_rule != GF_ANG_GL)
         return fail(GF_EINVAL,
                     "angular_rule must be GF_ANG_GC2, GF_ANG_GC1, GF_ANG_TANH_SINH or GF_ANG_GL");
+    if (q->radial_split != 0 && q->radial_split != 1)
+        return fail(GF_EINVAL, "radial_split must be 0 or 1");
+    if (q->radial_split && q->n_radial % 4 != 0)
+        return fail(GF_EINVAL, "radial_split needs n_radial divisible by 4, got %d", q->n_radial);
     if (q->angular_rule == GF_ANG_TANH_SINH && q->n_angular < 3)
         return fail(GF_EINVAL, "the tanh-sinh rule needs n_angular >= 3, got %d", q->n_angular);
     const double vals[] = {p->m1sq_re, p->m1sq_im, p->m2sq_re, p->m2sq_im,
@@ -383,7 +404,7 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
     std::vector<float> ang32;
     double wmid = 0.0;
     const int dim = params->dimension == 0 ? 4 : params->dimension;
-    gf::radial_table(quad->n_radial, params->lambda2, dim, rad);
+    gf::radial_table(quad->n_radial, params->lambda2, dim, quad->radial_split, rad);
     gf::angular_tables(quad->n_angular, quad->angular_rule, dim, ang, ang32, &wmid);
     gf::arc_table(quad->n_arc, arc);
 
@@ -578,7 +599,7 @@ int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, doubl
 int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_samples, uint8_t *out,
                        void *stream)
 {
-    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2};  // the map needs no nodes
+    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2, 0};  // the map needs no nodes
     int rc = gf::validate_params(params, &q1);
     if (rc != GF_OK) return rc;
     if ((rc = gf::validate_grid(*params, grid)) != GF_OK) return rc;

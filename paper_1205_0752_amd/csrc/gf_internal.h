@@ -43,6 +43,9 @@ struct ScanArgs {
                                          // subtraction at mu^2, (re, im) interleaved
     int n_taylor;                        // n of t^n (-1: no subtraction)
     int dim;                             // space-time dimension D (2, 3 or 4)
+    int split;                           // split radial rule (rad then holds GL xi, w)
+    double T;                            // log(1 + Lambda^2)
+    double sm1_re, sm1_im;               // sqrt(-m1^2), principal
     double mu2;
     double scale;
 
@@ -88,9 +91,11 @@ hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double
                             hipStream_t s);
 
 // Persistent launch of `waves` wavefronts over n_items work items (device
-// arrays); *counter must be 0 on entry.  All items share precision and lanes.
+// arrays); *counter must be 0 on entry.  All items share precision, lanes and
+// the split flag of the radial rule.
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
-                        unsigned *counter, int precision, int lanes, int waves, hipStream_t s);
+                        unsigned *counter, int precision, int lanes, int split, int waves,
+                        hipStream_t s);
 
 // ---- host helpers shared by plans and the server (gf_host.cpp) ----------
 
@@ -101,7 +106,7 @@ const char *last_error();
 
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 // radial table [r | sqrt r | W], angular pair tables, arc table [xi | w]
-void radial_table(int n_r, double lambda2, int dim, std::vector<double> &rad);
+void radial_table(int n_r, double lambda2, int dim, int split, std::vector<double> &rad);
 void angular_tables(int n_a, int rule, int dim, std::vector<double> &ang,
                     std::vector<float> &ang32, double *wmid);
 void arc_table(int n_arc, std::vector<double> &arc);

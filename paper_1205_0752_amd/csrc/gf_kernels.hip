@@ -24,7 +24,7 @@ namespace {
 // point's result does not depend on which launch computes it.
 // TAYLOR = false compiles out the t^n (n >= 1) epilogue, so the order-0 scan
 // carries no extra live values; both forms compute order 0 identically.
-template <int PREC, int L, bool TAYLOR, class Args>
+template <int PREC, int L, bool TAYLOR, bool SPLIT, class Args>
 __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 {
     constexpr int P = 64 / L;
@@ -49,12 +49,12 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
             ecls = kSingular;
         }
     }
-    const PointCtx pc = point_setup(a, xr, xi, ecls, sign);
+    const PointCtx pc = point_setup<SPLIT>(a, xr, xi, ecls, sign);
 
     double sr = 0.0, si = 0.0;
     for (int k = s; k < pc.nodes; k += L) {
         cd U, V2, w;
-        node_coeffs(a, pc, k, U, V2, w);
+        node_coeffs<SPLIT>(a, pc, k, U, V2, w);
         cd A = angular_sum<PREC>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
@@ -96,28 +96,28 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
 // Register budgets: the FP64 kernel runs best at 5 waves per SIMD, the FP32C
 // kernel at 6 (measured; the few spills this costs sit outside the inner loop).
-template <int L, bool TAYLOR>
+template <int L, bool TAYLOR, bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<0, L, TAYLOR>(a, wave, threadIdx.x & 63);
+    process_tile<0, L, TAYLOR, SPLIT>(a, wave, threadIdx.x & 63);
 }
 
-template <int L, bool TAYLOR>
+template <int L, bool TAYLOR, bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<1, L, TAYLOR>(a, wave, threadIdx.x & 63);
+    process_tile<1, L, TAYLOR, SPLIT>(a, wave, threadIdx.x & 63);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
 // many requests.  Each wave takes the next item from a device counter (one
 // lane's atomic, broadcast) until the list is exhausted, so every wave exits.
-template <int PREC, int L>
+template <int PREC, int L, bool SPLIT>
 __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem *items, int n_items,
                                            unsigned *counter)
 {
@@ -129,24 +129,24 @@ __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem 
         if (w >= (unsigned)n_items) break;
         const int req = ro(items)[w].req;
         const int tile = ro(items)[w].tile;
-        process_tile<PREC, L, true>(ro(reqs)[req], tile, lane);
+        process_tile<PREC, L, true, SPLIT>(ro(reqs)[req], tile, lane);
     }
 }
 
-template <int L>
+template <int L, bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 serve_kernel_fp64(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
                   int n_items, unsigned *counter)
 {
-    serve_loop<0, L>(reqs, items, n_items, counter);
+    serve_loop<0, L, SPLIT>(reqs, items, n_items, counter);
 }
 
-template <int L>
+template <int L, bool SPLIT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 serve_kernel_fp32c(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
                    int n_items, unsigned *counter)
 {
-    serve_loop<1, L>(reqs, items, n_items, counter);
+    serve_loop<1, L, SPLIT>(reqs, items, n_items, counter);
 }
 
 // Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
@@ -190,21 +190,25 @@ __device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd 
 // wavefront: K_0 = the subtraction sum of eq. 14 (the order-0 operator t^0),
 // and for t^n with n >= 1 the Taylor coefficients K_i = (1/i!) d^i/dx^i of the
 // same sum (eq. 13 about x = mu^2).
-template <class Args>
-__device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
+template <bool SPLIT, class Args>
+__device__ __forceinline__ void jmu_wave_impl(const Args &a, double mu2, double *dst, int lane)
 {
-    const PointCtx pc = point_setup(a, mu2, 0.0, kR, 0);
+    const PointCtx pc = point_setup<SPLIT>(a, mu2, 0.0, kR, 0);
     double sr = 0.0, si = 0.0;
     cd acc[GF_MAX_TAYLOR + 1];
     for (int i = 0; i <= GF_MAX_TAYLOR; ++i) acc[i] = mk(0.0, 0.0);
     for (int k = lane; k < pc.nodes; k += 64) {
         cd U, V2, w;
-        node_coeffs(a, pc, k, U, V2, w);
+        node_coeffs<SPLIT>(a, pc, k, U, V2, w);
         cd A = angular_sum<0>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
-        if (a.n_taylor > 0) taylor_node(a, U, ro(a.rad)[k], w, a.n_taylor, acc);
+        if (a.n_taylor > 0) {
+            double r, g;
+            radial_node<SPLIT>(a, pc, k, r, g);
+            taylor_node(a, U, r, w, a.n_taylor, acc);
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -229,6 +233,15 @@ __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst,
     }
 }
 
+template <class Args>
+__device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
+{
+    if (a.split)
+        jmu_wave_impl<true>(a, mu2, dst, lane);
+    else
+        jmu_wave_impl<false>(a, mu2, dst, lane);
+}
+
 __global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double *dst)
 {
     jmu_wave(a, mu2, dst, threadIdx.x);
@@ -249,17 +262,26 @@ template <int L>
 hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
     const int blocks = (a.n_tiles + 3) / 4;
-    const bool taylor = a.n_taylor > 0;
+    const bool taylor = a.n_taylor > 0, split = a.split != 0;
+    const dim3 g(blocks), b(256);
     if (precision == 0) {
-        if (taylor)
-            hipLaunchKernelGGL((scan_kernel_fp64<L, true>), dim3(blocks), dim3(256), 0, s, a);
+        if (taylor && split)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true, true>), g, b, 0, s, a);
+        else if (taylor)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true, false>), g, b, 0, s, a);
+        else if (split)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, false, true>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((scan_kernel_fp64<L, false>), dim3(blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp64<L, false, false>), g, b, 0, s, a);
     } else if (precision == 1) {
-        if (taylor)
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, true>), dim3(blocks), dim3(256), 0, s, a);
+        if (taylor && split)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, true>), g, b, 0, s, a);
+        else if (taylor)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, false>), g, b, 0, s, a);
+        else if (split)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, true>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, false>), dim3(blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, false>), g, b, 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -268,20 +290,29 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 
 template <int L>
 hipError_t serve_l(const ScanArgs *reqs, const WorkItem *items, int n_items, unsigned *counter,
-                   int precision, int waves, hipStream_t s)
+                   int precision, int split, int waves, hipStream_t s)
 {
-    const int blocks = (waves + 3) / 4;
+    const dim3 g((waves + 3) / 4), b(256);
     if (precision == 0) {
-        hipLaunchKernelGGL(serve_kernel_fp64<L>, dim3(blocks), dim3(256), 0, s, reqs, items,
-                           n_items, counter);
+        if (split)
+            hipLaunchKernelGGL((serve_kernel_fp64<L, true>), g, b, 0, s, reqs, items, n_items,
+                               counter);
+        else
+            hipLaunchKernelGGL((serve_kernel_fp64<L, false>), g, b, 0, s, reqs, items, n_items,
+                               counter);
     } else if (precision == 1) {
-        hipLaunchKernelGGL(serve_kernel_fp32c<L>, dim3(blocks), dim3(256), 0, s, reqs, items,
-                           n_items, counter);
+        if (split)
+            hipLaunchKernelGGL((serve_kernel_fp32c<L, true>), g, b, 0, s, reqs, items, n_items,
+                               counter);
+        else
+            hipLaunchKernelGGL((serve_kernel_fp32c<L, false>), g, b, 0, s, reqs, items, n_items,
+                               counter);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
 }  // namespace
 
 hipError_t launch_scan(const ScanArgs &a, int precision, int lanes, hipStream_t s)
@@ -314,17 +345,18 @@ hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double
 }
 
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
-                        unsigned *counter, int precision, int lanes, int waves, hipStream_t s)
+                        unsigned *counter, int precision, int lanes, int split, int waves,
+                        hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     switch (lanes) {
-    case 1: return serve_l<1>(reqs, items, n_items, counter, precision, waves, s);
-    case 2: return serve_l<2>(reqs, items, n_items, counter, precision, waves, s);
-    case 4: return serve_l<4>(reqs, items, n_items, counter, precision, waves, s);
-    case 8: return serve_l<8>(reqs, items, n_items, counter, precision, waves, s);
-    case 16: return serve_l<16>(reqs, items, n_items, counter, precision, waves, s);
-    case 32: return serve_l<32>(reqs, items, n_items, counter, precision, waves, s);
-    case 64: return serve_l<64>(reqs, items, n_items, counter, precision, waves, s);
+    case 1: return serve_l<1>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 2: return serve_l<2>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 4: return serve_l<4>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 8: return serve_l<8>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 16: return serve_l<16>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 32: return serve_l<32>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 64: return serve_l<64>(reqs, items, n_items, counter, precision, split, waves, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -24,6 +24,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -196,7 +197,8 @@ namespace {
 std::string key_radial(const gf_quadrature &q, const gf_params &p)
 {
     std::string k = "r" + std::to_string(q.n_radial) + ":" +
-                    std::to_string(p.dimension == 0 ? 4 : p.dimension) + ":";
+                    std::to_string(p.dimension == 0 ? 4 : p.dimension) + ":" +
+                    std::to_string(q.radial_split) + ":";
     k.append(reinterpret_cast<const char *>(&p.lambda2), sizeof(double));
     return k;
 }
@@ -234,7 +236,8 @@ Table *gf_server::ensure_table(const std::string &key, const Request &r, bool *f
     Table t;
     if (key[0] == 'r') {
         std::vector<double> rad;
-        gf::radial_table(r.q.n_radial, r.p.lambda2, r.p.dimension == 0 ? 4 : r.p.dimension, rad);
+        gf::radial_table(r.q.n_radial, r.p.lambda2, r.p.dimension == 0 ? 4 : r.p.dimension,
+                         r.q.radial_split, rad);
         t.host.resize(rad.size() * sizeof(double));
         std::memcpy(t.host.data(), rad.data(), t.host.size());
     } else if (key[0] == 'a') {
@@ -359,7 +362,8 @@ void gf_server::run()
         Batch b;
         std::vector<Request *> fresh;
         std::vector<Upload> uploads;
-        std::map<std::pair<int, int>, std::vector<gf::WorkItem>> groups;
+        // launch groups: (precision, lanes per point, split radial rule)
+        std::map<std::tuple<int, int, int>, std::vector<gf::WorkItem>> groups;
         Stage &st = stage[next_stage];
         {
             std::unique_lock<std::mutex> lock(mu);
@@ -401,7 +405,7 @@ void gf_server::run()
                         k = std::max(1LL, std::min(k, left));
                         k = std::min(k, kMaxItemsPerBatch - b.items);
                         if (k <= 0) break;
-                        auto &vec = groups[{r->q.precision, r->lanes}];
+                        auto &vec = groups[{r->q.precision, r->lanes, r->q.radial_split}];
                         for (long long t = 0; t < k; ++t)
                             vec.push_back(gf::WorkItem{r->slot, (int32_t)(r->next_tile + t)});
                         r->next_tile += k;
@@ -468,7 +472,8 @@ void gf_server::run()
                 e = gf::launch_serve(d_args,
                                      reinterpret_cast<const gf::WorkItem *>(st.d + off_items[gi]), n,
                                      reinterpret_cast<unsigned *>(st.d + off_cnt) + gi,
-                                     kv.first.first, kv.first.second, waves, stream);
+                                     std::get<0>(kv.first), std::get<1>(kv.first),
+                                     std::get<2>(kv.first), waves, stream);
                 ++gi;
             }
             if (e == hipSuccess) e = hipEventRecord(stage_ev[next_stage], stream);

@@ -63,13 +63,15 @@ class Quadrature:
     """Node counts: Gauss-Legendre radial nodes in t = log(1+y), angular nodes
     of the rule `angular_rule` (GC2: Gauss-Chebyshev second kind, the default;
     GC1: first kind; TANH_SINH: double exponential; GL: Gauss-Legendre),
-    Gauss-Legendre arc nodes;
+    Gauss-Legendre arc nodes; radial_split = 1 cuts the radial rule into four
+    Gauss-Legendre pieces at the point's near-singular radii;
     precision FP64 or FP32C (FP32 bulk, FP64 at the sensitive steps)."""
     n_radial: int = 64
     n_angular: int = 32
     n_arc: int = 16
     precision: int = FP64
     angular_rule: int = 0
+    radial_split: int = 0
 
 
 # --------------------------------------------------------------------------
