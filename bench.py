@@ -97,15 +97,27 @@ def cpu_baseline(params, quad, grid, seconds: float):
             "points_per_s": len(idx) / dt}
 
 
-def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
+def scan_kernel_name(params, quad, lanes, props=None):
+    """The kernel instance a scan launches: scan_kernel_<prec><L, TAYLOR, SPLIT,
+    POLES> (pole sums always run the instance with the t^n epilogue)."""
+    poles = props is not None
+    taylor = poles or getattr(params, "taylor_order", 0) > 0
+    split = bool(getattr(quad, "radial_split", 0)) and not poles
+    b = lambda v: "true" if v else "false"  # noqa: E731
+    return (f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{lanes}, {b(taylor)}, "
+            f"{b(split)}, {b(poles)}>")
+
+
+def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None):
     """Times `steps` scans with HIP events on the launch stream; the plan and the
-    output buffer are resident before timing starts."""
-    plan = gf.Plan(params, quad)
+    output buffer are resident before timing starts.  Evaluations count one
+    angular term per (p-k)-leg pole."""
+    plan = gf.Plan(params, quad, props=props)
     out = gf.empty_result(grid)
     cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
     gf.scan_plan(plan, grid, out, cls, lanes=lanes)
     torch.cuda.synchronize()
-    evals = evals_per_scan(cls.cpu().numpy(), quad)
+    evals = evals_per_scan(cls.cpu().numpy(), quad) * (len(props.poles1) if props else 1)
     used_lanes = lanes or plan.auto_lanes(grid)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -126,9 +138,7 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes):
     return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
-            "kernel": f"scan_kernel_{'fp64' if quad.precision == 0 else 'fp32c'}<{used_lanes}, "
-                      f"{'true' if getattr(params, 'taylor_order', 0) > 0 else 'false'}, "
-                      f"{'true' if getattr(quad, 'radial_split', 0) else 'false'}>"}
+            "kernel": scan_kernel_name(params, quad, used_lanes, props)}
 
 
 def time_launches(torch, fn, reps):
@@ -185,6 +195,15 @@ def extensions(gf, torch):
                                 "tflops": t["tflops"],
                                 "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS,
                                 "kernel": t["kernel"]}
+    from paper_1205_0752_amd.workloads import Propagators
+    props = Propagators(Propagators.conjugate_pair(1.0 + 0.8j, 0.5), ((1.0, 0.6), (3.0, 0.4)))
+    t = time_scan(gf, torch, p, g, q, 5, 1, 0, props=props)
+    out["pole_sum_scan"] = {"workload": "bench box and nodes with pole-sum propagators: a "
+                                        "complex-conjugate pair (1 +- 0.8i) on the (p-k) leg, "
+                                        "two real poles on the k leg",
+                            "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
+                            "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS,
+                            "kernel": t["kernel"]}
     t = time_scan(gf, torch, dataclasses.replace(p, taylor_order=2), g, q, 5, 1, 0)
     out["taylor2_scan"] = {"workload": "bench workload with the subtraction t^2 about mu^2",
                            "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],

@@ -161,6 +161,35 @@ typedef struct gf_plan gf_plan_t;
  * GF_ENOMEM, GF_EDEVICE. */
 int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out);
 
+/* ---- general propagators (the integrand plug-in) ------------------------
+ * The integrand F = P1((p-k)^2) P2(k^2) with each propagator a sum of poles,
+ *   P1(s) = sum_{a < n1} c1_a / (s + m1_a^2),   P2(s) = sum_{b < n2} c2_b / (s + m2_b^2),
+ * a form that covers propagators given by a spectral or pole decomposition
+ * (complex-conjugate pole pairs included), the inputs the method is meant
+ * for (the correlators of the introduction built from different propagators).
+ * gf_params' m1^2, m2^2 with residues 1 is the case n1 = n2 = 1.  Each pole
+ * position obeys the rule for m1^2, m2^2 (not on the non-positive real axis);
+ * 1 <= n1, n2 <= GF_MAX_POLES.  The contour rule generalises: the real axis is
+ * valid below the smallest Re sqrt(m1_a^2); the ray sector is bounded by every
+ * pole's bad ray; crossing only k-leg bad rays adds the residue of each
+ * crossed pole; crossing only (p-k)-leg bad rays uses the mirror point when
+ * G(conj x) = conj G(x) holds, i.e. when conjugating every pole position and
+ * residue maps (P1, P2) onto itself or onto (P2, P1) (as pole multisets). */
+#define GF_MAX_POLES 8
+typedef struct {
+    int32_t n1, n2;
+    double m1sq_re[GF_MAX_POLES], m1sq_im[GF_MAX_POLES];
+    double c1_re[GF_MAX_POLES], c1_im[GF_MAX_POLES];
+    double m2sq_re[GF_MAX_POLES], m2sq_im[GF_MAX_POLES];
+    double c2_re[GF_MAX_POLES], c2_im[GF_MAX_POLES];
+} gf_propagators;
+
+/* gf_plan with general propagators: props replaces the masses of params
+ * (props = NULL is gf_plan).  The split radial rule needs n1 = n2 = 1
+ * (GF_EUNSUPPORTED otherwise). */
+int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_quadrature *quad,
+               gf_plan_t **out);
+
 /* Scans a grid with a plan (STEP 5, eq. 15 at every point): launches the
  * fused grid/contour/quadrature kernel on `stream` (a hipStream_t, NULL for
  * the default stream) and returns without waiting.
@@ -296,6 +325,11 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out);
  * gf_scan_plan.  GF_EBUDGET if its output alone exceeds the arena. */
 int gf_server_submit(gf_server_t *srv, const gf_params *params, const gf_grid *grid,
                      const gf_quadrature *quad, uint64_t *ticket);
+
+/* gf_server_submit with general propagators (as gf_plan_ex; NULL = the
+ * masses of params). */
+int gf_server_submit_ex(gf_server_t *srv, const gf_params *params, const gf_propagators *props,
+                        const gf_grid *grid, const gf_quadrature *quad, uint64_t *ticket);
 
 /* *state = GF_REQ_QUEUED / RUNNING / DONE.  GF_ENOTFOUND for unknown tickets. */
 int gf_server_poll(gf_server_t *srv, uint64_t ticket, int *state);

@@ -34,7 +34,8 @@ class _Problem(ctypes.Structure):
                 ("n_radial", ctypes.c_int), ("n_angular", ctypes.c_int),
                 ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int),
                 ("taylor_order", ctypes.c_int), ("dimension", ctypes.c_int),
-                ("radial_split", ctypes.c_int)]
+                ("radial_split", ctypes.c_int), ("n1", ctypes.c_int), ("n2", ctypes.c_int),
+                ("p1", ctypes.c_double * 32), ("p2", ctypes.c_double * 32)]
 
 
 def build(verbose: bool = False) -> None:
@@ -108,16 +109,24 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def problem(params, quad) -> _Problem:
-    """ctypes problem record from workload Params / Quadrature objects."""
+def problem(params, quad, props=None) -> _Problem:
+    """ctypes problem record from workload Params / Quadrature objects and,
+    optionally, pole-sum Propagators (poles1, poles2: tuples of (m^2, c))."""
     m1, m2 = complex(params.m1sq), complex(params.m2sq)
-    return _Problem(m1.real, m1.imag, m2.real, m2.imag, float(params.mu2),
-                    float(params.lambda2), float(params.scale),
-                    int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
-                    int(getattr(quad, "angular_rule", 0)),
-                    int(getattr(params, "taylor_order", 0)),
-                    int(getattr(params, "dimension", 4)),
-                    int(getattr(quad, "radial_split", 0)))
+    pr = _Problem(m1.real, m1.imag, m2.real, m2.imag, float(params.mu2),
+                  float(params.lambda2), float(params.scale),
+                  int(quad.n_radial), int(quad.n_angular), int(quad.n_arc),
+                  int(getattr(quad, "angular_rule", 0)),
+                  int(getattr(params, "taylor_order", 0)),
+                  int(getattr(params, "dimension", 4)),
+                  int(getattr(quad, "radial_split", 0)))
+    if props is not None:
+        pr.n1, pr.n2 = len(props.poles1), len(props.poles2)
+        for arr, poles in ((pr.p1, props.poles1), (pr.p2, props.poles2)):
+            for k, (m, c) in enumerate(poles):
+                m, c = complex(m), complex(c)
+                arr[4 * k], arr[4 * k + 1], arr[4 * k + 2], arr[4 * k + 3] = m.real, m.imag, c.real, c.imag
+    return pr
 
 
 # ---------------------------------------------------------------- rules
@@ -190,7 +199,8 @@ def grid_points_at(grid, flat_idx) -> np.ndarray:
     return out
 
 
-def eval_points(params, quad, x, force_class: int | None = None, want_cond: bool = False):
+def eval_points(params, quad, x, force_class: int | None = None, want_cond: bool = False,
+                props=None):
     """G at arbitrary complex points x.  Returns (g, cls[, cond])."""
     lib = _load()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
@@ -199,7 +209,7 @@ def eval_points(params, quad, x, force_class: int | None = None, want_cond: bool
     g = np.zeros(2 * x.size)
     cls = ctypes.create_string_buffer(max(x.size, 1))
     cond = np.zeros(x.size) if want_cond else None
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     rc = lib.orc_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi),
                              -1 if force_class is None else int(force_class), _dp(g), cls,
                              _dp(cond) if want_cond else None)
@@ -212,14 +222,14 @@ def eval_points(params, quad, x, force_class: int | None = None, want_cond: bool
     return gc, c
 
 
-def scan(params, quad, grid, want_cond: bool = False):
+def scan(params, quad, grid, want_cond: bool = False, props=None):
     """G on the whole grid (row-major, Re fastest)."""
     lib = _load()
     n = grid.n_points
     g = np.zeros(2 * n)
     cls = ctypes.create_string_buffer(max(n, 1))
     cond = np.zeros(n) if want_cond else None
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     rc = lib.orc_scan(ctypes.byref(pr), grid.n_re, grid.n_im, grid.re_lo, grid.re_hi,
                       grid.im_lo, grid.im_hi, _dp(g), cls, _dp(cond) if want_cond else None)
     if rc != 0:
@@ -248,14 +258,14 @@ def eval_points_q(params, quad, x):
     return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
 
 
-def yscan(params, quad, x: complex, y, what: int = 0) -> np.ndarray:
+def yscan(params, quad, x: complex, y, what: int = 0, props=None) -> np.ndarray:
     """y-plane diagnostic at fixed x: <1/D1>(x, y) (what = 0) or the subtracted
     y-integrand y/(y + m2^2)(<1/D1>(x, y) - <1/D1>(mu^2, y)) (what = 1)."""
     y = np.ascontiguousarray(np.asarray(y, dtype=np.complex128).ravel())
     yr = np.ascontiguousarray(y.real)
     yi = np.ascontiguousarray(y.imag)
     out = np.zeros(2 * y.size)
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     _load().orc_yscan(ctypes.byref(pr), complex(x).real, complex(x).imag, y.size, _dp(yr), _dp(yi),
                       int(what), _dp(out))
     return out[0::2] + 1j * out[1::2]
@@ -279,12 +289,12 @@ def obstruction(params, x, n_samples: int = 4096):
             np.frombuffer(tie.raw[:x.size], dtype=np.uint8).astype(bool))
 
 
-def taylor(params, quad, n: int):
+def taylor(params, quad, n: int, props=None):
     """K_0..K_n of the subtraction at mu^2 by the Cauchy formula, and the
     radius rho of the circle (rounding error of K_i ~ eps max|S| rho^-i)."""
     out = np.zeros(2 * (n + 1))
     rho = ctypes.c_double()
-    if _load().orc_taylor(ctypes.byref(problem(params, quad)), int(n), _dp(out),
+    if _load().orc_taylor(ctypes.byref(problem(params, quad, props)), int(n), _dp(out),
                           ctypes.byref(rho)) != 0:
         raise ValueError("bad problem or order")
     return out[0::2] + 1j * out[1::2], rho.value
@@ -306,31 +316,31 @@ def threads() -> int:
     return int(_load().orc_threads())
 
 
-def jmu(params, quad) -> complex:
+def jmu(params, quad, props=None) -> complex:
     """Unscaled subtraction sum (real-axis contour at x = mu^2)."""
     re = ctypes.c_double()
     im = ctypes.c_double()
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     _load().orc_jmu(ctypes.byref(pr), ctypes.byref(re), ctypes.byref(im))
     return complex(re.value, im.value)
 
 
-def classify(params, quad, x) -> np.ndarray:
+def classify(params, quad, x, props=None) -> np.ndarray:
     lib = _load()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
     xr = np.ascontiguousarray(x.real)
     xi = np.ascontiguousarray(x.imag)
     cls = ctypes.create_string_buffer(max(x.size, 1))
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     lib.orc_classify_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), cls)
     return np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
 
 
-def evals_for_classes(params, quad, cls, x=None) -> int:
+def evals_for_classes(params, quad, cls, x=None, props=None) -> int:
     """Integrand evaluations for points of the given classes; a MIRROR point
     costs what its mirror image costs (needs x)."""
     lib = _load()
-    pr = problem(params, quad)
+    pr = problem(params, quad, props)
     per = {c: lib.orc_evals_for_class(ctypes.byref(pr), c) for c in (R, Y, YRES)}
     cls = np.asarray(cls)
     total = sum(int((cls == c).sum()) * per[c] for c in (R, Y, YRES))

@@ -74,6 +74,11 @@ typedef struct {
     int taylor_order;          /* n of the subtraction operator t^n (eq. 13), -1..8 */
     int dimension;             /* D = 2, 3 or 4 (0 means 4) */
     int radial_split;          /* 1: split the radial rule at the near-singular radii */
+    /* pole-sum propagators P1(s) = sum_a c1_a/(s + m1_a^2), P2(s) = sum_b
+     * c2_b/(s + m2_b^2); n1 = 0 means one pole per leg at m1sq, m2sq with
+     * residue 1.  Per pole: m^2 re, m^2 im, c re, c im. */
+    int n1, n2;
+    double p1[32], p2[32];
 } orc_problem;
 
 #define ORC_MAX_TAYLOR 8
@@ -280,33 +285,80 @@ void orc_angular_sum(double u_re, double u_im, double v_re, double v_im, int n,
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    cplx m1sq, m2sq;
-    double beta1, beta2;    /* bad-ray angles arg(-m1^2), arg(-m2^2) */
+    int n1, n2;
+    cplx m1[8], c1[8], m2[8], c2[8];  /* poles and residues of P1, P2 */
+    double b1[8], b2[8];    /* bad-ray angles arg(-m^2) of every pole */
+    cplx m1sq, m2sq;        /* the first pole of each leg */
     double lo, hi;          /* open sector (lo, hi) reachable by rotating the ray */
-    double vstar;           /* region-R bound on |Im sqrt(x)| = Re sqrt(m1^2) */
-    int mirror_ok;          /* real masses or a conjugate pair */
+    double vstar;           /* region-R bound on |Im sqrt(x)|: min_a Re sqrt(m1_a^2) */
+    int mirror_ok;          /* G(conj x) = conj G(x) for these propagators */
 } orc_geometry;
+
+/* arg(-m^2); a real positive m^2 gives carg(-m^2) = +pi or -pi depending on
+ * the sign of the zero imaginary part: it is the negative real axis either
+ * way, taken as +pi */
+static double orc_bad_ray(cplx m)
+{
+    return cimag(m) == 0.0 ? M_PI : carg(-m);
+}
+
+/* Is the pole multiset (m, c) of `a` (conjugated if conj) equal to that of b? */
+static int orc_same_poles(int na, const cplx *ma, const cplx *ca, int nb, const cplx *mb,
+                          const cplx *cb, int conj_a)
+{
+    if (na != nb) return 0;
+    int used[8] = {0};
+    for (int i = 0; i < na; ++i) {
+        cplx m = conj_a ? conj(ma[i]) : ma[i], c = conj_a ? conj(ca[i]) : ca[i];
+        int found = 0;
+        for (int j = 0; j < nb && !found; ++j)
+            if (!used[j] && m == mb[j] && c == cb[j]) used[j] = found = 1;
+        if (!found) return 0;
+    }
+    return 1;
+}
 
 static void orc_make_geometry(const orc_problem *p, orc_geometry *g)
 {
-    g->m1sq = p->m1sq_re + I * p->m1sq_im;
-    g->m2sq = p->m2sq_re + I * p->m2sq_im;
-    g->beta1 = carg(-g->m1sq);
-    g->beta2 = carg(-g->m2sq);
-    /* a real positive m^2 gives carg(-m^2) = +pi or -pi depending on the sign
-     * of the zero imaginary part; it is the negative real axis either way */
-    if (p->m1sq_im == 0.0) g->beta1 = M_PI;
-    if (p->m2sq_im == 0.0) g->beta2 = M_PI;
+    if (p->n1 == 0) {
+        g->n1 = g->n2 = 1;
+        g->m1[0] = p->m1sq_re + I * p->m1sq_im;
+        g->m2[0] = p->m2sq_re + I * p->m2sq_im;
+        g->c1[0] = g->c2[0] = 1.0;
+    } else {
+        g->n1 = p->n1;
+        g->n2 = p->n2;
+        for (int k = 0; k < p->n1; ++k) {
+            g->m1[k] = p->p1[4 * k] + I * p->p1[4 * k + 1];
+            g->c1[k] = p->p1[4 * k + 2] + I * p->p1[4 * k + 3];
+        }
+        for (int k = 0; k < p->n2; ++k) {
+            g->m2[k] = p->p2[4 * k] + I * p->p2[4 * k + 1];
+            g->c2[k] = p->p2[4 * k + 2] + I * p->p2[4 * k + 3];
+        }
+    }
+    g->m1sq = g->m1[0];
+    g->m2sq = g->m2[0];
     g->hi = M_PI;
     g->lo = -M_PI;
-    double b[2] = {g->beta1, g->beta2};
-    for (int k = 0; k < 2; ++k) {
-        if (b[k] > 0.0 && b[k] < g->hi) g->hi = b[k];
-        if (b[k] <= 0.0 && b[k] > g->lo) g->lo = b[k];
+    g->vstar = INFINITY;
+    for (int k = 0; k < g->n1; ++k) {
+        g->b1[k] = orc_bad_ray(g->m1[k]);
+        g->vstar = fmin(g->vstar, creal(csqrt(g->m1[k])));
     }
-    g->vstar = creal(csqrt(g->m1sq));
-    g->mirror_ok = (p->m1sq_im == 0.0 && p->m2sq_im == 0.0) ||
-                   (p->m1sq_re == p->m2sq_re && p->m1sq_im == -p->m2sq_im);
+    for (int k = 0; k < g->n2; ++k) g->b2[k] = orc_bad_ray(g->m2[k]);
+    for (int k = 0; k < g->n1 + g->n2; ++k) {
+        double b = k < g->n1 ? g->b1[k] : g->b2[k - g->n1];
+        if (b > 0.0 && b < g->hi) g->hi = b;
+        if (b <= 0.0 && b > g->lo) g->lo = b;
+    }
+    /* conjugation maps (P1, P2) onto itself (real-analytic propagators, e.g.
+     * real masses) or onto (P2, P1) (e.g. a conjugate mass pair, by the
+     * exchange of the two legs) */
+    g->mirror_ok = (orc_same_poles(g->n1, g->m1, g->c1, g->n1, g->m1, g->c1, 1) &&
+                    orc_same_poles(g->n2, g->m2, g->c2, g->n2, g->m2, g->c2, 1)) ||
+                   (orc_same_poles(g->n1, g->m1, g->c1, g->n2, g->m2, g->c2, 1) &&
+                    orc_same_poles(g->n2, g->m2, g->c2, g->n1, g->m1, g->c1, 1));
 }
 
 /* angular distance between two angles, in [0, pi] */
@@ -316,47 +368,63 @@ static double ang_dist(double a, double b)
     return d > M_PI ? 2.0 * M_PI - d : d;
 }
 
+/* Does rotating the ray from angle 0 to phi sweep across the ray at angle b? */
+static int orc_swept(double phi, double b)
+{
+    return phi > 0.0 ? (b > 0.0 && b < phi) : (b <= 0.0 && b > phi);
+}
+
 /* Rotated-contour class of x (Y, YRES, MIRROR or SINGULAR); for YRES,
- * *res_sign = +1 or -1. */
-static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign)
+ * *res_sign = +1 or -1 and *mask flags the k-leg poles swept across, whose
+ * residues the contour picks up. */
+static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, int *mask)
 {
     *res_sign = 0;
+    *mask = 0;
     if (phi > g->lo && phi < g->hi) return ORC_Y;
-    /* Rotating the ray from angle 0 to phi sweeps across the bad rays between. */
-    int cross1, cross2, on1, on2;
-    if (phi > 0.0) {
-        cross1 = g->beta1 > 0.0 && g->beta1 < phi;
-        cross2 = g->beta2 > 0.0 && g->beta2 < phi;
-    } else {
-        cross1 = g->beta1 <= 0.0 && g->beta1 > phi;
-        cross2 = g->beta2 <= 0.0 && g->beta2 > phi;
+    int cross1 = 0, on = 0, m = 0;
+    for (int k = 0; k < g->n1; ++k) {
+        cross1 |= orc_swept(phi, g->b1[k]);
+        on |= ang_dist(phi, g->b1[k]) == 0.0;
     }
-    on1 = ang_dist(phi, g->beta1) == 0.0;
-    on2 = ang_dist(phi, g->beta2) == 0.0;
-    if (on1 || on2) return ORC_SINGULAR;
-    if (cross2 && !cross1) {
+    for (int k = 0; k < g->n2; ++k) {
+        if (orc_swept(phi, g->b2[k])) m |= 1 << k;
+        on |= ang_dist(phi, g->b2[k]) == 0.0;
+    }
+    if (on) return ORC_SINGULAR;
+    if (m && !cross1) {
         *res_sign = phi > 0.0 ? 1 : -1;
+        *mask = m;
         return ORC_YRES;
     }
-    if (cross1 && !cross2 && g->mirror_ok) return ORC_MIRROR;
+    if (cross1 && !m && g->mirror_ok) return ORC_MIRROR;
     return ORC_SINGULAR;
 }
 
-/* Class of x; for YRES, *res_sign = +1 or -1. */
-static int orc_classify(const orc_geometry *g, cplx x, int *res_sign)
+/* Class of x; for YRES, *res_sign = +1 or -1 and *mask the residues due. */
+static int orc_classify_m(const orc_geometry *g, cplx x, int *res_sign, int *mask)
 {
     double v = fabs(cimag(csqrt(x)));
     double phi = carg(x);
-    int rot = orc_rotated_class(g, phi, res_sign);
+    int rot = orc_rotated_class(g, phi, res_sign, mask);
     if (v < g->vstar) {
-        double delta = fmin(ang_dist(phi, g->beta1), ang_dist(phi, g->beta2));
+        double delta = M_PI;
+        for (int k = 0; k < g->n1; ++k) delta = fmin(delta, ang_dist(phi, g->b1[k]));
+        for (int k = 0; k < g->n2; ++k) delta = fmin(delta, ang_dist(phi, g->b2[k]));
         if (v < ORC_R_NEAR * g->vstar || 1.0 - v / g->vstar >= ORC_R_SLOPE * delta ||
             rot == ORC_SINGULAR) {
             *res_sign = 0;
+            *mask = 0;
             return ORC_R;
         }
     }
     return rot;
+}
+
+static int orc_classify(const orc_geometry *g, cplx x, int *res_sign)
+{
+    int mask;
+    return orc_classify_m(g, x, res_sign, &mask);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -446,28 +514,59 @@ static void orc_radial_nodes(const orc_ctx *c, cplx xn, double *r, double *wr)
         }
 }
 
-/* The contour sum of the point x (class cls); the straight part's nodes are
- * those of the point xn (x itself, or mu^2 for the subtraction sums). */
+/* <P1(D1)>(x, y) = sum_a c1_a <1/(x + y + m1_a^2 - 2 sqrt(x) sqrt(y) z)>; with
+ * sens given, adds sum_a |c1_a| (that pole's absolute angular sum with its
+ * sensitivity factor, as angular_d1 counts it). */
+static cplx orc_ang_p1(const orc_ctx *c, cplx x, cplx y, cplx sxsy, double *sens)
+{
+    cplx s = 0.0;
+    for (int a = 0; a < c->geo.n1; ++a) {
+        double t = 0.0;
+        s += c->geo.c1[a] * angular_d1(x, y, sxsy, c->geo.m1[a], c->p->n_angular, c->z, c->w,
+                                       sens ? &t : NULL);
+        if (sens) *sens += cabs(c->geo.c1[a]) * t;
+    }
+    return s;
+}
+
+/* P2(y) = sum_b c2_b / (y + m2_b^2); *sens = sum_b |c2_b / (y + m2_b^2)|
+ * (1 + |y| / |y + m2_b^2|), its size times its sensitivity to y. */
+static cplx orc_p2(const orc_ctx *c, cplx y, double *sens)
+{
+    cplx s = 0.0;
+    *sens = 0.0;
+    for (int b = 0; b < c->geo.n2; ++b) {
+        cplx t = c->geo.c2[b] / (y + c->geo.m2[b]);
+        s += t;
+        *sens += cabs(t) * (1.0 + cabs(y) / cabs(y + c->geo.m2[b]));
+    }
+    return s;
+}
+
+/* One contour node: weight w (dy and the measure) at y with sqrt(y) = sy. */
+static cplx orc_node(const orc_ctx *c, cplx x, cplx sx, cplx y, cplx sy, cplx w, double *absum)
+{
+    double a = 0.0, sp = 0.0;
+    cplx ang = orc_ang_p1(c, x, y, sx * sy, absum ? &a : NULL);
+    cplx pre = w * orc_measure(orc_dim(c->p), y, sy) * orc_p2(c, y, &sp);
+    if (absum) *absum += cabs(w * orc_measure(orc_dim(c->p), y, sy)) * sp * a;
+    return pre * ang;
+}
+
+/* The contour sum of the point x (class cls, residue flags res_mask for
+ * YRES); the straight part's nodes are those of the point xn (x itself, or
+ * mu^2 for the subtraction sums). */
 static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_sign,
-                            double *absum)
+                            int res_mask, double *absum)
 {
     const int dim = orc_dim(c->p);
     const orc_problem *p = c->p;
-    cplx m1sq = c->geo.m1sq, m2sq = c->geo.m2sq;
     cplx sx = csqrt(x);
     cplx s = 0.0;
     double *rn = malloc(sizeof(double) * p->n_radial), *wn = malloc(sizeof(double) * p->n_radial);
     orc_radial_nodes(c, xn, rn, wn);
     if (cls == ORC_R) {
-        for (int i = 0; i < p->n_radial; ++i) {
-            cplx y = rn[i];
-            cplx sy = sqrt(rn[i]);
-            double a = 0.0;
-            cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-            cplx pre = wn[i] * orc_measure(dim, y, sy) / (y + m2sq);
-            s += pre * ang;
-            if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
-        }
+        for (int i = 0; i < p->n_radial; ++i) s += orc_node(c, x, sx, rn[i], sqrt(rn[i]), wn[i], absum);
         free(rn);
         free(wn);
         return s;
@@ -476,15 +575,8 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_
     double phi = carg(x);
     cplx e = cexp(I * phi);
     cplx eh = cexp(I * 0.5 * phi);
-    for (int i = 0; i < p->n_radial; ++i) {
-        cplx y = e * rn[i];
-        cplx sy = eh * sqrt(rn[i]);
-        double a = 0.0;
-        cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx pre = e * wn[i] * orc_measure(dim, y, sy) / (y + m2sq);
-        s += pre * ang;
-        if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
-    }
+    for (int i = 0; i < p->n_radial; ++i)
+        s += orc_node(c, x, sx, e * rn[i], eh * sqrt(rn[i]), e * wn[i], absum);
     /* arc |y| = Lambda^2 from angle phi back to 0: psi(s) = phi (1 - s)/2,
      * dy = i y psi'(s) ds = -i y (phi/2) ds */
     double lam = sqrt(p->lambda2);
@@ -492,22 +584,20 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_
         double psi = 0.5 * phi * (1.0 - c->arc_x[k]);
         cplx y = p->lambda2 * cexp(I * psi);
         cplx sy = lam * cexp(I * 0.5 * psi);
-        double a = 0.0;
-        cplx ang = angular_d1(x, y, sx * sy, m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx dy = -I * y * (0.5 * phi) * c->arc_w[k];
-        cplx pre = dy * orc_measure(dim, y, sy) / (y + m2sq);
-        s += pre * ang;
-        if (absum) *absum += cabs(pre) * a * (1.0 + cabs(y) / cabs(y + m2sq));
+        s += orc_node(c, x, sx, y, sy, -I * y * (0.5 * phi) * c->arc_w[k], absum);
     }
     if (cls == ORC_YRES) {
-        /* residue of y^{(D-2)/2}/(y + m2^2) <1/D1>(y) at y0 = -m2^2 is
-         * y0^{(D-2)/2} <1/D1>(y0) */
-        cplx y0 = -m2sq;
-        double a = 0.0;
-        cplx ang = angular_d1(x, y0, sx * csqrt(y0), m1sq, p->n_angular, c->z, c->w, absum ? &a : NULL);
-        cplx pre = res_sign * 2.0 * M_PI * I * orc_measure(dim, y0, csqrt(y0));
-        s += pre * ang;
-        if (absum) *absum += cabs(pre) * a;
+        /* residue of y^{(D-2)/2} P2(y) <P1>(y) at the pole y0 = -m2_b^2 of a
+         * swept k-leg pole is c2_b y0^{(D-2)/2} <P1>(y0) */
+        for (int b = 0; b < c->geo.n2; ++b) {
+            if (!(res_mask >> b & 1)) continue;
+            cplx y0 = -c->geo.m2[b];
+            double a = 0.0;
+            cplx ang = orc_ang_p1(c, x, y0, sx * csqrt(y0), absum ? &a : NULL);
+            cplx pre = res_sign * 2.0 * M_PI * I * c->geo.c2[b] * orc_measure(dim, y0, csqrt(y0));
+            s += pre * ang;
+            if (absum) *absum += cabs(pre) * a;
+        }
     }
     free(rn);
     free(wn);
@@ -535,11 +625,16 @@ static cplx orc_subtraction(const orc_ctx *c, cplx x, double *absum)
 /* G at one point; returns the class; *cond as described at orc_eval_points. */
 static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double *cond)
 {
-    int sign = 0;
-    int cls = orc_classify(&c->geo, x, &sign);
+    int sign = 0, mask = 0;
+    int cls = orc_classify_m(&c->geo, x, &sign, &mask);
     if (force_class >= 0) {
         cls = force_class;
-        if (cls == ORC_YRES) sign = carg(x) > 0.0 ? 1 : -1;
+        if (cls == ORC_YRES) {
+            sign = carg(x) > 0.0 ? 1 : -1;
+            mask = 0;
+            for (int b = 0; b < c->geo.n2; ++b)
+                if (orc_swept(carg(x), c->geo.b2[b])) mask |= 1 << b;
+        }
     }
     double absum = c->p->taylor_order < 0 ? 0.0 : c->jmu_abs;
     double *pab = cond ? &absum : NULL;
@@ -551,20 +646,20 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
     }
     if (cls == ORC_MIRROR) {
         cplx xb = conj(x);
-        int sb = 0;
-        int cb = orc_classify(&c->geo, xb, &sb);
+        int sb = 0, mb = 0;
+        int cb = orc_classify_m(&c->geo, xb, &sb, &mb);
         if (cb == ORC_MIRROR || cb == ORC_SINGULAR) {
             *g = NAN + I * NAN;
             if (cond) *cond = NAN;
             return ORC_SINGULAR;
         }
-        s = orc_contour_sum(c, xb, xb, cb, sb, pab);
+        s = orc_contour_sum(c, xb, xb, cb, sb, mb, pab);
         cplx gb = c->p->scale * (s - orc_subtraction(c, xb, pab));
         *g = conj(gb);
         if (cond) *cond = c->p->scale * absum / cabs(gb);
         return cls;
     }
-    s = orc_contour_sum(c, x, x, cls, sign, pab);
+    s = orc_contour_sum(c, x, x, cls, sign, mask, pab);
     *g = c->p->scale * (s - orc_subtraction(c, x, pab));
     if (cond) *cond = c->p->scale * absum / cabs(*g);
     return cls;
@@ -579,7 +674,8 @@ static void orc_ctx_free(orc_ctx *c);
  * 64 equally spaced points (exact up to (rho/R)^64 for S analytic in the disc
  * of radius R).  S is a sum of terms rational in x whose poles are the x where
  * some node's first propagator vanishes, x = (sqrt(y) z +- sqrt(y z^2 - y -
- * m1^2))^2; rho is half the distance from mu^2 to the nearest of them. */
+ * m1_a^2))^2 for any pole a of P1; rho is half the distance from mu^2 to the
+ * nearest of them. */
 static double orc_taylor_cauchy(const orc_ctx *c, int n, cplx *K)
 {
     const orc_problem *p = c->p;
@@ -588,11 +684,12 @@ static double orc_taylor_cauchy(const orc_ctx *c, int n, cplx *K)
     orc_radial_nodes(c, p->mu2, rn, wn);
     for (int i = 0; i < p->n_radial; ++i) {
         cplx sy = sqrt(rn[i]);
-        for (int j = 0; j < p->n_angular; ++j) {
-            cplx root = csqrt(rn[i] * c->z[j] * c->z[j] - rn[i] - c->geo.m1sq);
-            cplx s1 = sy * c->z[j] + root, s2 = sy * c->z[j] - root;
-            dmin = fmin(dmin, fmin(cabs(s1 * s1 - p->mu2), cabs(s2 * s2 - p->mu2)));
-        }
+        for (int j = 0; j < p->n_angular; ++j)
+            for (int a = 0; a < c->geo.n1; ++a) {
+                cplx root = csqrt(rn[i] * c->z[j] * c->z[j] - rn[i] - c->geo.m1[a]);
+                cplx s1 = sy * c->z[j] + root, s2 = sy * c->z[j] - root;
+                dmin = fmin(dmin, fmin(cabs(s1 * s1 - p->mu2), cabs(s2 * s2 - p->mu2)));
+            }
     }
     free(rn);
     free(wn);
@@ -601,7 +698,7 @@ static double orc_taylor_cauchy(const orc_ctx *c, int n, cplx *K)
     for (int i = 0; i <= n; ++i) K[i] = 0.0;
     for (int k = 0; k < N; ++k) {
         cplx e = cexp(I * 2.0 * M_PI * k / N);
-        cplx S = orc_contour_sum(c, p->mu2 + rho * e, p->mu2, ORC_R, 0, NULL);
+        cplx S = orc_contour_sum(c, p->mu2 + rho * e, p->mu2, ORC_R, 0, 0, NULL);
         for (int i = 0; i <= n; ++i) K[i] += S * cpow(rho * e, -i) / N;
     }
     return rho;
@@ -625,7 +722,7 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     orc_gauss_legendre(nr, c->gl_t, c->gl_w);
     if (p->n_arc > 0) orc_gauss_legendre(p->n_arc, c->arc_x, c->arc_w);
     if (p->radial_split) {
-        if (nr % 4 != 0) {
+        if (nr % 4 != 0 || p->n1 > 1 || p->n2 > 1) {  /* the split rule needs single poles */
             orc_ctx_free(c);
             return -1;
         }
@@ -646,7 +743,7 @@ static int orc_ctx_init(orc_ctx *c, const orc_problem *p)
     }
     /* subtraction term (eq. 14 at x = mu^2, real axis) */
     double a = 0.0;
-    c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, p->mu2, ORC_R, 0, &a);
+    c->jmu = orc_contour_sum(c, p->mu2 + 0.0 * I, p->mu2, ORC_R, 0, 0, &a);
     c->jmu_abs = a;
     if (p->taylor_order < -1 || p->taylor_order > ORC_MAX_TAYLOR) {
         orc_ctx_free(c);
@@ -783,9 +880,9 @@ long orc_evals_for_class(const orc_problem *p, int cls)
 int orc_threads(void) { return omp_get_max_threads(); }
 
 /* y-plane diagnostic at fixed x (the paper's Fig. 1): for each y_k,
- * what = 0: <1/D1>(x, y_k); what = 1: y^{(D-2)/2}/(y + m2^2) (<1/D1>(x, y) -
- * <1/D1>(mu^2, y)), the order-0 subtracted y-integrand of eq. 14 (principal
- * sqrt(y) for D = 3).  out: 2n doubles. */
+ * what = 0: <P1>(x, y_k); what = 1: y^{(D-2)/2} P2(y) (<P1>(x, y) - <P1>(mu^2, y)),
+ * the order-0 subtracted y-integrand of eq. 14 (principal sqrt(y) for D = 3;
+ * P1 = 1/D1 and P2 = 1/(y + m2^2) for single poles).  out: 2n doubles. */
 int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const double *y_re,
               const double *y_im, int what, double *out)
 {
@@ -796,17 +893,22 @@ int orc_yscan(const orc_problem *p, double x_re, double x_im, long n, const doub
         free(w);
         return -1;
     }
-    cplx x = x_re + I * x_im, m1sq = p->m1sq_re + I * p->m1sq_im, m2sq = p->m2sq_re + I * p->m2sq_im;
+    orc_geometry g;
+    orc_make_geometry(p, &g);
+    cplx x = x_re + I * x_im;
     cplx sx = csqrt(x), smu = sqrt(p->mu2);
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < n; ++k) {
         cplx y = y_re[k] + I * y_im[k];
         cplx sy = csqrt(y);
-        cplx a = angular_d1(x, y, sx * sy, m1sq, p->n_angular, z, w, NULL);
-        if (what == 1) {
-            cplx amu = angular_d1(p->mu2 + 0.0 * I, y, smu * sy, m1sq, p->n_angular, z, w, NULL);
-            a = orc_measure(orc_dim(p), y, csqrt(y)) / (y + m2sq) * (a - amu);
+        cplx a = 0.0, amu = 0.0, p2 = 0.0;
+        for (int q = 0; q < g.n1; ++q) {
+            a += g.c1[q] * angular_d1(x, y, sx * sy, g.m1[q], p->n_angular, z, w, NULL);
+            amu += g.c1[q] * angular_d1(p->mu2 + 0.0 * I, y, smu * sy, g.m1[q], p->n_angular, z, w,
+                                        NULL);
         }
+        for (int q = 0; q < g.n2; ++q) p2 += g.c2[q] / (y + g.m2[q]);
+        if (what == 1) a = orc_measure(orc_dim(p), y, csqrt(y)) * p2 * (a - amu);
         out[2 * k] = creal(a);
         out[2 * k + 1] = cimag(a);
     }

@@ -25,6 +25,8 @@ typedef struct {
     int taylor_order;   /* only 0 is implemented here */
     int dimension;      /* only 4 (or 0) is implemented here */
     int radial_split;   /* only 0 is implemented here */
+    int n1, n2;         /* only 0 (single poles) is implemented here */
+    double p1[32], p2[32];
 } orcq_problem;   /* same layout as the FP64 oracle's problem struct */
 
 #define QPI M_PIq

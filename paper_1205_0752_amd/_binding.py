@@ -27,10 +27,11 @@ GF_ENOTFOUND = -6
 CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 
 #: every symbol include/gf.h declares
-EXPORTS = ("gf_plan", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
+EXPORTS = ("gf_plan", "gf_plan_ex", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
            "gf_plan_jmu", "gf_plan_taylor", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
            "gf_yscan_plan", "gf_cut_curve", "gf_obstruction_map",
-           "gf_server_create", "gf_server_submit", "gf_server_poll", "gf_server_wait",
+           "gf_server_create", "gf_server_submit", "gf_server_submit_ex", "gf_server_poll",
+           "gf_server_wait",
            "gf_server_wait_any", "gf_server_result", "gf_server_copy_result",
            "gf_server_release", "gf_server_stats_get", "gf_server_destroy")
 
@@ -55,6 +56,33 @@ class _Quad(ctypes.Structure):
     _fields_ = [("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32),
                 ("n_arc", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("angular_rule", ctypes.c_int32), ("radial_split", ctypes.c_int32)]
+
+
+MAX_POLES = 8
+
+
+class _Props(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32)] + [
+        (name, ctypes.c_double * MAX_POLES)
+        for name in ("m1sq_re", "m1sq_im", "c1_re", "c1_im", "m2sq_re", "m2sq_im", "c2_re",
+                     "c2_im")]
+
+
+def c_props(props):
+    """ctypes record of a Propagators object (None -> None)."""
+    if props is None:
+        return None
+    r = _Props()
+    r.n1, r.n2 = len(props.poles1), len(props.poles2)
+    if not (1 <= r.n1 <= MAX_POLES and 1 <= r.n2 <= MAX_POLES):
+        raise ValueError(f"each propagator needs 1..{MAX_POLES} poles")
+    for k, (m, c) in enumerate(props.poles1):
+        m, c = complex(m), complex(c)
+        r.m1sq_re[k], r.m1sq_im[k], r.c1_re[k], r.c1_im[k] = m.real, m.imag, c.real, c.imag
+    for k, (m, c) in enumerate(props.poles2):
+        m, c = complex(m), complex(c)
+        r.m2sq_re[k], r.m2sq_im[k], r.c2_re[k], r.c2_im[k] = m.real, m.imag, c.real, c.imag
+    return r
 
 
 class _Grid(ctypes.Structure):
@@ -91,6 +119,8 @@ def load():
         vp = ctypes.c_void_p
         lib.gf_plan.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Quad),
                                 ctypes.POINTER(vp)]
+        lib.gf_plan_ex.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Props),
+                                   ctypes.POINTER(_Quad), ctypes.POINTER(vp)]
         lib.gf_scan_plan.argtypes = [vp, ctypes.POINTER(_Grid), vp, vp, vp]
         lib.gf_scan_plan_ex.argtypes = [vp, ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, vp]
         lib.gf_scan.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
@@ -115,6 +145,8 @@ def load():
         lib.gf_server_create.argtypes = [ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)]
         lib.gf_server_submit.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
                                          ctypes.POINTER(_Quad), u64p]
+        lib.gf_server_submit_ex.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Props),
+                                            ctypes.POINTER(_Grid), ctypes.POINTER(_Quad), u64p]
         lib.gf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
         lib.gf_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
         lib.gf_server_wait_any.argtypes = [vp, ctypes.c_double, u64p]
@@ -162,14 +194,18 @@ def _stream_handle(stream):
 
 class Plan:
     """Device-resident node tables and subtraction constant for one
-    (params, quadrature); see gf_plan."""
+    (params, quadrature), optionally with pole-sum propagators; see gf_plan and
+    gf_plan_ex."""
 
-    def __init__(self, params: Params, quad: Quadrature):
+    def __init__(self, params: Params, quad: Quadrature, props=None):
         self.params = params
         self.quad = quad
+        self.props = props
         h = ctypes.c_void_p()
-        _check(load().gf_plan(ctypes.byref(c_params(params)), ctypes.byref(c_quad(quad)),
-                              ctypes.byref(h)))
+        pr = c_props(props)
+        _check(load().gf_plan_ex(ctypes.byref(c_params(params)),
+                                 ctypes.byref(pr) if pr is not None else None,
+                                 ctypes.byref(c_quad(quad)), ctypes.byref(h)))
         self._h = h
 
     @property
@@ -301,11 +337,13 @@ class Server:
             raise RuntimeError("server is closed")
         return self._h
 
-    def submit(self, params: Params, grid: Grid, quad: Quadrature) -> int:
+    def submit(self, params: Params, grid: Grid, quad: Quadrature, props=None) -> int:
         t = ctypes.c_uint64()
-        _check(load().gf_server_submit(self.handle, ctypes.byref(c_params(params)),
-                                       ctypes.byref(c_grid(grid)), ctypes.byref(c_quad(quad)),
-                                       ctypes.byref(t)))
+        pr = c_props(props)
+        _check(load().gf_server_submit_ex(self.handle, ctypes.byref(c_params(params)),
+                                          ctypes.byref(pr) if pr is not None else None,
+                                          ctypes.byref(c_grid(grid)), ctypes.byref(c_quad(quad)),
+                                          ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket: int) -> int:

@@ -73,49 +73,88 @@ __device__ __forceinline__ double angle_between(double a, double b)
 }
 
 // Contour class of x (STEP 3).  Rotating the ray from angle 0 to phi = arg x
-// is free inside (lo, hi); sweeping across the k-leg pole ray arg(-m2^2) adds
-// its residue (sign of phi); across the ray arg(-m1^2) the conjugate point is
-// used instead.  The real axis is preferred where it is valid (|Im sqrt x| <
-// v*) and either comfortably inside (v < kRNear v*) or closer to its own edge
-// than the ray is to a bad ray.
-template <class Args>
-__device__ int classify(const Args &a, double xr, double xi, int *res_sign)
+// is free inside (lo, hi); sweeping across the k-leg pole rays arg(-m2_b^2)
+// adds their residues (sign of phi); across a ray arg(-m1_a^2) the conjugate
+// point is used instead.  The real axis is preferred where it is valid (|Im
+// sqrt x| < v*) and either comfortably inside (v < kRNear v*) or closer to its
+// own edge than the ray is to a bad ray.  POLES: every pole of the two pole
+// sums has its bad ray; *res_mask flags the k-leg poles whose residue is due.
+template <bool POLES = false, class Args>
+__device__ int classify(const Args &a, double xr, double xi, int *res_sign, int *res_mask = nullptr)
 {
     cd sx = csqrt_principal(xr, xi);
     double v = fabs(sx.i);
     double phi = atan2(xi, xr);
     int rot;
+    int mask = 0;
     *res_sign = 0;
-    if (phi > a.lo && phi < a.hi) {
-        rot = kY;
-    } else {
-        bool past1, past2;
-        if (phi > 0.0) {
-            past1 = a.beta1 > 0.0 && a.beta1 < phi;
-            past2 = a.beta2 > 0.0 && a.beta2 < phi;
+    double delta;
+    if (!POLES) {
+        delta = fmin(angle_between(phi, a.beta1), angle_between(phi, a.beta2));
+        if (phi > a.lo && phi < a.hi) {
+            rot = kY;
         } else {
-            past1 = a.beta1 <= 0.0 && a.beta1 > phi;
-            past2 = a.beta2 <= 0.0 && a.beta2 > phi;
+            bool past1, past2;
+            if (phi > 0.0) {
+                past1 = a.beta1 > 0.0 && a.beta1 < phi;
+                past2 = a.beta2 > 0.0 && a.beta2 < phi;
+            } else {
+                past1 = a.beta1 <= 0.0 && a.beta1 > phi;
+                past2 = a.beta2 <= 0.0 && a.beta2 > phi;
+            }
+            bool on_bad = angle_between(phi, a.beta1) == 0.0 || angle_between(phi, a.beta2) == 0.0;
+            if (on_bad) {
+                rot = kSingular;
+            } else if (past2 && !past1) {
+                rot = kYRes;
+                *res_sign = phi > 0.0 ? 1 : -1;
+                mask = 1;
+            } else if (past1 && !past2 && a.mirror_ok) {
+                rot = kMirror;
+            } else {
+                rot = kSingular;
+            }
         }
-        bool on_bad = angle_between(phi, a.beta1) == 0.0 || angle_between(phi, a.beta2) == 0.0;
-        if (on_bad) {
+    } else {
+        // swept means: on the way from angle 0 to phi
+        auto swept = [phi](double b) {
+            return phi > 0.0 ? (b > 0.0 && b < phi) : (b <= 0.0 && b > phi);
+        };
+        bool past1 = false, on_bad = false;
+        delta = M_PI;
+        for (int k = 0; k < a.n1; ++k) {
+            past1 = past1 || swept(a.b1[k]);
+            on_bad = on_bad || angle_between(phi, a.b1[k]) == 0.0;
+            delta = fmin(delta, angle_between(phi, a.b1[k]));
+        }
+        for (int k = 0; k < a.n2; ++k) {
+            if (swept(a.b2[k])) mask |= 1 << k;
+            on_bad = on_bad || angle_between(phi, a.b2[k]) == 0.0;
+            delta = fmin(delta, angle_between(phi, a.b2[k]));
+        }
+        if (phi > a.lo && phi < a.hi) {
+            rot = kY;
+            mask = 0;
+        } else if (on_bad) {
             rot = kSingular;
-        } else if (past2 && !past1) {
+        } else if (mask != 0 && !past1) {
             rot = kYRes;
             *res_sign = phi > 0.0 ? 1 : -1;
-        } else if (past1 && !past2 && a.mirror_ok) {
+        } else if (past1 && mask == 0 && a.mirror_ok) {
             rot = kMirror;
         } else {
             rot = kSingular;
         }
+        if (rot != kYRes) mask = 0;
     }
     if (v < a.vstar) {
-        double delta = fmin(angle_between(phi, a.beta1), angle_between(phi, a.beta2));
         if (v < kRNear * a.vstar || 1.0 - v / a.vstar >= kRSlope * delta || rot == kSingular) {
             *res_sign = 0;
+            if (res_mask) *res_mask = 0;
             return kR;
         }
     }
+    if (res_mask) *res_mask = mask;
     return rot;
 }
 
@@ -129,6 +168,7 @@ struct PointCtx {
     double phi;
     int nodes;  // contour nodes of this point
     int res_sign;
+    int res_mask;  // pole sums: the k-leg poles whose residue node is due
     double tb[5];  // split radial rule: piece boundaries in t = log(1+r)
 };
 
@@ -175,12 +215,14 @@ __device__ void split_boundaries(const Args &a, double xr, double xi, double *b)
     }
 }
 
-template <bool SPLIT = false, class Args>
-__device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign)
+template <bool SPLIT = false, bool POLES = false, class Args>
+__device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign,
+                                int res_mask = 1)
 {
     PointCtx P;
     P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
     P.res_sign = res_sign;
+    P.res_mask = res_mask;
     if (SPLIT) {
         double b[5];
         split_boundaries(a, xr, xi, b);
@@ -201,7 +243,7 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
             P.dirD = P.dir;
         }
         P.phi = phi;
-        P.nodes = a.n_r + a.n_arc + (cls == kYRes ? 1 : 0);
+        P.nodes = a.n_r + a.n_arc + (cls == kYRes ? (POLES ? __popc(res_mask) : 1) : 0);
     } else {
         P.dir = mk(1.0, 0.0);
         P.dirD = P.dir;
@@ -244,7 +286,19 @@ __device__ __forceinline__ void radial_node(const Args &a, const PointCtx &P, in
     g = a.dim == 4 ? dr * r : (a.dim == 3 ? dr * sqrt(r) : dr);
 }
 
-template <bool SPLIT = false, class Args>
+// The k-leg pole sum P2(y) = sum_b c2_b / (y + m2_b^2).
+template <class Args>
+__device__ __forceinline__ cd prop2(const Args &a, cd y)
+{
+    cd p = mk(0.0, 0.0);
+    for (int b = 0; b < a.n2; ++b) {
+        const auto *q = &a.p2[4 * b];
+        p = cadd(p, cdiv(mk(q[2], q[3]), cadd(y, mk(q[0], q[1]))));
+    }
+    return p;
+}
+
+template <bool SPLIT = false, bool POLES = false, class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V2, cd &w)
 {
@@ -258,7 +312,10 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
         const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
         U = cadd(P.x1, y);
         V2 = cmul(x4, y);                                      // 4 x y
-        w = cdiv(cscale(P.dirD, g), cadd(y, m2));
+        if (POLES)
+            w = cmul(cscale(P.dirD, g), prop2(a, y));
+        else
+            w = cdiv(cscale(P.dirD, g), cadd(y, m2));
     } else if (k < a.n_r + a.n_arc) {
         const int q = k - a.n_r;
         const auto *arc = ro(a.arc);
@@ -279,13 +336,31 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
         } else if (a.dim == 2) {
             f = mk(1.0, 0.0);
         }
-        w = cdiv(cmul(dy, f), cadd(y, m2));
-    } else {
+        if (POLES)
+            w = cmul(cmul(dy, f), prop2(a, y));
+        else
+            w = cdiv(cmul(dy, f), cadd(y, m2));
+    } else if (!POLES) {
         const cd y0 = mk(-a.m2_re, -a.m2_im);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
         const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i Res
         const cd fy = a.dim == 4 ? y0 : (a.dim == 3 ? mk(a.sy0_re, a.sy0_im) : mk(1.0, 0.0));
+        w = mk(-fy.i * f, fy.r * f);
+    } else {
+        // residue node j: the j-th k-leg pole flagged in res_mask
+        const int j = k - a.n_r - a.n_arc;
+        int m = P.res_mask;
+        for (int it = 0; it < j; ++it) m &= m - 1;  // drop the j lowest flags
+        const int b = m ? __ffs(m) - 1 : 0;
+        const auto *q = &a.p2[4 * b];
+        const cd y0 = mk(-q[0], -q[1]);
+        U = cadd(P.x1, y0);
+        V2 = cmul(x4, y0);
+        const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i c2_b y0^{(D-2)/2}
+        const cd fy = cmul(mk(q[2], q[3]), a.dim == 4 ? y0
+                                           : (a.dim == 3 ? csqrt_principal(y0.r, y0.i)
+                                                         : mk(1.0, 0.0)));
         w = mk(-fy.i * f, fy.r * f);
     }
 }
@@ -451,6 +526,21 @@ __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 {
     if (PREC == 0 || near_angular_cut(U, V2)) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
     return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V2);
+}
+
+// Pole sums: <P1(D1)> = sum_a c1_a <1/(U_a - V z)>, U_a = U + m1_a^2 - m1_0^2
+// (U carries pole 0); one folded angular sum per pole.
+template <int PREC, bool POLES, class Args>
+__device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2)
+{
+    if (!POLES) return angular_sum<PREC>(a, U, V2);
+    cd A = mk(0.0, 0.0);
+    for (int p = 0; p < a.n1; ++p) {
+        const auto *q = &a.p1[4 * p];
+        const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
+        A = cadd(A, cmul(mk(q[2], q[3]), angular_sum<PREC>(a, Ua, V2)));
+    }
+    return A;
 }
 
 }  // namespace

@@ -9,8 +9,8 @@ namespace {
 // y-plane diagnostic (the paper's Fig. 1): at fixed x, the angular average
 // <1/D1>(x, y) over a cell-centred grid of complex y (what = 0), or the
 // order-0 subtracted y-integrand y^{(D-2)/2}/(y + m2^2) (<1/D1>(x, y) -
-// <1/D1>(mu^2, y)) of eq. 14 (what = 1).  One lane per y point, 8 x 8 tiles,
-// FP64.
+// <1/D1>(mu^2, y)) of eq. 14 (what = 1); with pole sums, <P1> and P2(y) in
+// place of <1/D1> and 1/(y + m2^2).  One lane per y point, 8 x 8 tiles, FP64.
 __global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, double xi, double mu2,
                                                     int what)
 {
@@ -23,13 +23,23 @@ __global__ void __launch_bounds__(256) yscan_kernel(ScanArgs a, double xr, doubl
     const cd y = mk(fma((double)ia + 0.5, a.d_re, a.re_lo), fma((double)ib + 0.5, a.d_im, a.im_lo));
     const cd x = mk(xr, xi);
     const cd m1 = mk(a.m1_re, a.m1_im);
-    cd A = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(cadd(x, y), m1), cmul(mk(4.0 * xr, 4.0 * xi), y));
+    const cd V2 = cmul(mk(4.0 * xr, 4.0 * xi), y);
+    cd A;
+    if (!a.poles) {
+        A = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(cadd(x, y), m1), V2);
+    } else {
+        A = angular_sum_p<0, true>(a, cadd(cadd(x, y), m1), V2);  // <P1((p-k)^2)>
+    }
     if (what == 1) {
-        const cd Amu = angular_sum64(a.ang, a.n_a / 2, a.wmid, cadd(mk(mu2 + y.r, y.i), m1),
-                                     cscale(y, 4.0 * mu2));
+        const cd Umu = cadd(mk(mu2 + y.r, y.i), m1), V2mu = cscale(y, 4.0 * mu2);
+        const cd Amu = a.poles ? angular_sum_p<0, true>(a, Umu, V2mu)
+                               : angular_sum64(a.ang, a.n_a / 2, a.wmid, Umu, V2mu);
         // the radial measure y^{(D-2)/2} (principal sqrt(y) for D = 3)
         const cd f = a.dim == 4 ? y : (a.dim == 3 ? csqrt_principal(y.r, y.i) : mk(1.0, 0.0));
-        A = cdiv(cmul(f, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
+        if (!a.poles)
+            A = cdiv(cmul(f, mk(A.r - Amu.r, A.i - Amu.i)), cadd(y, mk(a.m2_re, a.m2_im)));
+        else
+            A = cmul(cmul(f, mk(A.r - Amu.r, A.i - Amu.i)), prop2(a, y));
     }
     const size_t idx = (size_t)ib * (size_t)a.n_re + (size_t)ia;
     reinterpret_cast<double2 *>(a.out)[idx] = make_double2(A.r, A.i);

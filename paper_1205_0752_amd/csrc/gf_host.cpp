@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -21,6 +22,8 @@ struct gf_plan {
     int device = -1;
     gf_params params{};
     gf_quadrature quad{};
+    gf_propagators props{};
+    bool has_props = false;
     void *d_mem = nullptr;       // one allocation holding every table
     gf::ScanArgs base{};         // kernel arguments minus the grid and outputs
     double jmu[2 * (GF_MAX_TAYLOR + 1)] = {};  // host copy of K_0..K_n
@@ -223,18 +226,59 @@ void arc_table(int nc, std::vector<double> &arc)
     }
 }
 
-void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
+namespace {
+
+// A propagator as a multiset of (m^2 re, m^2 im, c re, c im), optionally conjugated.
+std::vector<std::array<double, 4>> pole_set(const double *p, int n, bool conj)
+{
+    std::vector<std::array<double, 4>> v;
+    for (int k = 0; k < n; ++k) {
+        const double s = conj ? -1.0 : 1.0;
+        // + 0.0 turns -0.0 into +0.0 so that equal values compare equal
+        v.push_back({p[4 * k] + 0.0, s * p[4 * k + 1] + 0.0, p[4 * k + 2] + 0.0,
+                     s * p[4 * k + 3] + 0.0});
+    }
+    std::sort(v.begin(), v.end());
+    return v;
+}
+
+}  // namespace
+
+void fill_constants(ScanArgs &a, const gf_params &p, const gf_propagators *props,
+                    const gf_quadrature &q)
 {
     a.n_r = q.n_radial;
     a.n_a = q.n_angular;
     a.n_arc = q.n_arc;
-    a.m1_re = p.m1sq_re;
-    a.m1_im = p.m1sq_im;
-    a.m2_re = p.m2sq_re;
-    a.m2_im = p.m2sq_im;
+    // poles: from props, or one pole per leg at the masses of p with residue 1
+    a.poles = props ? 1 : 0;
+    a.n1 = props ? props->n1 : 1;
+    a.n2 = props ? props->n2 : 1;
+    for (int k = 0; k < GF_MAX_POLES; ++k) {
+        for (int c = 0; c < 4; ++c) a.p1[4 * k + c] = a.p2[4 * k + c] = 0.0;
+        a.b1[k] = a.b2[k] = 0.0;
+    }
+    for (int k = 0; k < a.n1; ++k) {
+        a.p1[4 * k] = props ? props->m1sq_re[k] : p.m1sq_re;
+        a.p1[4 * k + 1] = props ? props->m1sq_im[k] : p.m1sq_im;
+        a.p1[4 * k + 2] = props ? props->c1_re[k] : 1.0;
+        a.p1[4 * k + 3] = props ? props->c1_im[k] : 0.0;
+        a.b1[k] = bad_ray(a.p1[4 * k], a.p1[4 * k + 1]);
+    }
+    for (int k = 0; k < a.n2; ++k) {
+        a.p2[4 * k] = props ? props->m2sq_re[k] : p.m2sq_re;
+        a.p2[4 * k + 1] = props ? props->m2sq_im[k] : p.m2sq_im;
+        a.p2[4 * k + 2] = props ? props->c2_re[k] : 1.0;
+        a.p2[4 * k + 3] = props ? props->c2_im[k] : 0.0;
+        a.b2[k] = bad_ray(a.p2[4 * k], a.p2[4 * k + 1]);
+    }
+    a.m1_re = a.p1[0];
+    a.m1_im = a.p1[1];
+    a.m2_re = a.p2[0];
+    a.m2_im = a.p2[1];
     a.lam2 = p.lambda2;
     a.lam = std::sqrt(p.lambda2);
-    const std::complex<double> sy0 = std::sqrt(std::complex<double>(-p.m2sq_re, -p.m2sq_im));
+    const std::complex<double> sy0 = std::sqrt(std::complex<double>(-a.m2_re, -a.m2_im));
     a.sy0_re = sy0.real();
     a.sy0_im = sy0.imag();
     a.scale = p.scale;
@@ -242,23 +286,55 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q)
     a.dim = p.dimension == 0 ? 4 : p.dimension;
     a.split = q.radial_split;
     a.T = std::log1p(p.lambda2);
-    const std::complex<double> sm1 = std::sqrt(std::complex<double>(-p.m1sq_re, -p.m1sq_im));
+    const std::complex<double> sm1 = std::sqrt(std::complex<double>(-a.m1_re, -a.m1_im));
     a.sm1_re = sm1.real();
     a.sm1_im = sm1.imag();
     a.mu2 = p.mu2;
-    // bad rays arg(-m1^2), arg(-m2^2) and the open sector (lo, hi) around the
+    // bad rays arg(-m^2) of every pole and the open sector (lo, hi) around the
     // positive real axis that the ray can sweep without crossing one
-    a.beta1 = bad_ray(p.m1sq_re, p.m1sq_im);
-    a.beta2 = bad_ray(p.m2sq_re, p.m2sq_im);
+    a.beta1 = a.b1[0];
+    a.beta2 = a.b2[0];
     a.hi = M_PI;
     a.lo = -M_PI;
-    for (double b : {a.beta1, a.beta2}) {
+    a.vstar = INFINITY;
+    for (int k = 0; k < a.n1 + a.n2; ++k) {
+        const double b = k < a.n1 ? a.b1[k] : a.b2[k - a.n1];
         if (b > 0.0 && b < a.hi) a.hi = b;
         if (b <= 0.0 && b > a.lo) a.lo = b;
     }
-    a.vstar = std::real(std::sqrt(std::complex<double>(p.m1sq_re, p.m1sq_im)));
-    a.mirror_ok = (p.m1sq_im == 0.0 && p.m2sq_im == 0.0) ||
-                  (p.m1sq_re == p.m2sq_re && p.m1sq_im == -p.m2sq_im);
+    // the real axis is valid below the smallest Re sqrt(m1_a^2)
+    for (int k = 0; k < a.n1; ++k)
+        a.vstar = std::min(a.vstar,
+                           std::real(std::sqrt(std::complex<double>(a.p1[4 * k], a.p1[4 * k + 1]))));
+    // G(conj x) = conj G(x) when conjugation maps (P1, P2) onto itself or onto (P2, P1)
+    const auto P1 = pole_set(a.p1, a.n1, false), P2 = pole_set(a.p2, a.n2, false);
+    const auto C1 = pole_set(a.p1, a.n1, true), C2 = pole_set(a.p2, a.n2, true);
+    a.mirror_ok = (C1 == P1 && C2 == P2) || (C1 == P2 && C2 == P1);
+}
+
+int validate_props(const gf_propagators *props, const gf_quadrature &q)
+{
+    if (!props) return GF_OK;
+    if (props->n1 < 1 || props->n1 > GF_MAX_POLES || props->n2 < 1 || props->n2 > GF_MAX_POLES)
+        return fail(GF_EINVAL, "n1, n2 must be in [1, %d], got %d, %d", GF_MAX_POLES, props->n1,
+                    props->n2);
+    for (int leg = 0; leg < 2; ++leg) {
+        const int n = leg ? props->n2 : props->n1;
+        const double *mr = leg ? props->m2sq_re : props->m1sq_re;
+        const double *mi = leg ? props->m2sq_im : props->m1sq_im;
+        const double *cr = leg ? props->c2_re : props->c1_re;
+        const double *ci = leg ? props->c2_im : props->c1_im;
+        for (int k = 0; k < n; ++k) {
+            if (!finite(mr[k]) || !finite(mi[k]) || !finite(cr[k]) || !finite(ci[k]))
+                return fail(GF_EINVAL, "pole positions and residues must be finite");
+            if (mi[k] == 0.0 && mr[k] <= 0.0)
+                return fail(GF_EINVAL, "pole %d of leg %d lies on the non-positive real axis", k,
+                            leg + 1);
+        }
+    }
+    if (q.radial_split && (props->n1 > 1 || props->n2 > 1))
+        return fail(GF_EUNSUPPORTED, "the split radial rule needs one pole per leg");
+    return GF_OK;
 }
 
 int validate_params(const gf_params *p, const gf_quadrature *q)
@@ -302,7 +378,7 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
     return GF_OK;
 }
 
-int validate_grid(const gf_params &p, const gf_grid *g)
+int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid *g)
 {
     if (!g) return fail(GF_EINVAL, "grid must not be NULL");
     if (g->n_re < 0 || g->n_im < 0) return fail(GF_EINVAL, "grid sizes must be >= 0");
@@ -314,8 +390,13 @@ int validate_grid(const gf_params &p, const gf_grid *g)
     if (!(g->re_lo < g->re_hi) || !(g->im_lo < g->im_hi))
         return fail(GF_EINVAL, "grid bounds must satisfy lo < hi");
     // the closing arc |y| = Lambda^2 must clear the angular cut, which reaches
-    // out to |y| = (sqrt|x| + sqrt(|x| + |m1^2|))^2
-    const double m1abs = std::hypot(p.m1sq_re, p.m1sq_im);
+    // out to |y| = (sqrt|x| + sqrt(|x| + |m1^2|))^2 (largest |m1_a^2| of a pole sum)
+    double m1abs = std::hypot(p.m1sq_re, p.m1sq_im);
+    if (props) {
+        m1abs = 0.0;
+        for (int k = 0; k < props->n1; ++k)
+            m1abs = std::max(m1abs, std::hypot(props->m1sq_re[k], props->m1sq_im[k]));
+    }
     const double cr[2] = {g->re_lo, g->re_hi}, ci[2] = {g->im_lo, g->im_hi};
     for (double a : cr)
         for (double b : ci) {
@@ -393,10 +474,17 @@ const char *gf_version(void) { return "gf 0.2 (gfx950)"; }
 
 int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
 {
+    return gf_plan_ex(params, nullptr, quad, out);
+}
+
+int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_quadrature *quad,
+               gf_plan_t **out)
+{
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
     *out = nullptr;
     int rc = gf::validate_params(params, quad);
     if (rc != GF_OK) return rc;
+    if ((rc = gf::validate_props(props, *quad)) != GF_OK) return rc;
     int dev;
     if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
 
@@ -442,8 +530,12 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
         }
     }
 
+    if (props) {
+        plan->props = *props;
+        plan->has_props = true;
+    }
     gf::ScanArgs &a = plan->base;
-    gf::fill_constants(a, *params, *quad);
+    gf::fill_constants(a, *params, props, *quad);
     a.rad = reinterpret_cast<const double *>(base + off_rad);
     a.ang = reinterpret_cast<const double *>(base + off_ang);
     a.arc = reinterpret_cast<const double *>(base + off_arc);
@@ -513,7 +605,7 @@ int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_
                     int lanes_per_point, void *stream)
 {
     if (!plan) return fail(GF_EINVAL, "plan must not be NULL");
-    int rc = gf::validate_grid(plan->params, grid);
+    int rc = gf::validate_grid(plan->params, plan->has_props ? &plan->props : nullptr, grid);
     if (rc != GF_OK) return rc;
     if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
@@ -602,13 +694,13 @@ int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_sampl
     const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2, 0};  // the map needs no nodes
     int rc = gf::validate_params(params, &q1);
     if (rc != GF_OK) return rc;
-    if ((rc = gf::validate_grid(*params, grid)) != GF_OK) return rc;
+    if ((rc = gf::validate_grid(*params, nullptr, grid)) != GF_OK) return rc;
     if (n_samples < 2 || n_samples > (1 << 20))
         return fail(GF_EINVAL, "n_samples must be in [2, 2^20], got %d", n_samples);
     if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
     gf::ScanArgs a{};
-    gf::fill_constants(a, *params, q1);
+    gf::fill_constants(a, *params, nullptr, q1);
     if ((rc = gf::set_grid(a, *grid, 1)) != GF_OK) return rc;
     hipError_t e = gf::launch_obstruction(a, n_samples, std::log1p(params->lambda2), out,
                                           static_cast<hipStream_t>(stream));

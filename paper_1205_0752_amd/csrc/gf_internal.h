@@ -46,6 +46,14 @@ struct ScanArgs {
     int split;                           // split radial rule (rad then holds GL xi, w)
     double T;                            // log(1 + Lambda^2)
     double sm1_re, sm1_im;               // sqrt(-m1^2), principal
+
+    // general propagators: n1, n2 poles, per pole (m^2 re, m^2 im, c re, c im),
+    // and each pole's bad ray arg(-m^2); pole 0 is also in m1_*, m2_*
+    int poles;  // 0: one pole per leg with residue 1 (the fields above suffice)
+    int n1, n2;
+    double p1[4 * GF_MAX_POLES];
+    double p2[4 * GF_MAX_POLES];
+    double b1[GF_MAX_POLES], b2[GF_MAX_POLES];
     double mu2;
     double scale;
 
@@ -91,11 +99,11 @@ hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double
                             hipStream_t s);
 
 // Persistent launch of `waves` wavefronts over n_items work items (device
-// arrays); *counter must be 0 on entry.  All items share precision, lanes and
-// the split flag of the radial rule.
+// arrays); *counter must be 0 on entry.  All items share precision, lanes,
+// the split flag of the radial rule and the pole-sum flag.
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
-                        unsigned *counter, int precision, int lanes, int split, int waves,
-                        hipStream_t s);
+                        unsigned *counter, int precision, int lanes, int split, int poles,
+                        int waves, hipStream_t s);
 
 // ---- host helpers shared by plans and the server (gf_host.cpp) ----------
 
@@ -111,9 +119,11 @@ void angular_tables(int n_a, int rule, int dim, std::vector<double> &ang,
                     std::vector<float> &ang32, double *wmid);
 void arc_table(int n_arc, std::vector<double> &arc);
 // masses, cutoff, scale and contour geometry of a (params, quadrature)
-void fill_constants(ScanArgs &a, const gf_params &p, const gf_quadrature &q);
+void fill_constants(ScanArgs &a, const gf_params &p, const gf_propagators *props,
+                    const gf_quadrature &q);
+int validate_props(const gf_propagators *props, const gf_quadrature &q);
 int validate_params(const gf_params *p, const gf_quadrature *q);
-int validate_grid(const gf_params &p, const gf_grid *g);
+int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid *g);
 // lanes per point the automatic choice uses for a grid
 int auto_lanes(const gf_grid &g);
 // grid fields and wave tiles of a ScanArgs for `lanes` lanes per point

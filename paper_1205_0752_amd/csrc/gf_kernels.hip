@@ -24,7 +24,7 @@ namespace {
 // point's result does not depend on which launch computes it.
 // TAYLOR = false compiles out the t^n (n >= 1) epilogue, so the order-0 scan
 // carries no extra live values; both forms compute order 0 identically.
-template <int PREC, int L, bool TAYLOR, bool SPLIT, class Args>
+template <int PREC, int L, bool TAYLOR, bool SPLIT, bool POLES, class Args>
 __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 {
     constexpr int P = 64 / L;
@@ -38,24 +38,24 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
     double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
     double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
-    int sign = 0;
-    int cls = valid ? classify(a, xr, xi, &sign) : kSingular;
+    int sign = 0, mask = 1;
+    int cls = valid ? classify<POLES>(a, xr, xi, &sign, &mask) : kSingular;
     int ecls = cls;
     if (cls == kMirror) {
         xi = -xi;  // evaluate at conj x, conjugate the result
-        ecls = classify(a, xr, xi, &sign);
+        ecls = classify<POLES>(a, xr, xi, &sign, &mask);
         if (ecls == kMirror || ecls == kSingular) {
             cls = kSingular;
             ecls = kSingular;
         }
     }
-    const PointCtx pc = point_setup<SPLIT>(a, xr, xi, ecls, sign);
+    const PointCtx pc = point_setup<SPLIT, POLES>(a, xr, xi, ecls, sign, mask);
 
     double sr = 0.0, si = 0.0;
     for (int k = s; k < pc.nodes; k += L) {
         cd U, V2, w;
-        node_coeffs<SPLIT>(a, pc, k, U, V2, w);
-        cd A = angular_sum<PREC>(a, U, V2);
+        node_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
+        cd A = angular_sum_p<PREC, POLES>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -96,28 +96,28 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
 // Register budgets: the FP64 kernel runs best at 5 waves per SIMD, the FP32C
 // kernel at 6 (measured; the few spills this costs sit outside the inner loop).
-template <int L, bool TAYLOR, bool SPLIT>
+template <int L, bool TAYLOR, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<0, L, TAYLOR, SPLIT>(a, wave, threadIdx.x & 63);
+    process_tile<0, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
 }
 
-template <int L, bool TAYLOR, bool SPLIT>
+template <int L, bool TAYLOR, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<1, L, TAYLOR, SPLIT>(a, wave, threadIdx.x & 63);
+    process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
 // many requests.  Each wave takes the next item from a device counter (one
 // lane's atomic, broadcast) until the list is exhausted, so every wave exits.
-template <int PREC, int L, bool SPLIT>
+template <int PREC, int L, bool SPLIT, bool POLES>
 __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem *items, int n_items,
                                            unsigned *counter)
 {
@@ -129,24 +129,24 @@ __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem 
         if (w >= (unsigned)n_items) break;
         const int req = ro(items)[w].req;
         const int tile = ro(items)[w].tile;
-        process_tile<PREC, L, true, SPLIT>(ro(reqs)[req], tile, lane);
+        process_tile<PREC, L, true, SPLIT, POLES>(ro(reqs)[req], tile, lane);
     }
 }
 
-template <int L, bool SPLIT>
+template <int L, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 serve_kernel_fp64(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
                   int n_items, unsigned *counter)
 {
-    serve_loop<0, L, SPLIT>(reqs, items, n_items, counter);
+    serve_loop<0, L, SPLIT, POLES>(reqs, items, n_items, counter);
 }
 
-template <int L, bool SPLIT>
+template <int L, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 serve_kernel_fp32c(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
                    int n_items, unsigned *counter)
 {
-    serve_loop<1, L, SPLIT>(reqs, items, n_items, counter);
+    serve_loop<1, L, SPLIT, POLES>(reqs, items, n_items, counter);
 }
 
 // Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
@@ -190,24 +190,32 @@ __device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd 
 // wavefront: K_0 = the subtraction sum of eq. 14 (the order-0 operator t^0),
 // and for t^n with n >= 1 the Taylor coefficients K_i = (1/i!) d^i/dx^i of the
 // same sum (eq. 13 about x = mu^2).
-template <bool SPLIT, class Args>
+template <bool SPLIT, bool POLES, class Args>
 __device__ __forceinline__ void jmu_wave_impl(const Args &a, double mu2, double *dst, int lane)
 {
-    const PointCtx pc = point_setup<SPLIT>(a, mu2, 0.0, kR, 0);
+    const PointCtx pc = point_setup<SPLIT, POLES>(a, mu2, 0.0, kR, 0, 0);
     double sr = 0.0, si = 0.0;
     cd acc[GF_MAX_TAYLOR + 1];
     for (int i = 0; i <= GF_MAX_TAYLOR; ++i) acc[i] = mk(0.0, 0.0);
     for (int k = lane; k < pc.nodes; k += 64) {
         cd U, V2, w;
-        node_coeffs<SPLIT>(a, pc, k, U, V2, w);
-        cd A = angular_sum<0>(a, U, V2);
+        node_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
+        cd A = angular_sum_p<0, POLES>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
         if (a.n_taylor > 0) {
             double r, g;
             radial_node<SPLIT>(a, pc, k, r, g);
-            taylor_node(a, U, r, w, a.n_taylor, acc);
+            if (!POLES) {
+                taylor_node(a, U, r, w, a.n_taylor, acc);
+            } else {
+                for (int p = 0; p < a.n1; ++p) {  // pole a of P1: U_a, weight c1_a omega
+                    const auto *q = &a.p1[4 * p];
+                    const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
+                    taylor_node(a, Ua, r, cmul(w, mk(q[2], q[3])), a.n_taylor, acc);
+                }
+            }
         }
     }
 #pragma unroll
@@ -236,10 +244,12 @@ __device__ __forceinline__ void jmu_wave_impl(const Args &a, double mu2, double 
 template <class Args>
 __device__ __forceinline__ void jmu_wave(const Args &a, double mu2, double *dst, int lane)
 {
-    if (a.split)
-        jmu_wave_impl<true>(a, mu2, dst, lane);
+    if (a.poles)
+        jmu_wave_impl<false, true>(a, mu2, dst, lane);  // split needs single poles
+    else if (a.split)
+        jmu_wave_impl<true, false>(a, mu2, dst, lane);
     else
-        jmu_wave_impl<false>(a, mu2, dst, lane);
+        jmu_wave_impl<false, false>(a, mu2, dst, lane);
 }
 
 __global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double *dst)
@@ -264,24 +274,30 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
     const int blocks = (a.n_tiles + 3) / 4;
     const bool taylor = a.n_taylor > 0, split = a.split != 0;
     const dim3 g(blocks), b(256);
+    // pole sums run one kernel form (t^n epilogue compiled in; the split rule
+    // needs single poles); single poles pick the form without unused parts
     if (precision == 0) {
-        if (taylor && split)
-            hipLaunchKernelGGL((scan_kernel_fp64<L, true, true>), g, b, 0, s, a);
+        if (a.poles)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true, false, true>), g, b, 0, s, a);
+        else if (taylor && split)
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true, true, false>), g, b, 0, s, a);
         else if (taylor)
-            hipLaunchKernelGGL((scan_kernel_fp64<L, true, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp64<L, true, false, false>), g, b, 0, s, a);
         else if (split)
-            hipLaunchKernelGGL((scan_kernel_fp64<L, false, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp64<L, false, true, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((scan_kernel_fp64<L, false, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp64<L, false, false, false>), g, b, 0, s, a);
     } else if (precision == 1) {
-        if (taylor && split)
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, true>), g, b, 0, s, a);
+        if (a.poles)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, false, true>), g, b, 0, s, a);
+        else if (taylor && split)
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, true, false>), g, b, 0, s, a);
         else if (taylor)
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, true, false, false>), g, b, 0, s, a);
         else if (split)
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, true, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((scan_kernel_fp32c<L, false, false, false>), g, b, 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -290,23 +306,29 @@ hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 
 template <int L>
 hipError_t serve_l(const ScanArgs *reqs, const WorkItem *items, int n_items, unsigned *counter,
-                   int precision, int split, int waves, hipStream_t s)
+                   int precision, int split, int poles, int waves, hipStream_t s)
 {
     const dim3 g((waves + 3) / 4), b(256);
     if (precision == 0) {
-        if (split)
-            hipLaunchKernelGGL((serve_kernel_fp64<L, true>), g, b, 0, s, reqs, items, n_items,
-                               counter);
+        if (poles)
+            hipLaunchKernelGGL((serve_kernel_fp64<L, false, true>), g, b, 0, s, reqs, items,
+                               n_items, counter);
+        else if (split)
+            hipLaunchKernelGGL((serve_kernel_fp64<L, true, false>), g, b, 0, s, reqs, items,
+                               n_items, counter);
         else
-            hipLaunchKernelGGL((serve_kernel_fp64<L, false>), g, b, 0, s, reqs, items, n_items,
-                               counter);
+            hipLaunchKernelGGL((serve_kernel_fp64<L, false, false>), g, b, 0, s, reqs, items,
+                               n_items, counter);
     } else if (precision == 1) {
-        if (split)
-            hipLaunchKernelGGL((serve_kernel_fp32c<L, true>), g, b, 0, s, reqs, items, n_items,
-                               counter);
+        if (poles)
+            hipLaunchKernelGGL((serve_kernel_fp32c<L, false, true>), g, b, 0, s, reqs, items,
+                               n_items, counter);
+        else if (split)
+            hipLaunchKernelGGL((serve_kernel_fp32c<L, true, false>), g, b, 0, s, reqs, items,
+                               n_items, counter);
         else
-            hipLaunchKernelGGL((serve_kernel_fp32c<L, false>), g, b, 0, s, reqs, items, n_items,
-                               counter);
+            hipLaunchKernelGGL((serve_kernel_fp32c<L, false, false>), g, b, 0, s, reqs, items,
+                               n_items, counter);
     } else {
         return hipErrorInvalidValue;
     }
@@ -345,18 +367,18 @@ hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double
 }
 
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
-                        unsigned *counter, int precision, int lanes, int split, int waves,
-                        hipStream_t s)
+                        unsigned *counter, int precision, int lanes, int split, int poles,
+                        int waves, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     switch (lanes) {
-    case 1: return serve_l<1>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 2: return serve_l<2>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 4: return serve_l<4>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 8: return serve_l<8>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 16: return serve_l<16>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 32: return serve_l<32>(reqs, items, n_items, counter, precision, split, waves, s);
-    case 64: return serve_l<64>(reqs, items, n_items, counter, precision, split, waves, s);
+    case 1: return serve_l<1>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 2: return serve_l<2>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 4: return serve_l<4>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 8: return serve_l<8>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 16: return serve_l<16>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 32: return serve_l<32>(reqs, items, n_items, counter, precision, split, poles, waves, s);
+    case 64: return serve_l<64>(reqs, items, n_items, counter, precision, split, poles, waves, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -103,6 +103,8 @@ struct Request {
     gf_params p{};
     gf_grid g{};
     gf_quadrature q{};
+    gf_propagators props{};
+    bool has_props = false;
     int state = GF_REQ_QUEUED;
     int slot = -1;
     size_t out_off = 0, out_bytes = 0;
@@ -321,7 +323,7 @@ bool gf_server::admit_one(Request *r, Stage &st, std::vector<Request *> &fresh,
     r->slot = free_slots.back();
     free_slots.pop_back();
     gf::ScanArgs &a = r->args;
-    gf::fill_constants(a, r->p, r->q);
+    gf::fill_constants(a, r->p, r->has_props ? &r->props : nullptr, r->q);
     a.rad = reinterpret_cast<const double *>(d_arena + tb[0]->off);
     a.ang = reinterpret_cast<const double *>(d_arena + tb[1]->off);
     a.ang32 = reinterpret_cast<const float *>(d_arena + tb[1]->off + tb[1]->off32);
@@ -362,8 +364,8 @@ void gf_server::run()
         Batch b;
         std::vector<Request *> fresh;
         std::vector<Upload> uploads;
-        // launch groups: (precision, lanes per point, split radial rule)
-        std::map<std::tuple<int, int, int>, std::vector<gf::WorkItem>> groups;
+        // launch groups: (precision, lanes per point, split radial rule, pole sums)
+        std::map<std::tuple<int, int, int, int>, std::vector<gf::WorkItem>> groups;
         Stage &st = stage[next_stage];
         {
             std::unique_lock<std::mutex> lock(mu);
@@ -405,7 +407,8 @@ void gf_server::run()
                         k = std::max(1LL, std::min(k, left));
                         k = std::min(k, kMaxItemsPerBatch - b.items);
                         if (k <= 0) break;
-                        auto &vec = groups[{r->q.precision, r->lanes, r->q.radial_split}];
+                        auto &vec = groups[{r->q.precision, r->lanes, r->q.radial_split,
+                                            r->has_props ? 1 : 0}];
                         for (long long t = 0; t < k; ++t)
                             vec.push_back(gf::WorkItem{r->slot, (int32_t)(r->next_tile + t)});
                         r->next_tile += k;
@@ -473,7 +476,8 @@ void gf_server::run()
                                      reinterpret_cast<const gf::WorkItem *>(st.d + off_items[gi]), n,
                                      reinterpret_cast<unsigned *>(st.d + off_cnt) + gi,
                                      std::get<0>(kv.first), std::get<1>(kv.first),
-                                     std::get<2>(kv.first), waves, stream);
+                                     std::get<2>(kv.first), std::get<3>(kv.first), waves,
+                                     stream);
                 ++gi;
             }
             if (e == hipSuccess) e = hipEventRecord(stage_ev[next_stage], stream);
@@ -570,9 +574,16 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out)
 int gf_server_submit(gf_server_t *s, const gf_params *params, const gf_grid *grid,
                      const gf_quadrature *quad, uint64_t *ticket)
 {
+    return gf_server_submit_ex(s, params, nullptr, grid, quad, ticket);
+}
+
+int gf_server_submit_ex(gf_server_t *s, const gf_params *params, const gf_propagators *props,
+                        const gf_grid *grid, const gf_quadrature *quad, uint64_t *ticket)
+{
     if (!s || !ticket) return fail(GF_EINVAL, "NULL argument");
     int rc = gf::validate_params(params, quad);
-    if (rc == GF_OK) rc = gf::validate_grid(*params, grid);
+    if (rc == GF_OK) rc = gf::validate_props(props, *quad);
+    if (rc == GF_OK) rc = gf::validate_grid(*params, props, grid);
     std::lock_guard<std::mutex> lock(s->mu);
     if (rc != GF_OK) {
         ++s->n_rejected;
@@ -584,6 +595,10 @@ int gf_server_submit(gf_server_t *s, const gf_params *params, const gf_grid *gri
     r->p = *params;
     r->g = *grid;
     r->q = *quad;
+    if (props) {
+        r->props = *props;
+        r->has_props = true;
+    }
     r->out_bytes = (size_t)grid->n_re * (size_t)grid->n_im * 16;
     if (gf::align256(r->out_bytes) > s->arena.size()) {
         delete r;
@@ -597,7 +612,7 @@ int gf_server_submit(gf_server_t *s, const gf_params *params, const gf_grid *gri
     // one lane per point: the batch already fills the GPU with many requests,
     // and whole 64-point tiles waste no lanes on short node lists
     r->lanes = 1;
-    r->cost_per_tile = (64.0 / r->lanes) * nominal_evals_per_point(*quad) *
+    r->cost_per_tile = (64.0 / r->lanes) * nominal_evals_per_point(*quad) * (props ? props->n1 : 1) *
                        (quad->precision == GF_PREC_FP32C ? 0.6 : 1.0);
     r->t_submit = Clock::now();
     if (!s->any_submit) {

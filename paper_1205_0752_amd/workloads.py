@@ -43,6 +43,22 @@ class Params:
 
 
 @dataclasses.dataclass(frozen=True)
+class Propagators:
+    """Pole-sum propagators P1(s) = sum_a c1_a / (s + m1_a^2) on the (p-k) leg
+    and P2(s) = sum_b c2_b / (s + m2_b^2) on the k leg: tuples of (m^2, c),
+    1 to 8 poles each."""
+    poles1: tuple
+    poles2: tuple
+
+    @staticmethod
+    def conjugate_pair(m2: complex, c: complex = 0.5) -> tuple:
+        """A pole pair at m^2 and conj(m^2) with residues c and conj(c), e.g. the
+        propagator s / (s^2 + M^4) = (1/2)/(s + i M^2) + (1/2)/(s - i M^2)."""
+        m2, c = complex(m2), complex(c)
+        return ((m2, c), (m2.conjugate(), c.conjugate()))
+
+
+@dataclasses.dataclass(frozen=True)
 class Grid:
     """Cell-centred n_re x n_im box over [re_lo, re_hi] x [im_lo, im_hi];
     results are row-major with the Re index fastest."""
