@@ -280,13 +280,17 @@ int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_sampl
 
 /* ---- serving: continuous batching of scan requests ----------------------
  *
- * A server owns one HIP stream, a device-memory arena of `device_budget_bytes`
- * and a scheduler thread.  Submitted requests wait in FIFO order until their
- * output (16 bytes per point) and any node tables not yet resident fit in the
- * arena and a slot is free; admitted requests run concurrently: each scheduler
- * iteration packs wave tiles of every running request (a fair share of
- * `batch_evals` integrand evaluations each, oldest first) into persistent
- * kernel launches, and keeps two such batches in flight.  A request completes
+ * A server owns three HIP streams (one for staging and subtraction sums, two
+ * that take the persistent launches in turn), a device-memory arena of
+ * `device_budget_bytes` and a scheduler thread.  Submitted requests wait in
+ * FIFO order until their output (16 bytes per point) and any node tables not
+ * yet resident fit in the arena and a slot is free; admitted requests run
+ * concurrently: each scheduler iteration packs wave tiles of every running
+ * request (a fair share of `batch_evals` integrand evaluations each, oldest
+ * first, topped up with further tiles while the batch has fewer than about
+ * 1.5 tiles per wave slot of the device) into persistent kernel launches, most
+ * expensive tiles first, and keeps three such batches in flight; a launch's
+ * last long tiles overlap the next launch on the other stream.  A request completes
  * when its last tile has run; its result stays in the arena until
  * gf_server_release.  Every point is computed by the same device code and
  * tables as gf_scan_plan_ex with one lane per point, so a served result is

@@ -93,10 +93,11 @@ hipError_t launch_obstruction(const ScanArgs &a, int n, double T, uint8_t *out, 
 // Computes the unscaled real-axis sum at x = mu^2 (FP64) into dst[0..1].
 hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s);
 
-// The same for n requests at once: request i uses reqs[slots[i]] and mu2[i] and
-// writes into that request's jmu slot (device pointers).
-hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double *mu2, int n,
-                            hipStream_t s);
+// The same for n requests at once (device pointers): copies staged[i] into
+// reqs[slots[i]] and writes request i's coefficients, at mu2[i], into the jmu
+// slot that staged[i] names.
+hipError_t launch_jmu_batch(ScanArgs *reqs, const ScanArgs *staged, const int *slots,
+                            const double *mu2, int n, hipStream_t s);
 
 // Persistent launch of `waves` wavefronts over n_items work items (device
 // arrays); *counter must be 0 on entry.  All items share precision, lanes,
@@ -104,6 +105,11 @@ hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,
                         unsigned *counter, int precision, int lanes, int split, int poles,
                         int waves, hipStream_t s);
+
+// Wavefronts of that group's persistent kernel the current device holds at
+// once (occupancy x compute units x 4 waves per 256-thread block); 4096 if
+// the runtime cannot say.
+int serve_resident_waves(int precision, int lanes, int split, int poles);
 
 // ---- host helpers shared by plans and the server (gf_host.cpp) ----------
 

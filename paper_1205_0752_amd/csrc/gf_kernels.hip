@@ -257,14 +257,23 @@ __global__ void __launch_bounds__(64) jmu_kernel(ScanArgs a, double mu2, double 
     jmu_wave(a, mu2, dst, threadIdx.x);
 }
 
-// One wave per request: J_mu of request i into its args' jmu slot.
-__global__ void __launch_bounds__(64) jmu_batch_kernel(const ScanArgs *__restrict__ reqs,
+// One wave per request: installs request i's argument record (staged[i]) in
+// its slot of the request table, and writes J_mu (and the Taylor
+// coefficients) of that request into the record's jmu slot.
+__global__ void __launch_bounds__(64) jmu_batch_kernel(ScanArgs *__restrict__ reqs,
+                                                       const ScanArgs *__restrict__ staged,
                                                        const int *__restrict__ slots,
                                                        const double *__restrict__ mu2, int n)
 {
+    static_assert(sizeof(ScanArgs) % sizeof(unsigned long long) == 0, "record size");
     const int i = blockIdx.x;
     if (i >= n) return;
-    const auto &a = ro(reqs)[__builtin_amdgcn_readfirstlane(slots[i])];
+    const int slot = __builtin_amdgcn_readfirstlane(slots[i]);
+    constexpr int words = sizeof(ScanArgs) / sizeof(unsigned long long);
+    const auto *src = reinterpret_cast<const unsigned long long *>(staged + i);
+    auto *dst = reinterpret_cast<unsigned long long *>(reqs + slot);
+    for (int k = threadIdx.x; k < words; k += 64) dst[k] = src[k];
+    const auto &a = ro(staged)[i];
     jmu_wave(a, mu2[i], const_cast<double *>(a.jmu), threadIdx.x);
 }
 
@@ -358,12 +367,52 @@ hipError_t launch_jmu(const ScanArgs &a, double mu2, double *dst, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_jmu_batch(const ScanArgs *reqs, const int *slots, const double *mu2, int n,
-                            hipStream_t s)
+hipError_t launch_jmu_batch(ScanArgs *reqs, const ScanArgs *staged, const int *slots,
+                            const double *mu2, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(jmu_batch_kernel, dim3(n), dim3(64), 0, s, reqs, slots, mu2, n);
+    hipLaunchKernelGGL(jmu_batch_kernel, dim3(n), dim3(64), 0, s, reqs, staged, slots, mu2, n);
     return hipGetLastError();
+}
+
+namespace {
+
+template <int L>
+const void *serve_fn(int precision, int split, int poles)
+{
+    if (precision == 0)
+        return poles ? reinterpret_cast<const void *>(serve_kernel_fp64<L, false, true>)
+               : split ? reinterpret_cast<const void *>(serve_kernel_fp64<L, true, false>)
+                       : reinterpret_cast<const void *>(serve_kernel_fp64<L, false, false>);
+    if (precision == 1)
+        return poles ? reinterpret_cast<const void *>(serve_kernel_fp32c<L, false, true>)
+               : split ? reinterpret_cast<const void *>(serve_kernel_fp32c<L, true, false>)
+                       : reinterpret_cast<const void *>(serve_kernel_fp32c<L, false, false>);
+    return nullptr;
+}
+
+}  // namespace
+
+int serve_resident_waves(int precision, int lanes, int split, int poles)
+{
+    const void *f = nullptr;
+    switch (lanes) {
+    case 1: f = serve_fn<1>(precision, split, poles); break;
+    case 2: f = serve_fn<2>(precision, split, poles); break;
+    case 4: f = serve_fn<4>(precision, split, poles); break;
+    case 8: f = serve_fn<8>(precision, split, poles); break;
+    case 16: f = serve_fn<16>(precision, split, poles); break;
+    case 32: f = serve_fn<32>(precision, split, poles); break;
+    case 64: f = serve_fn<64>(precision, split, poles); break;
+    default: break;
+    }
+    int dev = 0, cus = 0, blocks = 0;
+    if (!f || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 256, 0) != hipSuccess ||
+        cus <= 0 || blocks <= 0)
+        return 4096;
+    return cus * blocks * 4;
 }
 
 hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items,

@@ -4,9 +4,15 @@
 // and node tables) and a slot table.  A scheduler thread repeatedly packs wave
 // tiles of every running request into persistent kernel launches (one per
 // precision x lanes-per-point group), giving each running request a fair share
-// of the batch's evaluation budget, and keeps two batches in flight so the GPU
-// never waits for the host.  A request is done when its last tile's batch has
-// completed (HIP event); its output stays in the arena until released.
+// of the batch's evaluation budget.  Within a launch the most expensive tiles
+// are handed out first, so the launch ends on short ones.  A batch's staging
+// copy, table uploads and subtraction sums run on a prologue stream; its
+// launches run on compute streams taken in turn, each waiting for its own
+// prologue only, so the waves of the next batch (and of the other precision)
+// fill the compute units that a launch's last long tiles leave idle.  Three
+// batches stay in flight so the GPU never waits for the host.  A request is
+// done when its last tile's batch has completed (HIP events); its output stays
+// in the arena until released.
 //
 // Every point is computed by the same device function, table values and
 // subtraction-sum kernel as a standalone scan with one lane per point, so a
@@ -138,13 +144,16 @@ struct Upload {
 };
 
 struct Batch {
-    hipEvent_t ev = nullptr;
+    std::vector<hipEvent_t> ev;  // all must complete
     int stage = 0;
     std::vector<std::pair<Request *, long long>> tiles;  // tiles per request
     long long items = 0;
 };
 
-constexpr int kStages = 3;
+constexpr int kMaxInflight = 3;
+constexpr int kStages = kMaxInflight + 1;  // one per batch in flight + the one being filled
+constexpr int kComputeStreams = 2;
+constexpr int kMaxGroups = 8;  // precision x split x pole sums (one lanes value)
 constexpr size_t kStageBytes = 32u << 20;
 constexpr long long kMaxItemsPerBatch = 1 << 20;
 constexpr int kMaxNewPerBatch = 256;
@@ -154,7 +163,12 @@ constexpr int kMaxNewPerBatch = 256;
 struct gf_server {
     int device = -1;
     gf_server_config cfg{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;           // prologue: staging, uploads, subtraction sums
+    hipStream_t comp[kComputeStreams] = {};  // persistent serve launches, in turn
+    int next_comp = 0;
+    hipEvent_t group_ev[kStages][kMaxGroups] = {};
+    std::map<std::tuple<int, int, int, int>, int> resident;  // waves per launch group
+    long long fill_items = 0;  // items a batch takes at least, while tiles remain
     char *d_arena = nullptr;
     Arena arena;
     gf::ScanArgs *d_args = nullptr;
@@ -365,6 +379,9 @@ void gf_server::run()
         std::vector<Request *> fresh;
         std::vector<Upload> uploads;
         // launch groups: (precision, lanes per point, split radial rule, pole sums)
+        // -> runs of consecutive tiles (request, first tile, count)
+        std::map<std::tuple<int, int, int, int>, std::vector<std::tuple<Request *, long long, long long>>>
+            runs;
         std::map<std::tuple<int, int, int, int>, std::vector<gf::WorkItem>> groups;
         Stage &st = stage[next_stage];
         {
@@ -407,10 +424,8 @@ void gf_server::run()
                         k = std::max(1LL, std::min(k, left));
                         k = std::min(k, kMaxItemsPerBatch - b.items);
                         if (k <= 0) break;
-                        auto &vec = groups[{r->q.precision, r->lanes, r->q.radial_split,
-                                            r->has_props ? 1 : 0}];
-                        for (long long t = 0; t < k; ++t)
-                            vec.push_back(gf::WorkItem{r->slot, (int32_t)(r->next_tile + t)});
+                        runs[{r->q.precision, r->lanes, r->q.radial_split, r->has_props ? 1 : 0}]
+                            .emplace_back(r, r->next_tile, k);
                         r->next_tile += k;
                         b.tiles.emplace_back(r, k);
                         b.items += k;
@@ -418,9 +433,39 @@ void gf_server::run()
                         if (budget <= 0.0 || b.items >= kMaxItemsPerBatch) break;
                     }
                 }
+                // the budget bought too few (long) tiles to occupy every wave
+                // slot: top up, oldest first, so the launch is not one short
+                // of work while tiles remain
+                for (Request *r : active) {
+                    if (b.items >= fill_items) break;
+                    const long long k = std::min(r->n_tiles - r->next_tile, fill_items - b.items);
+                    if (k <= 0) continue;
+                    runs[{r->q.precision, r->lanes, r->q.radial_split, r->has_props ? 1 : 0}]
+                        .emplace_back(r, r->next_tile, k);
+                    r->next_tile += k;
+                    b.tiles.emplace_back(r, k);
+                    b.items += k;
+                }
             }
         }
 
+        // longest tiles first within each launch (stable: ties keep admission order)
+        for (auto &kv : runs) {
+            auto &rv = kv.second;
+            std::stable_sort(rv.begin(), rv.end(), [](const auto &x, const auto &y) {
+                return std::get<0>(x)->cost_per_tile > std::get<0>(y)->cost_per_tile;
+            });
+            auto &vec = groups[kv.first];
+            for (const auto &run : rv)
+                for (long long t = 0; t < std::get<2>(run); ++t)
+                    vec.push_back(gf::WorkItem{std::get<0>(run)->slot,
+                                               (int32_t)(std::get<1>(run) + t)});
+        }
+
+        if (groups.size() > (size_t)kMaxGroups) {
+            fail_worker(hipErrorInvalidValue, "too many launch groups in one batch");
+            break;
+        }
         const bool launch_now = !fresh.empty() || b.items > 0;
         if (launch_now) {
             // stage: argument records, subtraction-sum inputs, counters, items
@@ -460,32 +505,42 @@ void gf_server::run()
             for (size_t k = 0; e == hipSuccess && k < uploads.size(); ++k)
                 e = hipMemcpyAsync(d_arena + uploads[k].arena_off, st.d + uploads[k].stage_off,
                                    uploads[k].bytes, hipMemcpyDeviceToDevice, stream);
-            for (size_t i = 0; e == hipSuccess && i < fresh.size(); ++i)
-                e = hipMemcpyAsync(d_args + fresh[i]->slot, st.d + off_args + i * sizeof(gf::ScanArgs),
-                                   sizeof(gf::ScanArgs), hipMemcpyDeviceToDevice, stream);
             if (e == hipSuccess && !fresh.empty())
-                e = gf::launch_jmu_batch(d_args, reinterpret_cast<const int *>(st.d + off_slots),
+                e = gf::launch_jmu_batch(d_args, reinterpret_cast<const gf::ScanArgs *>(st.d + off_args),
+                                         reinterpret_cast<const int *>(st.d + off_slots),
                                          reinterpret_cast<const double *>(st.d + off_mu2),
                                          (int)fresh.size(), stream);
+            if (e == hipSuccess) e = hipEventRecord(stage_ev[next_stage], stream);
             size_t gi = 0;
             for (auto &kv : groups) {
                 if (e != hipSuccess) break;
                 const int n = (int)kv.second.size();
-                const int waves = std::min(n, 4096);
-                e = gf::launch_serve(d_args,
-                                     reinterpret_cast<const gf::WorkItem *>(st.d + off_items[gi]), n,
-                                     reinterpret_cast<unsigned *>(st.d + off_cnt) + gi,
-                                     std::get<0>(kv.first), std::get<1>(kv.first),
-                                     std::get<2>(kv.first), std::get<3>(kv.first), waves,
-                                     stream);
+                auto rit = resident.find(kv.first);
+                if (rit == resident.end())
+                    rit = resident
+                              .emplace(kv.first, gf::serve_resident_waves(
+                                                     std::get<0>(kv.first), std::get<1>(kv.first),
+                                                     std::get<2>(kv.first), std::get<3>(kv.first)))
+                              .first;
+                const int waves = std::min(n, rit->second);
+                hipStream_t cs = comp[next_comp];
+                next_comp = (next_comp + 1) % kComputeStreams;
+                e = hipStreamWaitEvent(cs, stage_ev[next_stage], 0);
+                if (e == hipSuccess)
+                    e = gf::launch_serve(d_args,
+                                         reinterpret_cast<const gf::WorkItem *>(st.d + off_items[gi]),
+                                         n, reinterpret_cast<unsigned *>(st.d + off_cnt) + gi,
+                                         std::get<0>(kv.first), std::get<1>(kv.first),
+                                         std::get<2>(kv.first), std::get<3>(kv.first), waves, cs);
+                if (e == hipSuccess) e = hipEventRecord(group_ev[next_stage][gi], cs);
+                if (e == hipSuccess) b.ev.push_back(group_ev[next_stage][gi]);
                 ++gi;
             }
-            if (e == hipSuccess) e = hipEventRecord(stage_ev[next_stage], stream);
             if (e != hipSuccess) {
                 fail_worker(e, "serving launch");
                 break;
             }
-            b.ev = stage_ev[next_stage];
+            if (b.ev.empty()) b.ev.push_back(stage_ev[next_stage]);
             b.stage = next_stage;
             next_stage = (next_stage + 1) % kStages;
             {
@@ -496,11 +551,13 @@ void gf_server::run()
             inflight.push_back(std::move(b));
         }
 
-        // retire the oldest batch once two are in flight, or when there was
-        // nothing new to launch
-        if (inflight.size() >= 2 || (!inflight.empty() && !launch_now)) {
+        // retire the oldest batch once kMaxInflight are in flight, or when
+        // there was nothing new to launch
+        if ((int)inflight.size() >= kMaxInflight || (!inflight.empty() && !launch_now)) {
             Batch &o = inflight.front();
-            e = hipEventSynchronize(o.ev);
+            e = hipSuccess;
+            for (hipEvent_t ev : o.ev)
+                if (e == hipSuccess) e = hipEventSynchronize(ev);
             if (e != hipSuccess) {
                 fail_worker(e, "hipEventSynchronize");
                 break;
@@ -520,7 +577,7 @@ void gf_server::run()
     }
     // drain
     while (!inflight.empty()) {
-        (void)hipEventSynchronize(inflight.front().ev);
+        for (hipEvent_t ev : inflight.front().ev) (void)hipEventSynchronize(ev);
         inflight.pop_front();
     }
 }
@@ -549,6 +606,8 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out)
     s->cfg = *cfg;
     if (s->cfg.batch_evals == 0.0) s->cfg.batch_evals = 2e10;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    for (int k = 0; e == hipSuccess && k < kComputeStreams; ++k)
+        e = hipStreamCreateWithFlags(&s->comp[k], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->d_arena, cfg->device_budget_bytes);
     if (e == hipSuccess) e = hipMalloc(&s->d_args, sizeof(gf::ScanArgs) * cfg->max_inflight);
     if (e == hipSuccess)
@@ -558,12 +617,17 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out)
         e = hipHostMalloc(reinterpret_cast<void **>(&s->stage[k].h), kStageBytes, 0);
         if (e == hipSuccess) e = hipMalloc(&s->stage[k].d, kStageBytes);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev[k], hipEventDisableTiming);
+        for (int g = 0; e == hipSuccess && g < kMaxGroups; ++g)
+            e = hipEventCreateWithFlags(&s->group_ev[k][g], hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         int r = hip_fail(e, "gf_server_create");
         gf_server_destroy(s);
         return r;
     }
+    s->fill_items = 3LL * std::max(gf::serve_resident_waves(0, 1, 0, 0),
+                                   gf::serve_resident_waves(1, 1, 0, 0)) / 2;
+    s->fill_items = std::min<long long>(s->fill_items, kMaxItemsPerBatch);
     s->arena.init(cfg->device_budget_bytes);
     for (int k = cfg->max_inflight - 1; k >= 0; --k) s->free_slots.push_back(k);
     s->worker = std::thread([s] { s->run(); });
@@ -788,8 +852,12 @@ int gf_server_destroy(gf_server_t *s)
     (void)hipGetDevice(&cur);
     if (s->device >= 0 && cur != s->device) (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (int k = 0; k < kComputeStreams; ++k)
+        if (s->comp[k]) (void)hipStreamSynchronize(s->comp[k]);
     for (int k = 0; k < kStages; ++k) {
         if (s->stage_ev[k]) (void)hipEventDestroy(s->stage_ev[k]);
+        for (int g = 0; g < kMaxGroups; ++g)
+            if (s->group_ev[k][g]) (void)hipEventDestroy(s->group_ev[k][g]);
         if (s->stage[k].h) (void)hipHostFree(s->stage[k].h);
         if (s->stage[k].d) (void)hipFree(s->stage[k].d);
     }
@@ -797,6 +865,8 @@ int gf_server_destroy(gf_server_t *s)
     if (s->d_args) (void)hipFree(s->d_args);
     if (s->d_arena) (void)hipFree(s->d_arena);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (int k = 0; k < kComputeStreams; ++k)
+        if (s->comp[k]) (void)hipStreamDestroy(s->comp[k]);
     if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
     for (auto &kv : s->reqs) delete kv.second;
     delete s;
