@@ -43,9 +43,14 @@ def _small_trace(n, seed, sides=(16, 32, 48, 64, 96, 128), orders=(32, 64, 128))
 
 def test_served_results_equal_standalone_bitwise():
     """40 mixed requests (real and conjugate masses, FP64 and FP32C, several
-    grid sizes and orders) submitted together: each result is bitwise equal to
-    its own standalone scan."""
+    grid sizes and orders) and six 512^2 grids submitted together: each result
+    is bitwise equal to its own standalone scan.  The six large grids hold
+    24,576 tiles, more than a batch takes even when it tops up to fill the
+    device's wave slots (about 9,200 on this GPU), so their tiles are spread
+    over several batches."""
     reqs = _small_trace(40, seed=11)
+    big = serving_trace(6, 1e6, seed=12, sides=(512,), orders=(32,))
+    reqs = reqs[:20] + big + reqs[20:]
     assert {r.quad.precision for r in reqs} == {0, 1}
     assert any(complex(r.params.m1sq).imag != 0 for r in reqs)
     with gf.Server(budget_bytes=256 << 20, max_inflight=64, batch_evals=2e8) as srv:
@@ -56,7 +61,7 @@ def test_served_results_equal_standalone_bitwise():
         st = srv.stats()
         for t in tickets:
             srv.release(t)
-    assert st["completed"] == 40 and st["batches"] >= 2
+    assert st["completed"] == len(reqs) and st["batches"] >= 3
     for r, g in zip(reqs, results):
         ref = _standalone(r)
         same = np.array_equal(g.view(np.float64), ref.view(np.float64), equal_nan=True)
