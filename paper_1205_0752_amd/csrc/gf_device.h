@@ -385,18 +385,23 @@ __device__ __forceinline__ int scale_exponent(cd U2, cd V2)
 __device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
                                             cd V2in)
 {
+    // sum_j 2w_j / D_j = sum_j 2w_j conj(D_j) / |D_j|^2 with D_j = U^2 - V^2 z_j^2,
+    // and conj(D_j) = conj(U^2) - conj(V^2) z_j^2, so the pair sum is
+    // conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j / |D_j|^2 and
+    // T1 = sum 2w_j z_j^2 / |D_j|^2; the table holds (z_j^2, 2w_j, 2w_j z_j^2).
     const auto *tab = ro(table);
     const cd U2in = cmul(U, U);
     const int e = scale_exponent(U2in, V2in);
     const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
     const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
-    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, z0 = 0.0, z1 = 0.0;  // T0 and T1, two partial sums each
     int p = 0;
     for (; p + 4 <= npair; p += 4) {
-        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
-        const double zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
-        const double zz2 = tab[2 * p + 4], ww2 = tab[2 * p + 5];
-        const double zz3 = tab[2 * p + 6], ww3 = tab[2 * p + 7];
+        const auto *t = tab + 3 * p;
+        const double zz0 = t[0], ww0 = t[1], wz0 = t[2];
+        const double zz1 = t[3], ww1 = t[4], wz1 = t[5];
+        const double zz2 = t[6], ww2 = t[7], wz2 = t[8];
+        const double zz3 = t[9], ww3 = t[10], wz3 = t[11];
         const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
         const double dr1 = fma(-v2r, zz1, u2r), di1 = fma(-v2i, zz1, u2i);
         const double dr2 = fma(-v2r, zz2, u2r), di2 = fma(-v2i, zz2, u2i);
@@ -408,28 +413,27 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
         const double p01 = q0 * q1, p23 = q2 * q3;
         const double inv = rcp64(p01 * p23);
         const double i01 = p23 * inv, i23 = p01 * inv;
-        const double t0 = ww0 * (q1 * i01);
-        const double t1 = ww1 * (q0 * i01);
-        const double t2 = ww2 * (q3 * i23);
-        const double t3 = ww3 * (q2 * i23);
-        ar0 = fma(t0, dr0, ar0);
-        ai0 = fma(t0, di0, ai0);
-        ar1 = fma(t1, dr1, ar1);
-        ai1 = fma(t1, di1, ai1);
-        ar0 = fma(t2, dr2, ar0);
-        ai0 = fma(t2, di2, ai0);
-        ar1 = fma(t3, dr3, ar1);
-        ai1 = fma(t3, di3, ai1);
+        const double r0 = q1 * i01, r1 = q0 * i01, r2 = q3 * i23, r3 = q2 * i23;  // 1 / q_k
+        s0 = fma(ww0, r0, s0);
+        z0 = fma(wz0, r0, z0);
+        s1 = fma(ww1, r1, s1);
+        z1 = fma(wz1, r1, z1);
+        s0 = fma(ww2, r2, s0);
+        z0 = fma(wz2, r2, z0);
+        s1 = fma(ww3, r3, s1);
+        z1 = fma(wz3, r3, z1);
     }
     for (; p < npair; ++p) {
-        const double zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        const double zz0 = tab[3 * p], ww0 = tab[3 * p + 1], wz0 = tab[3 * p + 2];
         const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
-        const double t0 = ww0 * rcp64(fma(dr0, dr0, di0 * di0));
-        ar0 = fma(t0, dr0, ar0);
-        ai0 = fma(t0, di0, ai0);
+        const double r0 = rcp64(fma(dr0, dr0, di0 * di0));
+        s0 = fma(ww0, r0, s0);
+        z0 = fma(wz0, r0, z0);
     }
-    // sum 2w / D = sum 2w conj(D) / |D|^2 (scaled by 2^e), then times U
-    cd A = cmul(U, mk(ldexp(ar0 + ar1, -e), -ldexp(ai0 + ai1, -e)));
+    const double T0 = s0 + s1, T1 = z0 + z1;
+    // the pair sum (scaled by 2^e): conj(U^2) T0 - conj(V^2) T1, then times U
+    const double sr = fma(u2r, T0, -(v2r * T1)), si = fma(u2i, T0, -(v2i * T1));
+    cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
     return A;
 }
@@ -447,9 +451,12 @@ __device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
 // FP32 angular sum with compensated accumulation.  U^2 and V^2 are formed in
 // FP64 and scaled by an exact power of two 2^-e (e = exponent of their largest
 // component) before rounding to FP32, so every FP32 denominator is O(1) and the
-// shared-reciprocal product q0 q1 stays in range.  Terms are summed in FP32
-// blocks of kBlock pairs; block sums enter a (hi, lo) two-sum accumulator; the
-// node's sum leaves in FP64 as U 2^-e (hi + lo).
+// shared-reciprocal product q0 q1 stays in range.  As in the FP64 sum, the
+// pair sum is conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j/|D_j|^2
+// and T1 = sum 2w_j z_j^2/|D_j|^2 (positive terms); each is summed in FP32
+// blocks of kBlock pairs whose block sums enter a (hi, lo) two-sum accumulator,
+// and the combination with the FP32 values of U^2 and V^2 (exact in FP64) is
+// taken in FP64.  The table holds (z_j^2, 2w_j, 2w_j z_j^2) in FP32.
 constexpr int kBlock = 16;
 
 __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
@@ -460,40 +467,53 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
     const int e = scale_exponent(U2, V2);
     const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
     const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
-    float hr = 0.0f, lr = 0.0f, hi = 0.0f, li = 0.0f;
+    float h0 = 0.0f, l0 = 0.0f, h1 = 0.0f, l1 = 0.0f;  // T0 and T1 as (hi, lo)
     int p = 0;
     while (p < npair) {
         const int pe = min(p + kBlock, npair);
-        float br0 = 0.0f, bi0 = 0.0f, br1 = 0.0f, bi1 = 0.0f;
-        for (; p + 2 <= pe; p += 2) {
-            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
-            const float zz1 = tab[2 * p + 2], ww1 = tab[2 * p + 3];
+        float b0 = 0.0f, c0 = 0.0f, b1 = 0.0f, c1 = 0.0f;
+        const auto *t = tab + 3 * p;
+        // four pairs per step, two shared reciprocals (of q0 q1 and q2 q3)
+        for (; p + 4 <= pe; p += 4, t += 12) {
+            const float zz0 = t[0], ww0 = t[1], wz0 = t[2];
+            const float zz1 = t[3], ww1 = t[4], wz1 = t[5];
+            const float zz2 = t[6], ww2 = t[7], wz2 = t[8];
+            const float zz3 = t[9], ww3 = t[10], wz3 = t[11];
             const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
             const float dr1 = fmaf(-v2r, zz1, u2r), di1 = fmaf(-v2i, zz1, u2i);
+            const float dr2 = fmaf(-v2r, zz2, u2r), di2 = fmaf(-v2i, zz2, u2i);
+            const float dr3 = fmaf(-v2r, zz3, u2r), di3 = fmaf(-v2i, zz3, u2i);
             const float q0 = fmaf(dr0, dr0, di0 * di0);
             const float q1 = fmaf(dr1, dr1, di1 * di1);
-            const float inv = __builtin_amdgcn_rcpf(q0 * q1);
-            const float t0 = ww0 * (q1 * inv);
-            const float t1 = ww1 * (q0 * inv);
-            br0 = fmaf(t0, dr0, br0);
-            bi0 = fmaf(t0, di0, bi0);
-            br1 = fmaf(t1, dr1, br1);
-            bi1 = fmaf(t1, di1, bi1);
+            const float q2 = fmaf(dr2, dr2, di2 * di2);
+            const float q3 = fmaf(dr3, dr3, di3 * di3);
+            const float inv01 = __builtin_amdgcn_rcpf(q0 * q1);
+            const float inv23 = __builtin_amdgcn_rcpf(q2 * q3);
+            const float r0 = q1 * inv01, r1 = q0 * inv01;  // 1 / q_k
+            const float r2 = q3 * inv23, r3 = q2 * inv23;
+            b0 = fmaf(ww0, r0, b0);
+            c0 = fmaf(wz0, r0, c0);
+            b1 = fmaf(ww1, r1, b1);
+            c1 = fmaf(wz1, r1, c1);
+            b0 = fmaf(ww2, r2, b0);
+            c0 = fmaf(wz2, r2, c0);
+            b1 = fmaf(ww3, r3, b1);
+            c1 = fmaf(wz3, r3, c1);
         }
-        if (p < pe) {
-            const float zz0 = tab[2 * p], ww0 = tab[2 * p + 1];
+        for (; p < pe; ++p, t += 3) {
+            const float zz0 = t[0], ww0 = t[1], wz0 = t[2];
             const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
-            const float t0 = ww0 * __builtin_amdgcn_rcpf(fmaf(dr0, dr0, di0 * di0));
-            br0 = fmaf(t0, dr0, br0);
-            bi0 = fmaf(t0, di0, bi0);
-            ++p;
+            const float r0 = __builtin_amdgcn_rcpf(fmaf(dr0, dr0, di0 * di0));
+            b0 = fmaf(ww0, r0, b0);
+            c0 = fmaf(wz0, r0, c0);
         }
-        two_sum(hr, lr, br0 + br1);
-        two_sum(hi, li, bi0 + bi1);
+        two_sum(h0, l0, b0 + b1);
+        two_sum(h1, l1, c0 + c1);
     }
-    const double sr = ldexp((double)hr + (double)lr, -e);
-    const double si = ldexp((double)hi + (double)li, -e);
-    cd A = cmul(U, mk(sr, -si));
+    const double T0 = (double)h0 + (double)l0, T1 = (double)h1 + (double)l1;
+    const double sr = fma((double)u2r, T0, -((double)v2r * T1));
+    const double si = fma((double)u2i, T0, -((double)v2i * T1));
+    cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
     return A;
 }

@@ -153,20 +153,24 @@ void radial_table(int nr, double lambda2, int dim, int split, std::vector<double
 void angular_tables(int na, int rule, int dim, std::vector<double> &ang,
                     std::vector<float> &ang32, double *wmid)
 {
-    // Stored folded over the symmetric pairs (z_j, -z_j) as (z_j^2, 2 w_j), j
-    // running over the positive nodes; an odd rule's middle node z = 0 keeps
-    // its weight apart.  Weights follow the normalised D-dimensional angular
+    // Stored folded over the symmetric pairs (z_j, -z_j), j running over the
+    // positive nodes as (z_j^2, 2 w_j, 2 w_j z_j^2), in FP64 and rounded to FP32;
+    // an odd rule's middle node z = 0 keeps its weight apart.  Weights follow the normalised D-dimensional angular
     // measure (1 - z^2)^{(D-3)/2} dz / N_D, N_D = pi (D = 2), 2 (D = 3),
     // pi/2 (D = 4).  Each rule integrates g(z) against its own weight function
     // omega(z) and is applied to g = f (1 - z^2)^{(D-3)/2} / omega.
     const int npair = na / 2;
-    ang.assign(2 * (size_t)std::max(npair, 1), 0.0);
-    ang32.assign(2 * (size_t)std::max(npair, 1), 0.0f);
+    ang.assign(3 * (size_t)std::max(npair, 1), 0.0);
+    ang32.assign(3 * (size_t)std::max(npair, 1), 0.0f);
     *wmid = 0.0;
     const double norm = dim == 2 ? M_PI : (dim == 3 ? 2.0 : M_PI_2);
     auto put = [&](int j, double zsq, double w) {
-        ang[2 * j] = zsq;
-        ang[2 * j + 1] = 2.0 * w;
+        ang[3 * j] = zsq;
+        ang[3 * j + 1] = 2.0 * w;
+        ang[3 * j + 2] = 2.0 * w * zsq;
+        ang32[3 * j] = (float)zsq;
+        ang32[3 * j + 1] = (float)(2.0 * w);
+        ang32[3 * j + 2] = (float)(2.0 * w * zsq);
     };
     // s^{D-2} for s = sin(theta) = sqrt(1 - z^2)
     auto sinpow = [&](double s) { return dim == 4 ? s * s : (dim == 3 ? s : 1.0); };
@@ -212,7 +216,6 @@ void angular_tables(int na, int rule, int dim, std::vector<double> &ang,
         }
         if (na % 2 == 1) *wmid = h * M_PI_2 / norm;
     }
-    for (size_t i = 0; i < ang.size(); ++i) ang32[i] = (float)ang[i];
 }
 
 void arc_table(int nc, std::vector<double> &arc)

@@ -26,7 +26,7 @@ struct ScanArgs {
     // Device tables:
     //   rad: r[n_r], sqrt_r[n_r], g[n_r]   (y nodes of GL in log(1+y), dy r^{(D-2)/2}
     //                                       weights), FP64
-    //   ang: (z^2, 2w) for the n_a/2 symmetric pairs of the GC-II rule, FP64
+    //   ang: (z^2, 2w, 2w z^2) for the n_a/2 symmetric pairs of the angular rule, FP64
     //   arc: xi[n_arc], w[n_arc]           (GL on [-1, 1]), FP64
     //   ang32: the pair table rounded to FP32
     const double *rad;

@@ -161,7 +161,7 @@ __device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd 
 {
     const double *tab = a.ang;
     for (int j = 0; j < a.n_a / 2; ++j) {
-        const double z2 = ro(tab)[2 * j], w2 = ro(tab)[2 * j + 1];
+        const double z2 = ro(tab)[3 * j], w2 = ro(tab)[3 * j + 1];
         const cd D0 = mk(U0.r * U0.r - U0.i * U0.i - 4.0 * a.mu2 * y * z2, 2.0 * U0.r * U0.i);
         const cd D1 = mk(2.0 * U0.r - 4.0 * y * z2, 2.0 * U0.i);
         const cd rD = cdiv(mk(1.0, 0.0), D0);
