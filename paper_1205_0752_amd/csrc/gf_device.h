@@ -389,6 +389,9 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     // and conj(D_j) = conj(U^2) - conj(V^2) z_j^2, so the pair sum is
     // conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j / |D_j|^2 and
     // T1 = sum 2w_j z_j^2 / |D_j|^2; the table holds (z_j^2, 2w_j, 2w_j z_j^2).
+    // Eight (then four) denominators share one reciprocal of their product,
+    // refined by one Newton step; each 1/q_k is unfolded by multiplying out the
+    // others (the scaling keeps every q_k, and so the product, in range).
     const auto *tab = ro(table);
     const cd U2in = cmul(U, U);
     const int e = scale_exponent(U2in, V2in);
@@ -396,6 +399,29 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
     double s0 = 0.0, s1 = 0.0, z0 = 0.0, z1 = 0.0;  // T0 and T1, two partial sums each
     int p = 0;
+    for (; p + 8 <= npair; p += 8) {
+        const auto *t = tab + 3 * p;
+        double q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double dr = fma(-v2r, t[3 * k], u2r), di = fma(-v2i, t[3 * k], u2i);
+            q[k] = fma(dr, dr, di * di);
+        }
+        const double p01 = q[0] * q[1], p23 = q[2] * q[3], p45 = q[4] * q[5], p67 = q[6] * q[7];
+        const double p03 = p01 * p23, p47 = p45 * p67;
+        const double inv = rcp64(p03 * p47);
+        const double i03 = p47 * inv, i47 = p03 * inv;
+        const double i01 = p23 * i03, i23 = p01 * i03, i45 = p67 * i47, i67 = p45 * i47;
+        const double r[8] = {q[1] * i01, q[0] * i01, q[3] * i23, q[2] * i23,
+                             q[5] * i45, q[4] * i45, q[7] * i67, q[6] * i67};
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            s0 = fma(t[3 * k + 1], r[k], s0);
+            z0 = fma(t[3 * k + 2], r[k], z0);
+            s1 = fma(t[3 * k + 4], r[k + 1], s1);
+            z1 = fma(t[3 * k + 5], r[k + 1], z1);
+        }
+    }
     for (; p + 4 <= npair; p += 4) {
         const auto *t = tab + 3 * p;
         const double zz0 = t[0], ww0 = t[1], wz0 = t[2];
