@@ -57,8 +57,9 @@ extern "C" {
 
 /* ---- precision of the angular (hot) sum -------------------------------- */
 #define GF_PREC_FP64 0   /* everything in FP64 */
-#define GF_PREC_FP32C 1  /* angular sum in FP32 with compensated (two-sum)
-                            accumulation; sqrt(x), contour choice, per-node
+#define GF_PREC_FP32C 1  /* angular sum in FP32, its blocks of 16 pairs
+                            accumulated in FP64; nodes near the angular cut
+                            in FP64; sqrt(x), contour choice, per-node
                             coefficients, radial sum, mu^2 subtraction and
                             scaling in FP64 */
 

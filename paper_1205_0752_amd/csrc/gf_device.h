@@ -298,25 +298,33 @@ __device__ __forceinline__ cd prop2(const Args &a, cd y)
     return p;
 }
 
-template <bool SPLIT = false, bool POLES = false, class Args>
-__device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
-                                            cd &V2, cd &w)
+// Node k < n_r: the straight part (real axis or ray).
+template <bool SPLIT, bool POLES, class Args>
+__device__ __forceinline__ void radial_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
+                                              cd &V2, cd &w)
 {
-    const cd m2 = mk(a.m2_re, a.m2_im);
     // 4 x, recovered from x + m1^2 (recomputing it per node keeps fewer
     // registers live across the node loop than carrying it)
     const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
-    if (k < a.n_r) {
-        double r, g;
-        radial_node<SPLIT>(a, P, k, r, g);
-        const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
-        U = cadd(P.x1, y);
-        V2 = cmul(x4, y);                                      // 4 x y
-        if (POLES)
-            w = cmul(cscale(P.dirD, g), prop2(a, y));
-        else
-            w = cdiv(cscale(P.dirD, g), cadd(y, m2));
-    } else if (k < a.n_r + a.n_arc) {
+    double r, g;
+    radial_node<SPLIT>(a, P, k, r, g);
+    const cd y = cscale(P.dir, r);                         // y = e^{i phi} r
+    U = cadd(P.x1, y);
+    V2 = cmul(x4, y);                                      // 4 x y
+    if (POLES)
+        w = cmul(cscale(P.dirD, g), prop2(a, y));
+    else
+        w = cdiv(cscale(P.dirD, g), cadd(y, mk(a.m2_re, a.m2_im)));
+}
+
+// Node k >= n_r: the arc |y| = Lambda^2, then the residue nodes.
+template <bool POLES, class Args>
+__device__ __forceinline__ void outer_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
+                                             cd &V2, cd &w)
+{
+    const cd m2 = mk(a.m2_re, a.m2_im);
+    const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
+    if (k < a.n_r + a.n_arc) {
         const int q = k - a.n_r;
         const auto *arc = ro(a.arc);
         const double xi = arc[q];
@@ -365,15 +373,24 @@ __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, in
     }
 }
 
+template <bool SPLIT = false, bool POLES = false, class Args>
+__device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
+                                            cd &V2, cd &w)
+{
+    if (k < a.n_r)
+        radial_coeffs<SPLIT, POLES>(a, P, k, U, V2, w);
+    else
+        outer_coeffs<POLES>(a, P, k, U, V2, w);
+}
+
 // Angular sum A = sum_j w_j / (U - V z_j) over the GC-II rule.  The rule is
 // symmetric (z_{n+1-j} = -z_j, equal weights), so each node pair is folded:
 //   w/(U - V z) + w/(U + V z) = 2 w U / (U^2 - V^2 z^2),
 // one complex denominator per two integrand evaluations; the middle node of an
 // odd rule (z = 0) adds w/U.  U^2 and V^2 are scaled by an exact power of two
 // 2^-e (e = exponent of their largest component), which changes no rounding
-// and keeps every |D|^2 near 1, so four denominators can share one reciprocal
-// (1/q0 = q1 q2 q3 / (q0 q1 q2 q3)) without overflow.  Table: (z^2, 2w) per
-// pair, FP64.
+// and keeps every |D|^2 of order 1 or below, so several denominators can share
+// one reciprocal (1/q0 = q1 q2 ... / (q0 q1 q2 ...)) without overflow.
 __device__ __forceinline__ int scale_exponent(cd U2, cd V2)
 {
     const double big = fmax(fmax(fabs(U2.r), fabs(U2.i)), fmax(fabs(V2.r), fabs(V2.i)));
@@ -464,24 +481,16 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     return A;
 }
 
-// Knuth's two-sum: s + e == a + b exactly (round-to-nearest, no contraction).
-__device__ __forceinline__ void two_sum(float &hi, float &lo, float b)
-{
-    const float s = hi + b;
-    const float bb = s - hi;
-    const float e = (hi - (s - bb)) + (b - bb);
-    hi = s;
-    lo += e;
-}
-
-// FP32 angular sum with compensated accumulation.  U^2 and V^2 are formed in
+// FP32 angular sum with blocked accumulation.  U^2 and V^2 are formed in
 // FP64 and scaled by an exact power of two 2^-e (e = exponent of their largest
 // component) before rounding to FP32, so every FP32 denominator is O(1) and the
 // shared-reciprocal product q0 q1 stays in range.  As in the FP64 sum, the
 // pair sum is conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j/|D_j|^2
 // and T1 = sum 2w_j z_j^2/|D_j|^2 (positive terms); each is summed in FP32
-// blocks of kBlock pairs whose block sums enter a (hi, lo) two-sum accumulator,
-// and the combination with the FP32 values of U^2 and V^2 (exact in FP64) is
+// blocks of kBlock pairs whose block sums are added in FP64 (for sums of
+// positive terms this bounds the error by the block's, like a two-sum
+// accumulator of the block sums, at two instructions per block and sum), and
+// the combination with the FP32 values of U^2 and V^2 (exact in FP64) is
 // taken in FP64.  The table holds (z_j^2, 2w_j, 2w_j z_j^2) in FP32.
 constexpr int kBlock = 16;
 
@@ -493,7 +502,7 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
     const int e = scale_exponent(U2, V2);
     const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
     const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
-    float h0 = 0.0f, l0 = 0.0f, h1 = 0.0f, l1 = 0.0f;  // T0 and T1 as (hi, lo)
+    double T0 = 0.0, T1 = 0.0;  // FP32 block sums added in FP64
     int p = 0;
     while (p < npair) {
         const int pe = min(p + kBlock, npair);
@@ -533,10 +542,9 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
             b0 = fmaf(ww0, r0, b0);
             c0 = fmaf(wz0, r0, c0);
         }
-        two_sum(h0, l0, b0 + b1);
-        two_sum(h1, l1, c0 + c1);
+        T0 += (double)(b0 + b1);
+        T1 += (double)(c0 + c1);
     }
-    const double T0 = (double)h0 + (double)l0, T1 = (double)h1 + (double)l1;
     const double sr = fma((double)u2r, T0, -((double)v2r * T1));
     const double si = fma((double)u2i, T0, -((double)v2i * T1));
     cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));

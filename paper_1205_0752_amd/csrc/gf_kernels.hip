@@ -51,10 +51,23 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
     }
     const PointCtx pc = point_setup<SPLIT, POLES>(a, xr, xi, ecls, sign, mask);
 
+    // The straight part's nodes, then the arc and residue nodes, in one
+    // sequence k = s, s + L, ... per lane: two loops so that the arc's sine
+    // and cosine constants are live only in the second.
     double sr = 0.0, si = 0.0;
-    for (int k = s; k < pc.nodes; k += L) {
+    int k = s;
+    const int n_straight = min(pc.nodes, a.n_r);
+    for (; k < n_straight; k += L) {
         cd U, V2, w;
-        node_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
+        radial_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
+        cd A = angular_sum_p<PREC, POLES>(a, U, V2);
+        cd t = cmul(w, A);
+        sr += t.r;
+        si += t.i;
+    }
+    for (; k < pc.nodes; k += L) {
+        cd U, V2, w;
+        outer_coeffs<POLES>(a, pc, k, U, V2, w);
         cd A = angular_sum_p<PREC, POLES>(a, U, V2);
         cd t = cmul(w, A);
         sr += t.r;
@@ -94,10 +107,11 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
     }
 }
 
-// Register budgets: the FP64 kernel runs best at 5 waves per SIMD, the FP32C
-// kernel at 6 (measured; the few spills this costs sit outside the inner loop).
+// Register budgets: the FP64 kernel runs best at 4 waves per SIMD (109 VGPRs,
+// nothing spilled; 5 waves spill and are 2 % slower), the FP32C kernel at 6
+// (measured; its few spills sit outside the inner loop).
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -134,7 +148,7 @@ __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem 
 }
 
 template <int L, bool SPLIT, bool POLES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 serve_kernel_fp64(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict__ items,
                   int n_items, unsigned *counter)
 {
