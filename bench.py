@@ -299,7 +299,7 @@ def main() -> int:
     ap.add_argument("--skip-extensions", action="store_true",
                     help="skip the y-plane scan, obstruction map and tanh-sinh measurements")
     ap.add_argument("--serve-requests", type=int, default=6000)
-    ap.add_argument("--serve-rate", type=float, default=880.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-rate", type=float, default=1180.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-budget", type=int, default=1 << 30, help="device bytes")
     ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
