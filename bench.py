@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -109,9 +110,10 @@ def scan_kernel_name(params, quad, lanes, props=None):
 
 
 def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None):
-    """Times `steps` scans with HIP events on the launch stream; the plan and the
-    output buffer are resident before timing starts.  Evaluations count one
-    angular term per (p-k)-leg pole."""
+    """Times `steps` scans with HIP events on the launch stream (one event
+    between consecutive scans, so each scan's duration is known as well as the
+    mean); the plan and the output buffer are resident before timing starts.
+    Evaluations count one angular term per (p-k)-leg pole."""
     plan = gf.Plan(params, quad, props=props)
     out = gf.empty_result(grid)
     cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
@@ -123,21 +125,24 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None):
     for _ in range(warmup):
         gf.scan_plan(plan, grid, out, lanes=lanes, stream=stream)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for i in range(steps):
         gf.scan_plan(plan, grid, out, lanes=lanes, stream=stream)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / steps
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    per_scan = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     plan.close()
     sec = ms / 1e3
     return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
             "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
             "wall": wall, "lanes": used_lanes,
+            "latency_ms": {"p50": per_scan[(steps - 1) // 2],
+                           "p99": per_scan[min(steps - 1, math.ceil(0.99 * steps) - 1)],
+                           "max": per_scan[-1]},
             "kernel": scan_kernel_name(params, quad, used_lanes, props)}
 
 
@@ -350,6 +355,7 @@ def main() -> int:
                    "grid_points": grid.n_points, "evals_per_step": t["evals"],
                    "lanes_per_point": t["lanes"], "parallelism": "single GPU"},
         "points_per_s": t["points_per_s"],
+        "scan_latency_ms": t["latency_ms"],
         "wall_s_timed": t["wall"],
         "roofline": {"bound": "alu", "achieved": t["tflops"],
                      "peak": FP64_PEAK_TFLOPS if quad.precision == 0 else FP32_PEAK_TFLOPS,
@@ -366,7 +372,8 @@ def main() -> int:
         result["fp32c"] = {"workload": f"c2_fp32c_1024sq: {g2.n_re}x{g2.n_im} grid, "
                                        f"{q2.n_radial}x{q2.n_angular}(+{q2.n_arc} arc) nodes",
                            "evals_per_s": t2["evals_per_s"], "points_per_s": t2["points_per_s"],
-                           "ms_per_step": t2["ms"], "tflops": t2["tflops"],
+                           "ms_per_step": t2["ms"], "scan_latency_ms": t2["latency_ms"],
+                           "tflops": t2["tflops"],
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
                            "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS,
                            "error_vs_fp64": fp32c_errors(gf, torch, p2, g2, q2)}
