@@ -109,21 +109,25 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
 // Register budgets: the FP64 kernel runs best at 4 waves per SIMD (109 VGPRs,
 // nothing spilled; 5 waves spill and are 2 % slower), the FP32C kernel at 6
-// (measured; its few spills sit outside the inner loop).
+// (measured; its few spills sit outside the inner loop).  One wave (one tile)
+// per workgroup: a tile's cost depends on its points' classes (a tile of
+// points without a contour ends at once), and a one-wave workgroup frees its
+// slot for the next tile by itself, where a four-wave workgroup would hold
+// the slots of its finished waves until the last one ends.
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 scan_kernel_fp64(ScanArgs a)
 {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
     process_tile<0, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
 }
 
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6)))
 scan_kernel_fp32c(ScanArgs a)
 {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
     process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
 }
@@ -294,9 +298,9 @@ __global__ void __launch_bounds__(64) jmu_batch_kernel(ScanArgs *__restrict__ re
 template <int L>
 hipError_t launch_l(const ScanArgs &a, int precision, hipStream_t s)
 {
-    const int blocks = (a.n_tiles + 3) / 4;
+    const int blocks = a.n_tiles;
     const bool taylor = a.n_taylor > 0, split = a.split != 0;
-    const dim3 g(blocks), b(256);
+    const dim3 g(blocks), b(64);
     // pole sums run one kernel form (t^n epilogue compiled in; the split rule
     // needs single poles); single poles pick the form without unused parts
     if (precision == 0) {
