@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -93,9 +94,38 @@ def cpu_baseline(params, quad, grid, seconds: float):
             break
         n = int(min(grid.n_points, len(idx) * seconds / max(dt, 1e-3)))
     ev = evals_per_scan(c, quad)
-    return {"value": ev / dt, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{len(idx)} random points of the same grid ({ev:.3e} evals, {dt:.1f} s)",
-            "points_per_s": len(idx) / dt}
+    out = {"value": ev / dt, "unit": "evals/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{len(idx)} random points of the same grid ({ev:.3e} evals, {dt:.1f} s)",
+           "points_per_s": len(idx) / dt}
+    # the same oracle on one core: a child process with OMP_NUM_THREADS=1 (it
+    # loads only the oracle and numpy), on a sample sized for about 3 s
+    m = max(64, int(len(idx) * 3.0 / max(dt * oracle.threads(), 1e-3)))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(m)],
+                           env=env, capture_output=True, text=True, timeout=120)
+        out["single_core"] = json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["single_core"] = {"error": str(e)}
+    return out
+
+
+def cpu_worker(n_points: int) -> int:
+    """Child of cpu_baseline: times the oracle on `n_points` random points of the
+    bench grid and prints one JSON object (never touches the GPU)."""
+    import oracle
+    from paper_1205_0752_amd.workloads import CONFIGS, sample_points
+    params, grid, quad = CONFIGS["c1_fp64_1024sq"]
+    oracle.build()
+    idx = sample_points(grid, min(n_points, grid.n_points), seed=11)
+    x = oracle.grid_points_at(grid, idx)
+    t = time.perf_counter()
+    _, c = oracle.eval_points(params, quad, x)
+    dt = time.perf_counter() - t
+    ev = evals_per_scan(c, quad)
+    print(json.dumps({"value": ev / dt, "unit": "evals/s", "cores": oracle.threads(),
+                      "sample": f"{len(idx)} random points ({ev:.3e} evals, {dt:.2f} s)"}))
+    return 0
 
 
 def scan_kernel_name(params, quad, lanes, props=None):
@@ -309,7 +339,11 @@ def main() -> int:
     ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM traffic counters) and exit")
+    ap.add_argument("--cpu-worker", type=int, default=0, metavar="POINTS",
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        return cpu_worker(args.cpu_worker)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the scan "
               "shards by grid tiles with no communication, but only one GPU is used here)",
