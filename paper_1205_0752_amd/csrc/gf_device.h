@@ -399,31 +399,52 @@ __device__ __forceinline__ int scale_exponent(cd U2, cd V2)
     return e;
 }
 
-__device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
-                                            cd V2in)
+// Near the angular cut: the folded denominators U^2 - V^2 s, s = z^2 in (0, 1),
+// come within dist(U^2, [0, V^2]) of zero; a node is "near" when
+// (|U^2| + |V^2|) > kCutSensitivity dist (tested in squares).  The test depends
+// on the node alone, so results stay reproducible.
+constexpr double kCutSensitivity = 16.0;
+
+__device__ __forceinline__ bool near_cut_sq(double ar, double ai, double br, double bi)
 {
-    // sum_j 2w_j / D_j = sum_j 2w_j conj(D_j) / |D_j|^2 with D_j = U^2 - V^2 z_j^2,
-    // and conj(D_j) = conj(U^2) - conj(V^2) z_j^2, so the pair sum is
-    // conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j / |D_j|^2 and
-    // T1 = sum 2w_j z_j^2 / |D_j|^2; the table holds (z_j^2, 2w_j, 2w_j z_j^2).
-    // Eight (then four) denominators share one reciprocal of their product,
-    // refined by one Newton step; each 1/q_k is unfolded by multiplying out the
-    // others (the scaling keeps every q_k, and so the product, in range).
+    const double vv = br * br + bi * bi;
+    const double uu = ar * ar + ai * ai;
+    if (vv == 0.0) return false;  // sum is exactly 1/U
+    // closest point of the segment s V^2, s in [0, 1], to U^2
+    double s = (ar * br + ai * bi) / vv;
+    s = fmin(fmax(s, 0.0), 1.0);
+    const double dr = ar - s * br, di = ai - s * bi;
+    return 2.0 * (uu + vv) > kCutSensitivity * kCutSensitivity * (dr * dr + di * di);
+}
+
+// Sums T0 = sum 2w_j / q_j and T1 = sum 2w_j z_j^2 / q_j of the folded pairs,
+// q_j = |U^2 - V^2 s_j|^2 (s_j = z_j^2), on the scaled U^2 = (ur, ui), V^2 = (vr, vi).
+// QUAD: q_j from the real quadratic c0 - c1 s + c2 s^2 (c0 = |U^2|^2,
+// c1 = 2 Re(U^2 conj V^2), c2 = |V^2|^2), two FMAs; its rounding, relative
+// ~eps (|U^2| + |V^2| s)^2 / q_j, is taken only away from the cut (below
+// kCutSensitivity^2 eps).  Otherwise q_j = |D_j|^2 from D_j itself.  Eight (then
+// four) denominators share one reciprocal of their product, refined by one
+// Newton step; each 1/q_k is unfolded by multiplying out the others (the
+// scaling keeps every q_k, and so the product, in range).
+template <bool QUAD>
+__device__ __forceinline__ void pair_sums64(const double *table, int npair, double ur, double ui,
+                                            double vr, double vi, double &T0, double &T1)
+{
     const auto *tab = ro(table);
-    const cd U2in = cmul(U, U);
-    const int e = scale_exponent(U2in, V2in);
-    const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
-    const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
+    const double c0 = fma(ur, ur, ui * ui), c2 = fma(vr, vr, vi * vi);
+    const double c1 = -2.0 * fma(ur, vr, ui * vi);
+    auto qof = [&](double s) {
+        if (QUAD) return fma(fma(c2, s, c1), s, c0);
+        const double dr = fma(-vr, s, ur), di = fma(-vi, s, ui);
+        return fma(dr, dr, di * di);
+    };
     double s0 = 0.0, s1 = 0.0, z0 = 0.0, z1 = 0.0;  // T0 and T1, two partial sums each
     int p = 0;
     for (; p + 8 <= npair; p += 8) {
         const auto *t = tab + 3 * p;
         double q[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double dr = fma(-v2r, t[3 * k], u2r), di = fma(-v2i, t[3 * k], u2i);
-            q[k] = fma(dr, dr, di * di);
-        }
+        for (int k = 0; k < 8; ++k) q[k] = qof(t[3 * k]);
         const double p01 = q[0] * q[1], p23 = q[2] * q[3], p45 = q[4] * q[5], p67 = q[6] * q[7];
         const double p03 = p01 * p23, p47 = p45 * p67;
         const double inv = rcp64(p03 * p47);
@@ -441,39 +462,46 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     }
     for (; p + 4 <= npair; p += 4) {
         const auto *t = tab + 3 * p;
-        const double zz0 = t[0], ww0 = t[1], wz0 = t[2];
-        const double zz1 = t[3], ww1 = t[4], wz1 = t[5];
-        const double zz2 = t[6], ww2 = t[7], wz2 = t[8];
-        const double zz3 = t[9], ww3 = t[10], wz3 = t[11];
-        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
-        const double dr1 = fma(-v2r, zz1, u2r), di1 = fma(-v2i, zz1, u2i);
-        const double dr2 = fma(-v2r, zz2, u2r), di2 = fma(-v2i, zz2, u2i);
-        const double dr3 = fma(-v2r, zz3, u2r), di3 = fma(-v2i, zz3, u2i);
-        const double q0 = fma(dr0, dr0, di0 * di0);
-        const double q1 = fma(dr1, dr1, di1 * di1);
-        const double q2 = fma(dr2, dr2, di2 * di2);
-        const double q3 = fma(dr3, dr3, di3 * di3);
+        const double q0 = qof(t[0]), q1 = qof(t[3]), q2 = qof(t[6]), q3 = qof(t[9]);
         const double p01 = q0 * q1, p23 = q2 * q3;
         const double inv = rcp64(p01 * p23);
         const double i01 = p23 * inv, i23 = p01 * inv;
         const double r0 = q1 * i01, r1 = q0 * i01, r2 = q3 * i23, r3 = q2 * i23;  // 1 / q_k
-        s0 = fma(ww0, r0, s0);
-        z0 = fma(wz0, r0, z0);
-        s1 = fma(ww1, r1, s1);
-        z1 = fma(wz1, r1, z1);
-        s0 = fma(ww2, r2, s0);
-        z0 = fma(wz2, r2, z0);
-        s1 = fma(ww3, r3, s1);
-        z1 = fma(wz3, r3, z1);
+        s0 = fma(t[1], r0, s0);
+        z0 = fma(t[2], r0, z0);
+        s1 = fma(t[4], r1, s1);
+        z1 = fma(t[5], r1, z1);
+        s0 = fma(t[7], r2, s0);
+        z0 = fma(t[8], r2, z0);
+        s1 = fma(t[10], r3, s1);
+        z1 = fma(t[11], r3, z1);
     }
     for (; p < npair; ++p) {
-        const double zz0 = tab[3 * p], ww0 = tab[3 * p + 1], wz0 = tab[3 * p + 2];
-        const double dr0 = fma(-v2r, zz0, u2r), di0 = fma(-v2i, zz0, u2i);
-        const double r0 = rcp64(fma(dr0, dr0, di0 * di0));
-        s0 = fma(ww0, r0, s0);
-        z0 = fma(wz0, r0, z0);
+        const auto *t = tab + 3 * p;
+        const double r0 = rcp64(qof(t[0]));
+        s0 = fma(t[1], r0, s0);
+        z0 = fma(t[2], r0, z0);
     }
-    const double T0 = s0 + s1, T1 = z0 + z1;
+    T0 = s0 + s1;
+    T1 = z0 + z1;
+}
+
+__device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
+                                            cd V2in)
+{
+    // sum_j 2w_j / D_j = sum_j 2w_j conj(D_j) / |D_j|^2 with D_j = U^2 - V^2 z_j^2,
+    // and conj(D_j) = conj(U^2) - conj(V^2) z_j^2, so the pair sum is
+    // conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j / |D_j|^2 and
+    // T1 = sum 2w_j z_j^2 / |D_j|^2; the table holds (z_j^2, 2w_j, 2w_j z_j^2).
+    const cd U2in = cmul(U, U);
+    const int e = scale_exponent(U2in, V2in);
+    const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
+    const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
+    double T0, T1;
+    if (near_cut_sq(u2r, u2i, v2r, v2i))
+        pair_sums64<false>(table, npair, u2r, u2i, v2r, v2i, T0, T1);
+    else
+        pair_sums64<true>(table, npair, u2r, u2i, v2r, v2i, T0, T1);
     // the pair sum (scaled by 2^e): conj(U^2) T0 - conj(V^2) T1, then times U
     const double sr = fma(u2r, T0, -(v2r * T1)), si = fma(u2i, T0, -(v2i * T1));
     cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
@@ -553,26 +581,13 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
 }
 
 // FP32C keeps a node's angular sum in FP64 when the node lies close to the
-// angular cut.  The folded denominators are U^2 - V^2 s with s = z^2 in (0, 1);
-// rounding U^2, V^2 and s to FP32 perturbs them by ~eps32 (|U^2| + |V^2|),
-// relative to their smallest size, the distance d from U^2 to the segment
-// [0, V^2].  Nodes with (|U^2| + |V^2|) > kFp32Sensitivity d (tested in
-// squares, in FP64) take the FP64 sum.  The test depends on the node alone, so
-// results stay reproducible.
-constexpr double kFp32Sensitivity = 16.0;
-
+// angular cut: rounding U^2, V^2 and s to FP32 perturbs the denominators by
+// ~eps32 (|U^2| + |V^2|), relative to their smallest size, the distance from
+// U^2 to the segment [0, V^2]; the same test as the FP64 sum's choice of form.
 __device__ __forceinline__ bool near_angular_cut(cd U, cd V2)
 {
     const cd U2 = cmul(U, U);
-    const double vv = V2.r * V2.r + V2.i * V2.i;
-    const double uu = U2.r * U2.r + U2.i * U2.i;
-    if (vv == 0.0) return false;  // sum is exactly 1/U
-    // closest point of the segment s V^2, s in [0, 1], to U^2
-    double s = (U2.r * V2.r + U2.i * V2.i) / vv;
-    s = fmin(fmax(s, 0.0), 1.0);
-    const double dr = U2.r - s * V2.r, di = U2.i - s * V2.i;
-    const double dd = dr * dr + di * di;
-    return 2.0 * (uu + vv) > kFp32Sensitivity * kFp32Sensitivity * dd;
+    return near_cut_sq(U2.r, U2.i, V2.r, V2.i);
 }
 
 template <int PREC, class Args>
