@@ -230,6 +230,30 @@ def test_large_node_counts():
     _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
 
 
+@pytest.mark.parametrize("p,grid", [
+    (Params(1.0, 1.0, 1.0, 1e6), Grid(32, 32, -16.0, 8.0, -8.0, 8.0)),
+    (Params(1.0, 1.0, 1.0, 1e6), Grid(32, 8, -12.0, 0.0, -0.1, 0.1)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Grid(32, 32, -12.0, 6.0, -6.0, 6.0))],
+    ids=["bench_box", "cut_band", "conjugate"])
+def test_fp64_rounding_against_quad_precision(p, grid):
+    """The FP64 kernel (shared reciprocals, the real quadratic for |D|^2 away
+    from the angular cut) against the same quadrature in __float128: its
+    errors are no larger than the plain FP64 oracle's, within a factor 4, in
+    median and maximum over the grid."""
+    q = Quadrature(128, 64, 16)
+    g, c = _gpu_scan(p, q, grid)
+    x = oracle.grid_points(grid)
+    gq, cq = oracle.eval_points_q(p, q, x)
+    go, co = oracle.eval_points(p, q, x)
+    ok = np.isfinite(gq) & (cq == c)
+    assert ok.sum() >= 0.5 * x.size
+    ref = np.abs(gq[ok])
+    e_gpu = np.abs(g[ok] - gq[ok]) / ref
+    e_or = np.abs(go[ok] - gq[ok]) / ref
+    assert np.median(e_gpu) <= 4 * np.median(e_or) + 1e-16, (np.median(e_gpu), np.median(e_or))
+    assert e_gpu.max() <= 4 * e_or.max() + 1e-16, (e_gpu.max(), e_or.max())
+
+
 # ---------------------------------------------------------------- FP32C (FP32 bulk)
 
 def _fp32c_report(g32, g_ref, x, cut_threshold):
