@@ -75,10 +75,22 @@ __device__ __forceinline__ cd cut_zeta(const CutWalk &w, double u)
     return cdiv(cmul(U, U), cmul(w.x4, y));
 }
 
-__device__ void cut_step(CutWalk &w, double u)
+// Im zeta has the sign of Im(U^2 conj(4 x y)) (|4 x y|^2 > 0): the sampling
+// needs no division.
+__device__ __forceinline__ double cut_im_sign(const CutWalk &w, cd y)
 {
-    const cd z = cut_zeta(w, u);
-    if (w.started && ((w.pi > 0.0) != (z.i > 0.0))) {
+    const cd U = cadd(w.x1, y);
+    const cd U2 = cmul(U, U);
+    const cd D = cmul(w.x4, y);
+    return U2.i * D.r - U2.r * D.i;
+}
+
+// One sample at parameter u, contour point y: a sign change of Im zeta since
+// the previous sample is located by bisection on u (with zeta itself).
+__device__ void cut_step(CutWalk &w, double u, cd y)
+{
+    const double si = cut_im_sign(w, y);
+    if (w.started && ((w.pi > 0.0) != (si > 0.0))) {
         double lo = w.pu, hi = u;
         const bool lo_pos = w.pi > 0.0;
         for (int it = 0; it < 40; ++it) {
@@ -92,8 +104,46 @@ __device__ void cut_step(CutWalk &w, double u)
         if (zc.r >= 0.0 && zc.r <= 1.0) w.hit = true;
     }
     w.pu = u;
-    w.pi = z.i;
+    w.pi = si;
     w.started = true;
+}
+
+// Samples along the straight part, y_k = dir (e^{u_k} - 1), u_k = k h,
+// h = T/(n-1), k = 1..n-1: e^{u} - 1 follows e_{k+1} = e_k c + e_k + c
+// (c = e^h - 1), taken afresh from expm1 every 64 samples, so each sample sits
+// within ~64 ulp of its exact position (far inside the oracle's tie band).
+__device__ void cut_walk_straight(CutWalk &w, int n, double T)
+{
+    const double h = T / (n - 1);
+    const double c = expm1(h);
+    double e = 0.0;
+    for (int k = 1; k < n; ++k) {
+        const double u = k * h;
+        e = (k & 63) == 1 ? expm1(u) : fma(e, c, e + c);
+        cut_step(w, u, cscale(w.dir, e));
+    }
+}
+
+// Samples along the arc, psi_k = phi (1 - k/(n-1)), k = 0..n-1: the unit
+// vector rotates by e^{-i phi/(n-1)} per sample, taken afresh from sincos every
+// 64 samples.
+__device__ void cut_walk_arc(CutWalk &w, int n, double phi)
+{
+    const double dpsi = phi / (n - 1);
+    double s, c;
+    sincos(-dpsi, &s, &c);
+    const cd rot = mk(c, s);
+    cd e = mk(1.0, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const double psi = fma(-(double)k, dpsi, phi);
+        if ((k & 63) == 0) {
+            sincos(psi, &s, &c);
+            e = mk(c, s);
+        } else {
+            e = cmul(e, rot);
+        }
+        cut_step(w, psi, cscale(e, w.lam2));
+    }
 }
 
 __device__ CutWalk cut_walk_begin(const ScanArgs &a, double xr, double xi)
@@ -115,7 +165,7 @@ __device__ CutWalk cut_walk_begin(const ScanArgs &a, double xr, double xi)
 __device__ bool cut_hits_real_axis(const ScanArgs &a, double xr, double xi, int n, double T)
 {
     CutWalk w = cut_walk_begin(a, xr, xi);
-    for (int k = 1; k < n; ++k) cut_step(w, T * k / (n - 1));
+    cut_walk_straight(w, n, T);
     return w.hit;
 }
 
@@ -128,10 +178,10 @@ __device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n,
     double s, c;
     sincos(phi, &s, &c);
     w.dir = mk(c, s);
-    for (int k = 1; k < n; ++k) cut_step(w, T * k / (n - 1));
+    cut_walk_straight(w, n, T);
     w.arc = true;
     w.started = false;
-    for (int k = 0; k < n; ++k) cut_step(w, phi * (1.0 - (double)k / (n - 1)));
+    cut_walk_arc(w, n, phi);
     return w.hit;
 }
 
