@@ -410,11 +410,12 @@ __device__ __forceinline__ bool near_cut_sq(double ar, double ai, double br, dou
     const double vv = br * br + bi * bi;
     const double uu = ar * ar + ai * ai;
     if (vv == 0.0) return false;  // sum is exactly 1/U
-    // closest point of the segment s V^2, s in [0, 1], to U^2
-    double s = (ar * br + ai * bi) / vv;
-    s = fmin(fmax(s, 0.0), 1.0);
-    const double dr = ar - s * br, di = ai - s * bi;
-    return 2.0 * (uu + vv) > kCutSensitivity * kCutSensitivity * (dr * dr + di * di);
+    // squared distance of U^2 from the segment s V^2, s in [0, 1], times |V^2|^2
+    // (no division): |U^2|^2 |V^2|^2 before the segment (dot <= 0), |U^2 - V^2|^2
+    // |V^2|^2 beyond it (dot >= |V^2|^2), else cross^2
+    const double dot = ar * br + ai * bi, cross = ar * bi - ai * br;
+    const double d2vv = dot <= 0.0 ? uu * vv : (dot >= vv ? (uu - 2.0 * dot + vv) * vv : cross * cross);
+    return 2.0 * (uu + vv) * vv > kCutSensitivity * kCutSensitivity * d2vv;
 }
 
 // Sums T0 = sum 2w_j / q_j and T1 = sum 2w_j z_j^2 / q_j of the folded pairs,
