@@ -157,6 +157,31 @@ def test_config1_full_size_sampled():
     assert np.max(np.abs(gm - np.conj(gm[::-1])) / np.abs(gm)) < 1e-13
 
 
+@pytest.mark.parametrize("name", ["c3a_conj_2048sq", "c3b_unequal_2048sq"])
+def test_config3_full_size_sampled(name):
+    """The 2048^2 workloads at full size and nodes (512 x 256 + 16): complex
+    masses m^2 = 1 +- 0.5i (every contour class) and unequal real masses
+    m1 = 1, m2 = 0.5 with mu^2 = 2, in the benchmark's launch configuration:
+    sampled points against the oracle; NaN exactly at the SINGULAR class.
+    With real masses the quadrature at conj x is the mirror image of the one
+    at x, so G(conj x) = conj G(x) to rounding, row against row (the grid is
+    symmetric under Im x -> -Im x); with conjugate masses conjugation swaps
+    the legs, which the continuum function allows but the discretised
+    integral only to its quadrature error, so that check is not made."""
+    p, grid, q = CONFIGS[name]
+    g, c = _gpu_scan(p, q, grid)
+    idx = sample_points(grid, 400, seed=3)
+    x = oracle.grid_points_at(grid, idx)
+    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
+    _compare(g[idx], c[idx], p, q, x, go, co, cond)
+    assert np.array_equal(np.isnan(g), c == gf.CLASS_SINGULAR)
+    if complex(p.m1sq).imag == 0 and complex(p.m2sq).imag == 0:
+        gm = g.reshape(grid.n_im, grid.n_re)
+        ok = np.isfinite(gm) & np.isfinite(gm[::-1])
+        rel = np.abs(gm - np.conj(gm[::-1]))[ok] / np.abs(gm[ok])
+        assert rel.max() < 1e-12, rel.max()
+
+
 def test_conjugate_masses_sampled():
     """m1^2 = 1 + 0.5i, m2^2 = 1 - 0.5i, mu^2 = 1 on the 2:1 box of the
     complex-mass workload (reduced to 256^2 points, 512 x 256 nodes)."""
