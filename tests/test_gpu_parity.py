@@ -245,14 +245,44 @@ def test_subtraction_constant_matches_oracle():
         assert abs(j - jo) <= 1e-13 * abs(jo)
 
 
-def test_large_node_counts():
-    """Maximum-size radial rule (8192 nodes) at a few points."""
+@pytest.mark.parametrize("q", [Quadrature(8192, 64, 64), Quadrature(64, 8192, 16),
+                               Quadrature(64, 8191, 1024), Quadrature(32, 7, 0)],
+                         ids=["n_r_8192", "n_a_8192", "n_a_8191_arc_1024", "tiny"])
+def test_large_node_counts(q):
+    """The maximum radial order (8192), the maximum angular order (8192, and
+    8191: odd, with the middle node), the maximum arc order (1024) and a tiny
+    rule without arc nodes (real-axis points only), at a few points."""
     p = Params(1.0, 1.0, 1.0, 1e6, 1.0)
-    q = Quadrature(8192, 64, 64)
-    grid = Grid(4, 2, -6.0, 3.0, -3.0, 3.0)
+    grid = Grid(4, 2, -6.0, 3.0, -3.0, 3.0) if q.n_arc else Grid(4, 2, 1.0, 3.0, -0.5, 0.5)
     g, c = _gpu_scan(p, q, grid)
     go, co, cond = oracle.scan(p, q, grid, want_cond=True)
     _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
+
+
+def test_maximum_taylor_order_and_pole_count():
+    """t^8, the highest subtraction order, and eight poles on each leg (real
+    pole sums), against the oracle on a small ragged grid."""
+    from paper_1205_0752_amd.workloads import Propagators
+    for p, props in ((Params(2.0, 0.7, 1.5, 1e6, 1.0, 8), None),
+                     (Params(1.0, 1.0, 1.0, 1e6, 1.0),
+                      Propagators(tuple((0.5 + 0.4 * k, 1.0 / (k + 1)) for k in range(8)),
+                                  tuple((0.3 + 0.5 * k, 0.5 + 0.1 * k) for k in range(8))))):
+        q = Quadrature(64, 32, 16)
+        grid = Grid(13, 9, -8.0, 4.0, -4.0, 4.0)
+        plan = gf.Plan(p, q, props=props)
+        out = gf.empty_result(grid)
+        cls = torch.empty((grid.n_im, grid.n_re), dtype=torch.int8, device="cuda")
+        gf.scan_plan(plan, grid, out, cls)
+        torch.cuda.synchronize()
+        plan.close()
+        g = out.cpu().numpy().ravel()
+        c = cls.cpu().numpy().ravel()
+        go, co, cond = oracle.scan(p, q, grid, want_cond=True, props=props)
+        keep = (c == co) & (co != oracle.SINGULAR)
+        assert (c != co).sum() <= 1 and keep.sum() >= 0.5 * c.size
+        err = np.abs(g[keep] - go[keep])
+        mag = np.abs(go[keep])
+        assert np.all(err <= np.maximum(1e-12 * mag, 64 * EPS * cond[keep] * mag)), np.max(err / mag)
 
 
 @pytest.mark.parametrize("p,grid", [
