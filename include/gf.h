@@ -119,7 +119,8 @@ typedef struct {
 /* Node counts: n_radial Gauss-Legendre nodes in log(1+y) (1..8192),
  * n_angular angular nodes (1..8192; >= 3 for tanh-sinh) of the rule
  * angular_rule (GF_ANG_*), n_arc Gauss-Legendre nodes on the closing arc
- * (0..1024; 0 drops the arc), precision GF_PREC_*.  radial_split = 1 uses,
+ * (1..1024: every ray contour needs its arc; real-axis points do not use
+ * them), precision GF_PREC_*.  radial_split = 1 uses,
  * like the paper's several sub-contour node arrays (section "Numerical
  * Implementation"), four Gauss-Legendre pieces of n_radial/4 nodes each
  * (n_radial a multiple of 4) along the straight part of every point's

@@ -347,8 +347,10 @@ int validate_params(const gf_params *p, const gf_quadrature *q)
         return fail(GF_EINVAL, "n_radial must be in [1, 8192], got %d", q->n_radial);
     if (q->n_angular < 1 || q->n_angular > 8192)
         return fail(GF_EINVAL, "n_angular must be in [1, 8192], got %d", q->n_angular);
-    if (q->n_arc < 0 || q->n_arc > 1024)
-        return fail(GF_EINVAL, "n_arc must be in [0, 1024], got %d", q->n_arc);
+    // every ray contour closes with the arc |y| = Lambda^2 back to the real
+    // axis; without arc nodes its points would silently miss that part
+    if (q->n_arc < 1 || q->n_arc > 1024)
+        return fail(GF_EINVAL, "n_arc must be in [1, 1024], got %d", q->n_arc);
     if (q->precision != GF_PREC_FP64 && q->precision != GF_PREC_FP32C)
         return fail(GF_EINVAL, "precision must be GF_PREC_FP64 or GF_PREC_FP32C");
     if (q->angular_rule != GF_ANG_GC2 && q->angular_rule != GF_ANG_GC1 &&
@@ -694,7 +696,7 @@ int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, doubl
 int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_samples, uint8_t *out,
                        void *stream)
 {
-    const gf_quadrature q1 = {1, 1, 0, GF_PREC_FP64, GF_ANG_GC2, 0};  // the map needs no nodes
+    const gf_quadrature q1 = {1, 1, 1, GF_PREC_FP64, GF_ANG_GC2, 0};  // the map needs no nodes
     int rc = gf::validate_params(params, &q1);
     if (rc != GF_OK) return rc;
     if ((rc = gf::validate_grid(*params, nullptr, grid)) != GF_OK) return rc;

@@ -44,6 +44,7 @@ def test_version(lib):
     (gf.Params(1.0, 1.0, 1.0, 1e4), gf.Quadrature(0, 32, 16), "n_radial"),
     (gf.Params(1.0, 1.0, 1.0, 1e4), gf.Quadrature(64, 9000, 16), "n_angular"),
     (gf.Params(1.0, 1.0, 1.0, 1e4), gf.Quadrature(64, 32, -1), "n_arc"),
+    (gf.Params(1.0, 1.0, 1.0, 1e4), gf.Quadrature(64, 32, 0), "n_arc"),
     (gf.Params(1.0, 1.0, 1.0, 1e4), gf.Quadrature(64, 32, 16, 7), "precision"),
 ])
 def test_plan_validation_before_any_device_call(lib, params, quad, msg):

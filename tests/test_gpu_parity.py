@@ -246,14 +246,14 @@ def test_subtraction_constant_matches_oracle():
 
 
 @pytest.mark.parametrize("q", [Quadrature(8192, 64, 64), Quadrature(64, 8192, 16),
-                               Quadrature(64, 8191, 1024), Quadrature(32, 7, 0)],
+                               Quadrature(64, 8191, 1024), Quadrature(32, 7, 1)],
                          ids=["n_r_8192", "n_a_8192", "n_a_8191_arc_1024", "tiny"])
 def test_large_node_counts(q):
     """The maximum radial order (8192), the maximum angular order (8192, and
     8191: odd, with the middle node), the maximum arc order (1024) and a tiny
-    rule without arc nodes (real-axis points only), at a few points."""
+    rule (7 angular nodes, one arc node), at a few points."""
     p = Params(1.0, 1.0, 1.0, 1e6, 1.0)
-    grid = Grid(4, 2, -6.0, 3.0, -3.0, 3.0) if q.n_arc else Grid(4, 2, 1.0, 3.0, -0.5, 0.5)
+    grid = Grid(4, 2, -6.0, 3.0, -3.0, 3.0)
     g, c = _gpu_scan(p, q, grid)
     go, co, cond = oracle.scan(p, q, grid, want_cond=True)
     _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
