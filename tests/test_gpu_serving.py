@@ -193,3 +193,36 @@ def test_poll_states_and_unknown_ticket():
         srv.release(t)
         with pytest.raises(gf.GFError):
             srv.release(t)
+
+
+def test_server_edge_cases():
+    """A zero-point grid completes at once with an empty result; a rejected
+    submission (no arc nodes) leaves the server working; a zero timeout on a
+    long request returns False and the request still completes; a released
+    ticket is unknown afterwards; destroying the server with requests still
+    queued and running returns (it drains the launched batches)."""
+    p = Params(1.0, 1.0, 1.0, 1e6)
+    with gf.Server(budget_bytes=64 << 20, max_inflight=16) as srv:
+        t0 = srv.submit(p, Grid(0, 4, -1.0, 1.0, -1.0, 1.0), Quadrature(64, 32, 16))
+        assert srv.wait(t0, 1000.0)
+        assert srv.result(t0).size == 0
+        srv.release(t0)
+        with pytest.raises(gf.GFError) as e:
+            srv.submit(p, Grid(8, 8, -1.0, 1.0, -1.0, 1.0), Quadrature(64, 32, 0))
+        assert e.value.code == -1
+        big = srv.submit(p, Grid(512, 512, -16.0, 8.0, -8.0, 8.0), Quadrature(512, 512, 16))
+        assert not srv.wait(big, 0.0)
+        assert srv.wait(big, WAIT_MS)
+        g = srv.result(big)
+        assert g.size == 512 * 512 and np.isfinite(g).all()
+        srv.release(big)
+        with pytest.raises(gf.GFError) as e:
+            srv.result(big)
+        assert e.value.code == -6
+        st = srv.stats()
+        assert st["completed"] == 2 and st["rejected"] == 1
+    # destroy with work outstanding
+    srv = gf.Server(budget_bytes=64 << 20, max_inflight=16)
+    for _ in range(12):
+        srv.submit(p, Grid(256, 256, -8.0, 4.0, -4.0, 4.0), Quadrature(256, 128, 16))
+    srv.close()
