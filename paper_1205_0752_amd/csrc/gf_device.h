@@ -400,22 +400,36 @@ __device__ __forceinline__ int scale_exponent(cd U2, cd V2)
 }
 
 // Near the angular cut: the folded denominators U^2 - V^2 s, s = z^2 in (0, 1),
-// come within dist(U^2, [0, V^2]) of zero; a node is "near" when
-// (|U^2| + |V^2|) > kCutSensitivity dist (tested in squares).  The test depends
-// on the node alone, so results stay reproducible.
+// come within dist(U^2, [0, V^2]) of zero.  The ratio (|U^2| + |V^2|) / dist
+// bounds how much rounding in U^2, V^2 or s is amplified in a denominator:
+// by the ratio itself for D computed directly, by its square for |D|^2 taken
+// from the quadratic in s.  A node is "near" when the ratio exceeds
+// kCutSensitivity; the FP32 sums take the quadratic only below
+// kQuad32Sensitivity, the square root of kCutSensitivity, so their worst
+// case stays that of the direct form at the near threshold.  The tests
+// depend on the node alone, so results stay reproducible.
 constexpr double kCutSensitivity = 16.0;
+constexpr double kQuad32Sensitivity = 4.0;
 
-__device__ __forceinline__ bool near_cut_sq(double ar, double ai, double br, double bi)
+// 2 (|U^2|^2 + |V^2|^2) |V^2|^2 and dist^2 |V^2|^2 (no division), on U^2 = (ar, ai),
+// V^2 = (br, bi): the squared ratio, up to a factor of at most 2, is lhs / d2vv.
+// The distance is |U^2| before the segment (dot <= 0), |U^2 - V^2| beyond it
+// (dot >= |V^2|^2), else |cross| / |V^2|.
+__device__ __forceinline__ void cut_measure(double ar, double ai, double br, double bi,
+                                            double &lhs, double &d2vv)
 {
     const double vv = br * br + bi * bi;
     const double uu = ar * ar + ai * ai;
-    if (vv == 0.0) return false;  // sum is exactly 1/U
-    // squared distance of U^2 from the segment s V^2, s in [0, 1], times |V^2|^2
-    // (no division): |U^2|^2 |V^2|^2 before the segment (dot <= 0), |U^2 - V^2|^2
-    // |V^2|^2 beyond it (dot >= |V^2|^2), else cross^2
     const double dot = ar * br + ai * bi, cross = ar * bi - ai * br;
-    const double d2vv = dot <= 0.0 ? uu * vv : (dot >= vv ? (uu - 2.0 * dot + vv) * vv : cross * cross);
-    return 2.0 * (uu + vv) * vv > kCutSensitivity * kCutSensitivity * d2vv;
+    d2vv = dot <= 0.0 ? uu * vv : (dot >= vv ? (uu - 2.0 * dot + vv) * vv : cross * cross);
+    lhs = 2.0 * (uu + vv) * vv;  // 0 when V^2 = 0: the sum is exactly 1/U, never near
+}
+
+__device__ __forceinline__ bool near_cut_sq(double ar, double ai, double br, double bi)
+{
+    double lhs, d2vv;
+    cut_measure(ar, ai, br, bi, lhs, d2vv);
+    return lhs > kCutSensitivity * kCutSensitivity * d2vv;
 }
 
 // Sums T0 = sum 2w_j / q_j and T1 = sum 2w_j z_j^2 / q_j of the folded pairs,
@@ -510,92 +524,98 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     return A;
 }
 
-// FP32 angular sum with blocked accumulation.  U^2 and V^2 are formed in
-// FP64 and scaled by an exact power of two 2^-e (e = exponent of their largest
-// component) before rounding to FP32, so every FP32 denominator is O(1) and the
-// shared-reciprocal product q0 q1 stays in range.  As in the FP64 sum, the
-// pair sum is conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j/|D_j|^2
-// and T1 = sum 2w_j z_j^2/|D_j|^2 (positive terms); each is summed in FP32
-// blocks of kBlock pairs whose block sums are added in FP64 (for sums of
-// positive terms this bounds the error by the block's, like a two-sum
-// accumulator of the block sums, at two instructions per block and sum), and
-// the combination with the FP32 values of U^2 and V^2 (exact in FP64) is
-// taken in FP64.  The table holds (z_j^2, 2w_j, 2w_j z_j^2) in FP32.
+// FP32 angular sum with blocked accumulation, on U^2 and V^2 formed in FP64
+// and scaled by the exact power of two 2^-e (e = exponent of their largest
+// component), so every FP32 denominator is O(1) and the shared-reciprocal
+// product q0 q1 stays in range.  As in the FP64 sum, the pair sum is
+// conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j/|D_j|^2 and
+// T1 = sum 2w_j z_j^2/|D_j|^2 (positive terms); each is summed in FP32 blocks
+// of kBlock pairs whose block sums are added in FP64 (for sums of positive
+// terms this bounds the error by the block's, like a two-sum accumulator of
+// the block sums, at two instructions per block and sum).  QUAD: q_j from the
+// quadratic c0 - c1 s + c2 s^2 with its coefficients formed in FP64 and
+// rounded once, so the denominators are those of the FP64 U^2, V^2, which the
+// final combination (in FP64) then takes.  Otherwise q_j = |D_j|^2 from D_j
+// in FP32, and the combination takes the FP32 values of U^2, V^2 (exact in
+// FP64) that D_j was formed from.  The table holds (z_j^2, 2w_j, 2w_j z_j^2) in FP32.
 constexpr int kBlock = 16;
 
+template <bool QUAD>
 __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
-                                             cd V2)
+                                             double u2r, double u2i, double v2r, double v2i, int e)
 {
     const auto *tab = ro(table);
-    const cd U2 = cmul(U, U);
-    const int e = scale_exponent(U2, V2);
-    const float u2r = (float)ldexp(U2.r, -e), u2i = (float)ldexp(U2.i, -e);
-    const float v2r = (float)ldexp(V2.r, -e), v2i = (float)ldexp(V2.i, -e);
+    const float fu2r = (float)u2r, fu2i = (float)u2i, fv2r = (float)v2r, fv2i = (float)v2i;
+    const float c0 = (float)fma(u2r, u2r, u2i * u2i), c2 = (float)fma(v2r, v2r, v2i * v2i);
+    const float c1 = (float)(-2.0 * fma(u2r, v2r, u2i * v2i));
+    auto qof = [&](float s) {
+        if (QUAD) return fmaf(fmaf(c2, s, c1), s, c0);
+        const float dr = fmaf(-fv2r, s, fu2r), di = fmaf(-fv2i, s, fu2i);
+        return fmaf(dr, dr, di * di);
+    };
     double T0 = 0.0, T1 = 0.0;  // FP32 block sums added in FP64
     int p = 0;
     while (p < npair) {
         const int pe = min(p + kBlock, npair);
-        float b0 = 0.0f, c0 = 0.0f, b1 = 0.0f, c1 = 0.0f;
+        float b0 = 0.0f, d0 = 0.0f, b1 = 0.0f, d1 = 0.0f;
         const auto *t = tab + 3 * p;
         // four pairs per step, two shared reciprocals (of q0 q1 and q2 q3)
         for (; p + 4 <= pe; p += 4, t += 12) {
-            const float zz0 = t[0], ww0 = t[1], wz0 = t[2];
-            const float zz1 = t[3], ww1 = t[4], wz1 = t[5];
-            const float zz2 = t[6], ww2 = t[7], wz2 = t[8];
-            const float zz3 = t[9], ww3 = t[10], wz3 = t[11];
-            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
-            const float dr1 = fmaf(-v2r, zz1, u2r), di1 = fmaf(-v2i, zz1, u2i);
-            const float dr2 = fmaf(-v2r, zz2, u2r), di2 = fmaf(-v2i, zz2, u2i);
-            const float dr3 = fmaf(-v2r, zz3, u2r), di3 = fmaf(-v2i, zz3, u2i);
-            const float q0 = fmaf(dr0, dr0, di0 * di0);
-            const float q1 = fmaf(dr1, dr1, di1 * di1);
-            const float q2 = fmaf(dr2, dr2, di2 * di2);
-            const float q3 = fmaf(dr3, dr3, di3 * di3);
+            const float q0 = qof(t[0]), q1 = qof(t[3]), q2 = qof(t[6]), q3 = qof(t[9]);
             const float inv01 = __builtin_amdgcn_rcpf(q0 * q1);
             const float inv23 = __builtin_amdgcn_rcpf(q2 * q3);
             const float r0 = q1 * inv01, r1 = q0 * inv01;  // 1 / q_k
             const float r2 = q3 * inv23, r3 = q2 * inv23;
-            b0 = fmaf(ww0, r0, b0);
-            c0 = fmaf(wz0, r0, c0);
-            b1 = fmaf(ww1, r1, b1);
-            c1 = fmaf(wz1, r1, c1);
-            b0 = fmaf(ww2, r2, b0);
-            c0 = fmaf(wz2, r2, c0);
-            b1 = fmaf(ww3, r3, b1);
-            c1 = fmaf(wz3, r3, c1);
+            b0 = fmaf(t[1], r0, b0);
+            d0 = fmaf(t[2], r0, d0);
+            b1 = fmaf(t[4], r1, b1);
+            d1 = fmaf(t[5], r1, d1);
+            b0 = fmaf(t[7], r2, b0);
+            d0 = fmaf(t[8], r2, d0);
+            b1 = fmaf(t[10], r3, b1);
+            d1 = fmaf(t[11], r3, d1);
         }
         for (; p < pe; ++p, t += 3) {
-            const float zz0 = t[0], ww0 = t[1], wz0 = t[2];
-            const float dr0 = fmaf(-v2r, zz0, u2r), di0 = fmaf(-v2i, zz0, u2i);
-            const float r0 = __builtin_amdgcn_rcpf(fmaf(dr0, dr0, di0 * di0));
-            b0 = fmaf(ww0, r0, b0);
-            c0 = fmaf(wz0, r0, c0);
+            const float r0 = __builtin_amdgcn_rcpf(qof(t[0]));
+            b0 = fmaf(t[1], r0, b0);
+            d0 = fmaf(t[2], r0, d0);
         }
         T0 += (double)(b0 + b1);
-        T1 += (double)(c0 + c1);
+        T1 += (double)(d0 + d1);
     }
-    const double sr = fma((double)u2r, T0, -((double)v2r * T1));
-    const double si = fma((double)u2i, T0, -((double)v2i * T1));
+    const double ar = QUAD ? u2r : (double)fu2r, ai = QUAD ? u2i : (double)fu2i;
+    const double br = QUAD ? v2r : (double)fv2r, bi = QUAD ? v2i : (double)fv2i;
+    const double sr = fma(ar, T0, -(br * T1)), si = fma(ai, T0, -(bi * T1));
     cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
     return A;
 }
 
-// FP32C keeps a node's angular sum in FP64 when the node lies close to the
-// angular cut: rounding U^2, V^2 and s to FP32 perturbs the denominators by
-// ~eps32 (|U^2| + |V^2|), relative to their smallest size, the distance from
-// U^2 to the segment [0, V^2]; the same test as the FP64 sum's choice of form.
-__device__ __forceinline__ bool near_angular_cut(cd U, cd V2)
+// FP32C: by the node's ratio (|U^2| + |V^2|) / dist, the FP64 sum near the cut
+// (rounding U^2, V^2 and s to FP32 perturbs a denominator by ~eps32 times the
+// ratio), the FP32 sum with direct denominators below that, and with the
+// quadratic below kQuad32Sensitivity.
+template <class Args>
+__device__ __forceinline__ cd angular_sum_fp32c(const Args &a, cd U, cd V2)
 {
     const cd U2 = cmul(U, U);
-    return near_cut_sq(U2.r, U2.i, V2.r, V2.i);
+    const int e = scale_exponent(U2, V2);
+    const double u2r = ldexp(U2.r, -e), u2i = ldexp(U2.i, -e);
+    const double v2r = ldexp(V2.r, -e), v2i = ldexp(V2.i, -e);
+    double lhs, d2vv;
+    cut_measure(u2r, u2i, v2r, v2i, lhs, d2vv);
+    if (lhs > kCutSensitivity * kCutSensitivity * d2vv)
+        return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+    if (lhs > kQuad32Sensitivity * kQuad32Sensitivity * d2vv)
+        return angular_sum32c<false>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e);
+    return angular_sum32c<true>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e);
 }
 
 template <int PREC, class Args>
 __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 {
-    if (PREC == 0 || near_angular_cut(U, V2)) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
-    return angular_sum32c(a.ang32, a.n_a / 2, a.wmid, U, V2);
+    if (PREC == 0) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+    return angular_sum_fp32c(a, U, V2);
 }
 
 // Pole sums: <P1(D1)> = sum_a c1_a <1/(U_a - V z)>, U_a = U + m1_a^2 - m1_0^2
