@@ -59,7 +59,9 @@ extern "C" {
 #define GF_PREC_FP64 0   /* everything in FP64 */
 #define GF_PREC_FP32C 1  /* angular sum in FP32, its blocks of 16 pairs
                             accumulated in FP64; nodes near the angular cut
-                            in FP64; sqrt(x), contour choice, per-node
+                            in FP64, nodes far from it with |D|^2 taken from
+                            its quadratic in z^2 (coefficients rounded once
+                            from FP64); sqrt(x), contour choice, per-node
                             coefficients, radial sum, mu^2 subtraction and
                             scaling in FP64 */
 
