@@ -410,6 +410,7 @@ def main() -> int:
                            "tflops": t2["tflops"],
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
                            "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS,
+                           "lanes_per_point": t2["lanes"], "kernel": t2["kernel"],
                            "error_vs_fp64": fp32c_errors(gf, torch, p2, g2, q2)}
     if not args.skip_extensions and args.config == "c1_fp64_1024sq":
         result["extensions"] = extensions(gf, torch)

@@ -212,8 +212,12 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
 /* As gf_scan_plan with an explicit number of lanes per grid point
  * (1, 2, 4, ..., 64; 0 = automatic).  Each point's quadrature nodes are
  * split across that many lanes of a 64-wide wavefront and the partial sums
- * reduced with cross-lane shuffles; automatic picks 1 for large grids and more
- * lanes for small ones so that the launch fills the GPU. */
+ * reduced with cross-lane shuffles.  Automatic takes the smallest count whose
+ * wave tiles make at least 4 rounds of the kernel's resident waves (8 for pole
+ * sums with a complex (p-k)-leg pole, whose plane can hold points without a
+ * contour), but none that leaves a lane fewer than 2048 angular pairs, and
+ * never fewer lanes than fill the GPU once: 1 for large grids, more for
+ * smaller ones.  Results depend on the lane count only through rounding. */
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
                     int lanes_per_point, void *stream);
 

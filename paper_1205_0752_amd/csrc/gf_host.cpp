@@ -416,15 +416,38 @@ int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid
     return GF_OK;
 }
 
-int auto_lanes(const gf_grid &g)
+// Lanes per point.  A launch should hold several rounds of the kernel's
+// resident waves: its last round drains with SIMDs left one or two waves that
+// cannot hide latency, so at least kRounds rounds, twice that when a complex
+// pole on the (p-k) leg can leave part of the plane without a contour (those
+// tiles end at once).  But each lane should keep kMinLanePairs angular pairs
+// (its share of a point's contour nodes times pairs per node times (p-k)-leg
+// poles): every lane repeats its point's setup and the nodes split unevenly.
+// And the grid should fill the device at least once.
+constexpr long long kRounds = 4;
+constexpr long long kMinLanePairs = 2048;
+
+int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g)
 {
+    const bool taylor = base.n_taylor > 0, split = base.split != 0, poles = base.poles != 0;
+    bool open_plane = false;  // a complex (p-k)-leg pole in a pole sum
+    for (int i = 0; poles && i < base.n1; ++i) open_plane = open_plane || base.p1[4 * i + 1] != 0.0;
+    const long long rounds = open_plane ? 2 * kRounds : kRounds;
+    const long long pairs = (long long)((base.n_a + 1) / 2) * (poles ? base.n1 : 1);
+    const long long nodes = (long long)base.n_r + base.n_arc + (poles ? base.n2 : 1);
+    int fill = 0, want = 0, work = 1;
     for (int l = 1; l <= 64; l *= 2) {
         int ta;
         long long nt;
         tiles_for(g, l, &ta, &nt);
-        if (nt >= 4096) return l;
+        const long long slots = scan_resident_waves(precision, l, taylor, split, poles);
+        if (!fill && nt >= slots) fill = l;
+        if (!want && nt >= rounds * slots) want = l;
+        if (l > 1 && (nodes + l - 1) / l * pairs >= kMinLanePairs) work = l;
     }
-    return 64;
+    if (!fill) fill = 64;
+    if (!want) want = 64;
+    return std::max(fill, std::min(want, work));
 }
 
 int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
@@ -603,7 +626,7 @@ int gf_plan_taylor(const gf_plan_t *plan, double *coeffs)
 int gf_plan_auto_lanes(const gf_plan_t *plan, const gf_grid *grid)
 {
     if (!plan || !grid) return fail(GF_EINVAL, "NULL argument");
-    return gf::auto_lanes(*grid);
+    return gf::auto_lanes(plan->base, plan->quad.precision, *grid);
 }
 
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
@@ -615,7 +638,7 @@ int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_
     if ((long long)grid->n_re * grid->n_im == 0) return GF_OK;
     if (!out) return fail(GF_EINVAL, "out must not be NULL");
     int lanes = lanes_per_point;
-    if (lanes == 0) lanes = gf::auto_lanes(*grid);
+    if (lanes == 0) lanes = gf::auto_lanes(plan->base, plan->quad.precision, *grid);
     if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)) != 0)
         return fail(GF_EINVAL, "lanes_per_point must be 0 or a power of two <= 64, got %d",
                     lanes_per_point);

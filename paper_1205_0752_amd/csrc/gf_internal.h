@@ -110,6 +110,10 @@ hipError_t launch_serve(const ScanArgs *reqs, const WorkItem *items, int n_items
 // once (occupancy x compute units x 4 waves per 256-thread block); 4096 if
 // the runtime cannot say.
 int serve_resident_waves(int precision, int lanes, int split, int poles);
+// Wavefronts of the scan kernel for these flags the current device holds at
+// once (occupancy x compute units; one wave per workgroup), cached per device
+// and kernel form; 4096 if the runtime cannot say.
+int scan_resident_waves(int precision, int lanes, bool taylor, bool split, bool poles);
 
 // ---- host helpers shared by plans and the server (gf_host.cpp) ----------
 
@@ -130,8 +134,9 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_propagators *props
 int validate_props(const gf_propagators *props, const gf_quadrature &q);
 int validate_params(const gf_params *p, const gf_quadrature *q);
 int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid *g);
-// lanes per point the automatic choice uses for a grid
-int auto_lanes(const gf_grid &g);
+// lanes per point the automatic choice uses for a grid scanned with a plan's
+// arguments and precision
+int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g);
 // grid fields and wave tiles of a ScanArgs for `lanes` lanes per point
 int set_grid(ScanArgs &a, const gf_grid &g, int lanes);
 int current_device(int *dev);

@@ -14,6 +14,7 @@
 // (U, V) in registers.  Partial sums of the L lanes of a point are combined
 // with cross-lane shuffles, the real-axis subtraction sum at mu^2 (eq. 14) is
 // removed, the result scaled, conjugated for mirror points, and written once.
+#include <atomic>
 #include "gf_device.h"
 
 namespace gf {
@@ -395,6 +396,27 @@ hipError_t launch_jmu_batch(ScanArgs *reqs, const ScanArgs *staged, const int *s
 
 namespace {
 
+// The scan kernel instance launch_l runs for these flags.
+template <int L>
+const void *scan_fn(int precision, bool taylor, bool split, bool poles)
+{
+    if (precision == 0)
+        return poles ? reinterpret_cast<const void *>(scan_kernel_fp64<L, true, false, true>)
+               : taylor && split
+                   ? reinterpret_cast<const void *>(scan_kernel_fp64<L, true, true, false>)
+               : taylor ? reinterpret_cast<const void *>(scan_kernel_fp64<L, true, false, false>)
+               : split  ? reinterpret_cast<const void *>(scan_kernel_fp64<L, false, true, false>)
+                        : reinterpret_cast<const void *>(scan_kernel_fp64<L, false, false, false>);
+    if (precision == 1)
+        return poles ? reinterpret_cast<const void *>(scan_kernel_fp32c<L, true, false, true>)
+               : taylor && split
+                   ? reinterpret_cast<const void *>(scan_kernel_fp32c<L, true, true, false>)
+               : taylor ? reinterpret_cast<const void *>(scan_kernel_fp32c<L, true, false, false>)
+               : split  ? reinterpret_cast<const void *>(scan_kernel_fp32c<L, false, true, false>)
+                        : reinterpret_cast<const void *>(scan_kernel_fp32c<L, false, false, false>);
+    return nullptr;
+}
+
 template <int L>
 const void *serve_fn(int precision, int split, int poles)
 {
@@ -410,6 +432,44 @@ const void *serve_fn(int precision, int split, int poles)
 }
 
 }  // namespace
+
+int scan_resident_waves(int precision, int lanes, bool taylor, bool split, bool poles)
+{
+    // cached per device and kernel form: [device][precision][log2 lanes][taylor][split][poles]
+    constexpr int kDevices = 16;
+    static std::atomic<int> cache[kDevices][2][7][2][2][2];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 4096;
+    int lg = 0;
+    while (lg < 7 && (1 << lg) != lanes) ++lg;
+    if (lg == 7 || precision < 0 || precision > 1) return 4096;
+    std::atomic<int> *slot = dev >= 0 && dev < kDevices
+                                 ? &cache[dev][precision][lg][taylor][split][poles]
+                                 : nullptr;
+    if (slot) {
+        const int v = slot->load(std::memory_order_relaxed);
+        if (v > 0) return v;
+    }
+    const void *f = nullptr;
+    switch (lanes) {
+    case 1: f = scan_fn<1>(precision, taylor, split, poles); break;
+    case 2: f = scan_fn<2>(precision, taylor, split, poles); break;
+    case 4: f = scan_fn<4>(precision, taylor, split, poles); break;
+    case 8: f = scan_fn<8>(precision, taylor, split, poles); break;
+    case 16: f = scan_fn<16>(precision, taylor, split, poles); break;
+    case 32: f = scan_fn<32>(precision, taylor, split, poles); break;
+    case 64: f = scan_fn<64>(precision, taylor, split, poles); break;
+    default: break;
+    }
+    int cus = 0, blocks = 0;
+    if (!f || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, 64, 0) != hipSuccess ||
+        cus <= 0 || blocks <= 0)
+        return 4096;
+    const int waves = cus * blocks;  // one wave per workgroup
+    if (slot) slot->store(waves, std::memory_order_relaxed);
+    return waves;
+}
 
 int serve_resident_waves(int precision, int lanes, int split, int poles)
 {
