@@ -215,7 +215,8 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
  * reduced with cross-lane shuffles.  Automatic takes the smallest count whose
  * wave tiles make at least 4 rounds of the kernel's resident waves (8 for pole
  * sums with a complex (p-k)-leg pole, whose plane can hold points without a
- * contour), but none that leaves a lane fewer than 2048 angular pairs, and
+ * contour), but none that leaves a lane fewer than 2048 angular pairs (4096
+ * in FP32C), and
  * never fewer lanes than fill the GPU once: 1 for large grids, more for
  * smaller ones.  Results depend on the lane count only through rounding. */
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
