@@ -213,7 +213,7 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
  * (1, 2, 4, ..., 64; 0 = automatic).  Each point's quadrature nodes are
  * split across that many lanes of a 64-wide wavefront and the partial sums
  * reduced with cross-lane shuffles.  Automatic takes the smallest count whose
- * wave tiles make at least 4 rounds of the kernel's resident waves (8 for pole
+ * wave tiles make at least 4 rounds of the kernel's resident waves (16 for pole
  * sums with a complex (p-k)-leg pole, whose plane can hold points without a
  * contour), but none that leaves a lane fewer than 2048 angular pairs (4096
  * in FP32C), and

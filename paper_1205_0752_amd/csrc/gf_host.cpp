@@ -418,9 +418,9 @@ int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid
 
 // Lanes per point.  A launch should hold several rounds of the kernel's
 // resident waves: its last round drains with SIMDs left one or two waves that
-// cannot hide latency, so at least kRounds rounds, twice that when a complex
-// pole on the (p-k) leg can leave part of the plane without a contour (those
-// tiles end at once).  But each lane should keep kMinLanePairs angular pairs
+// cannot hide latency, so at least kRounds rounds, four times that when a
+// complex pole on the (p-k) leg can leave part of the plane without a contour
+// (those tiles end at once: about half of them for a conjugate pair).  But each lane should keep kMinLanePairs angular pairs
 // (its share of a point's contour nodes times pairs per node times (p-k)-leg
 // poles): every lane repeats its point's setup and the nodes split unevenly;
 // FP32C pairs are cheaper than FP64 ones next to that setup, so it keeps twice
@@ -435,7 +435,7 @@ int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g)
     const bool taylor = base.n_taylor > 0, split = base.split != 0, poles = base.poles != 0;
     bool open_plane = false;  // a complex (p-k)-leg pole in a pole sum
     for (int i = 0; poles && i < base.n1; ++i) open_plane = open_plane || base.p1[4 * i + 1] != 0.0;
-    const long long rounds = open_plane ? 2 * kRounds : kRounds;
+    const long long rounds = open_plane ? 4 * kRounds : kRounds;
     const long long pairs = (long long)((base.n_a + 1) / 2) * (poles ? base.n1 : 1);
     const long long nodes = (long long)base.n_r + base.n_arc + (poles ? base.n2 : 1);
     int fill = 0, want = 0, work = 1;

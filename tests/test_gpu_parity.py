@@ -236,7 +236,7 @@ def test_empty_grid_and_validation_errors():
 
 def test_automatic_lanes_follow_the_rounds_and_lane_work_rule():
     """The automatic lanes per point on MI355X (4 resident FP64 waves and 6
-    FP32C waves per SIMD): at least 4 rounds of resident waves (8 for a pole
+    FP32C waves per SIMD): at least 4 rounds of resident waves (16 for a pole
     sum with a complex (p-k)-leg pole), no lane below 2048 angular pairs (4096
     in FP32C), the device filled at least once.  The bench grid keeps one lane per point."""
     from paper_1205_0752_amd.workloads import Propagators
@@ -252,7 +252,8 @@ def test_automatic_lanes_follow_the_rounds_and_lane_work_rule():
              (Quadrature(512, 256, 16, gf.FP32C), None, 1024, 2),
              (Quadrature(512, 256, 16, gf.FP32C), None, 512, 8),
              (Quadrature(512, 256, 16, gf.FP32C), None, 256, 16),
-             (Quadrature(256, 128, 16), pair, 1024, 2), (Quadrature(256, 128, 16), pair, 256, 16)]
+             (Quadrature(256, 128, 16), pair, 1024, 4), (Quadrature(256, 128, 16), pair, 512, 16),
+             (Quadrature(256, 128, 16), pair, 256, 16)]
     for q, props, n, want in cases:
         plan = gf.Plan(p, q, props=props)
         assert plan.auto_lanes(box(n)) == want, (q, props is not None, n)
