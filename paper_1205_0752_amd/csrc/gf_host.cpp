@@ -416,17 +416,19 @@ int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid
     return GF_OK;
 }
 
-// Lanes per point.  A launch should hold several rounds of the kernel's
-// resident waves: its last round drains with SIMDs left one or two waves that
-// cannot hide latency, so at least kRounds rounds, four times that when a
-// complex pole on the (p-k) leg can leave part of the plane without a contour
-// (those tiles end at once: about half of them for a conjugate pair).  But each lane should keep kMinLanePairs angular pairs
-// (its share of a point's contour nodes times pairs per node times (p-k)-leg
-// poles): every lane repeats its point's setup and the nodes split unevenly;
-// FP32C pairs are cheaper than FP64 ones next to that setup, so it keeps twice
-// as many (measured: FP32C on 256^2 at 4224 pairs per lane 9 % faster than at
-// 2176, FP64 at 1152 within 1 % of 2240).  And the grid should fill the
-// device at least once.
+// Lanes per point, the smallest count that meets three aims:
+//  * several rounds of the kernel's resident waves per launch, since the last
+//    round drains with SIMDs left one or two waves that cannot hide latency:
+//    kRounds rounds, four times that when a complex pole on the (p-k) leg can
+//    leave part of the plane without a contour (those tiles end at once; about
+//    half of them for a conjugate pair);
+//  * but no count that leaves a lane fewer than kMinLanePairs angular pairs
+//    (its share of a point's contour nodes x pairs per node x (p-k)-leg
+//    poles), since every lane repeats its point's setup and the nodes split
+//    unevenly; FP32C pairs are cheaper next to that setup, so it keeps twice
+//    as many (measured: FP32C on 256^2 9 % faster at 4224 pairs per lane than
+//    at 2176; FP64 at 1152 within 1 % of 2240);
+//  * and never fewer lanes than fill the device once.
 constexpr long long kRounds = 4;
 constexpr long long kMinLanePairs[2] = {2048, 4096};  // FP64, FP32C
 
