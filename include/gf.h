@@ -296,8 +296,9 @@ int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_sampl
  * yet resident fit in the arena and a slot is free; admitted requests run
  * concurrently: each scheduler iteration packs wave tiles of every running
  * request (a fair share of `batch_evals` integrand evaluations each, oldest
- * first, topped up with further tiles while the batch has fewer than about
- * 1.5 tiles per wave slot of the device) into persistent kernel launches, most
+ * first, topped up with further tiles to half the tiles still to run, at
+ * least 1.5 and at most 6 tiles per wave slot of the device: short batches
+ * while little waits, long ones under load) into persistent kernel launches, most
  * expensive tiles first, and keeps three such batches in flight; a launch's
  * last long tiles overlap the next launch on the other stream.  A request completes
  * when its last tile has run; its result stays in the arena until

@@ -168,7 +168,9 @@ struct gf_server {
     int next_comp = 0;
     hipEvent_t group_ev[kStages][kMaxGroups] = {};
     std::map<std::tuple<int, int, int, int>, int> resident;  // waves per launch group
-    long long fill_items = 0;  // items a batch takes at least, while tiles remain
+    // items a batch takes at least while tiles remain: between fill_min and
+    // fill_max, half the tiles still to run
+    long long fill_min = 0, fill_max = 0;
     char *d_arena = nullptr;
     Arena arena;
     gf::ScanArgs *d_args = nullptr;
@@ -412,6 +414,13 @@ void gf_server::run()
                 for (Request *r : running)
                     if (r->next_tile < r->n_tiles) active.push_back(r);
             if (!active.empty()) {
+                // top-up target: 1.5 rounds of resident waves while little work
+                // waits (short batches keep latency low), growing with the
+                // backlog to 6 rounds (long launches amortise their drain and
+                // the per-batch costs under load)
+                long long backlog = 0;
+                for (Request *r : active) backlog += r->n_tiles - r->next_tile;
+                const long long fill_items = std::min(fill_max, std::max(fill_min, backlog / 2));
                 double budget = cfg.batch_evals;
                 const double share = budget / (double)active.size();
                 for (int pass = 0; pass < 2 && budget > 0.0 && b.items < kMaxItemsPerBatch;
@@ -625,9 +634,10 @@ int gf_server_create(const gf_server_config *cfg, gf_server_t **out)
         gf_server_destroy(s);
         return r;
     }
-    s->fill_items = 3LL * std::max(gf::serve_resident_waves(0, 1, 0, 0),
-                                   gf::serve_resident_waves(1, 1, 0, 0)) / 2;
-    s->fill_items = std::min<long long>(s->fill_items, kMaxItemsPerBatch);
+    const long long waves = std::max(gf::serve_resident_waves(0, 1, 0, 0),
+                                     gf::serve_resident_waves(1, 1, 0, 0));
+    s->fill_min = std::min<long long>(3 * waves / 2, kMaxItemsPerBatch);
+    s->fill_max = std::min<long long>(6 * waves, kMaxItemsPerBatch);
     s->arena.init(cfg->device_budget_bytes);
     for (int k = cfg->max_inflight - 1; k >= 0; --k) s->free_slots.push_back(k);
     s->worker = std::thread([s] { s->run(); });
