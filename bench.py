@@ -417,6 +417,11 @@ def main() -> int:
     if not args.skip_serving and args.config == "c1_fp64_1024sq":
         result["serving"] = serve_trace(gf, args.serve_requests, args.serve_rate,
                                         args.serve_budget)
+        # capacity: the same trace generator offered well above what the device sustains
+        cap = serve_trace(gf, 1500, 4000.0, args.serve_budget)
+        result["serving_capacity"] = {k: cap[k] for k in (
+            "requests", "arrival_rate_per_s", "completed", "throughput_req_per_s",
+            "nominal_evals_per_s", "batches", "latency_ms")}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(params, quad, grid, args.cpu_seconds)
     print(json.dumps(result), flush=True)
