@@ -185,9 +185,12 @@ __device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n,
     return w.hit;
 }
 
-__global__ void __launch_bounds__(256) obstruction_kernel(ScanArgs a, int n, double T, uint8_t *out)
+// One wave (one 8x8 tile) per workgroup: a tile walks one contour part (class
+// R) or three (ray classes), so a four-wave workgroup would hold the slots of
+// its finished waves until its slowest one ends.
+__global__ void __launch_bounds__(64) obstruction_kernel(ScanArgs a, int n, double T, uint8_t *out)
 {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;
     const int lane = threadIdx.x & 63;
     const int ia = (wave % a.tiles_a) * 8 + lane % 8;
@@ -230,7 +233,7 @@ hipError_t launch_yscan(const ScanArgs &a, double xr, double xi, double mu2, int
 hipError_t launch_obstruction(const ScanArgs &a, int n, double T, uint8_t *out, hipStream_t s)
 {
     if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(obstruction_kernel, dim3((a.n_tiles + 3) / 4), dim3(256), 0, s, a, n, T, out);
+    hipLaunchKernelGGL(obstruction_kernel, dim3(a.n_tiles), dim3(64), 0, s, a, n, T, out);
     return hipGetLastError();
 }
 
