@@ -276,10 +276,12 @@ int gf_cut_curve(const gf_params *params, double x_re, double x_im, int n, doubl
  *   bit 1: the contour the scan uses at x (the contour class rule; for a
  *          mirror point, the contour of conj x);
  *   bit 2: x has no contour (class SINGULAR; bit 1 is then 0).
- * A crossing is detected between consecutive samples of the contour (each
- * straight part at t = log(1+|y|) = T k/(n-1), k = 1..n-1, T = log(1 +
- * Lambda^2); the closing arc at n equally spaced angles) where Im zeta changes
- * sign and the linearly interpolated Re zeta lies in [0, 1].  Points with
+ * The contour is sampled (each straight part at t = log(1+|y|) = T k/(n-1),
+ * k = 1..n-1, T = log(1 + Lambda^2); the closing arc at n equally spaced
+ * angles); where Im zeta changes sign between consecutive samples, the sign
+ * change is located by 40 bisection steps on the contour parameter (t, or the
+ * arc angle), and a crossing is counted when Re zeta at the midpoint of the
+ * final interval lies in [0, 1].  Points with
  * bit 0 clear form the region where the real-axis contour is unharmed.  out:
  * caller-owned device memory, n_re * n_im bytes [n_im][n_re]; asynchronous on
  * `stream`.  n_samples in [2, 2^20].  Errors: GF_EINVAL (also for the grid

@@ -207,6 +207,8 @@ class Plan:
                                  ctypes.byref(pr) if pr is not None else None,
                                  ctypes.byref(c_quad(quad)), ctypes.byref(h)))
         self._h = h
+        #: the GPU the plan's tables live on (the current device at creation)
+        self.device = _current_device()
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -242,6 +244,27 @@ class Plan:
             pass
 
 
+def _check_out(t, dtype, n: int, device: int, name: str = "out"):
+    """Raises ValueError unless `t` is a contiguous tensor of `dtype` with `n`
+    elements on GPU `device`: the library writes through its raw address."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements (n_re * n_im), got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must be on GPU {device}, got {t.device}")
+
+
+def _current_device() -> int:
+    import torch
+    return torch.cuda.current_device()
+
+
 def empty_result(grid: Grid, device=None):
     import torch
     return torch.empty((grid.n_im, grid.n_re), dtype=torch.complex128,
@@ -252,13 +275,11 @@ def scan_plan(plan: Plan, grid: Grid, out=None, cls=None, lanes: int = 0, stream
     """Launches gf_scan_plan_ex; returns `out` (complex128 [n_im, n_re]),
     asynchronous on `stream` (default: torch's current stream)."""
     import torch
+    if cls is not None:
+        _check_out(cls, torch.int8, grid.n_points, plan.device, "cls")
     if out is None:
-        out = empty_result(grid)
-    if out.dtype != torch.complex128 or not out.is_contiguous() or out.numel() != grid.n_points:
-        raise ValueError("out must be a contiguous complex128 tensor with n_re * n_im elements")
-    if cls is not None and (cls.dtype != torch.int8 or not cls.is_contiguous()
-                            or cls.numel() != grid.n_points):
-        raise ValueError("cls must be a contiguous int8 tensor with n_re * n_im elements")
+        out = empty_result(grid, torch.device("cuda", plan.device))
+    _check_out(out, torch.complex128, grid.n_points, plan.device)
     _check(load().gf_scan_plan_ex(plan.handle, ctypes.byref(c_grid(grid)),
                                   ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
                                   ctypes.c_void_p(cls.data_ptr() if cls is not None else 0),
@@ -273,8 +294,10 @@ def yscan_plan(plan: Plan, x: complex, ygrid: Grid, what: int = YSCAN_ANGULAR, o
                stream=None):
     """y-plane diagnostic (gf_yscan_plan): <1/D1>(x, y) or the subtracted
     y-integrand on a grid of complex y; complex128 [n_im, n_re] on the device."""
+    import torch
     if out is None:
-        out = empty_result(ygrid)
+        out = empty_result(ygrid, torch.device("cuda", plan.device))
+    _check_out(out, torch.complex128, ygrid.n_points, plan.device)
     x = complex(x)
     _check(load().gf_yscan_plan(plan.handle, x.real, x.imag, ctypes.byref(c_grid(ygrid)), int(what),
                                 ctypes.c_void_p(out.data_ptr() if ygrid.n_points else 0),
@@ -301,8 +324,10 @@ def obstruction_map(params: Params, grid: Grid, n_samples: int = 4096, out=None,
     [0, Lambda^2]; bit 1: it crosses the contour the scan uses; bit 2: no
     contour (gf_obstruction_map).  uint8 [n_im, n_re] on the device."""
     import torch
+    dev = _current_device()
     if out is None:
-        out = torch.empty((grid.n_im, grid.n_re), dtype=torch.uint8, device="cuda")
+        out = torch.empty((grid.n_im, grid.n_re), dtype=torch.uint8, device=torch.device("cuda", dev))
+    _check_out(out, torch.uint8, grid.n_points, dev)
     _check(load().gf_obstruction_map(ctypes.byref(c_params(params)), ctypes.byref(c_grid(grid)),
                                      int(n_samples),
                                      ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
@@ -312,8 +337,11 @@ def obstruction_map(params: Params, grid: Grid, n_samples: int = 4096, out=None,
 
 def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
     """One-call scan (gf_scan): plan looked up in the library's cache."""
+    import torch
+    dev = _current_device()
     if out is None:
-        out = empty_result(grid)
+        out = empty_result(grid, torch.device("cuda", dev))
+    _check_out(out, torch.complex128, grid.n_points, dev)
     _check(load().gf_scan(ctypes.byref(c_params(params)), ctypes.byref(c_grid(grid)),
                           ctypes.byref(c_quad(quad)),
                           ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),

@@ -227,6 +227,19 @@ std::string key_angular(const gf_quadrature &q, const gf_params &p)
 }
 std::string key_arc(const gf_quadrature &q) { return "c" + std::to_string(q.n_arc); }
 
+// Arena bytes of a request's three node tables, as ensure_table builds them:
+// radial [r | sqrt r | W] (3 n_r doubles), angular pairs in FP64 then FP32
+// (3 max(n_a/2, 1) each), arc [xi | w] (2 n_arc doubles); each range is
+// rounded up to the arena's 256-byte granule.
+size_t table_bytes(const gf_quadrature &q)
+{
+    const size_t npair = (size_t)std::max(q.n_angular / 2, 1);
+    const size_t rad = 3 * (size_t)q.n_radial * sizeof(double);
+    const size_t ang = gf::align256(3 * npair * sizeof(double)) + 3 * npair * sizeof(float);
+    const size_t arc = 2 * (size_t)std::max(q.n_arc, 1) * sizeof(double);
+    return gf::align256(rad) + gf::align256(ang) + gf::align256(arc);
+}
+
 double nominal_evals_per_point(const gf_quadrature &q)
 {
     return (double)(q.n_radial + q.n_arc) * (double)q.n_angular;
@@ -312,29 +325,35 @@ bool gf_server::admit_one(Request *r, Stage &st, std::vector<Request *> &fresh,
         }
         if (!arena.alloc(r->out_bytes, &out_off)) return false;
     }
+    // Each table is pinned (refs raised) as soon as it is found or built, so
+    // that building the next one cannot evict it; every failure below unpins
+    // what this call pinned and returns the output range.
     Table *tb[3] = {nullptr, nullptr, nullptr};
+    auto undo = [&](int pinned) {
+        for (int k = 0; k < pinned; ++k) --tb[k]->refs;
+        arena.release(out_off, r->out_bytes);
+        return false;
+    };
     for (int k = 0; k < 3; ++k) {
         bool fits;
         tb[k] = ensure_table(r->keys[k], *r, &fits);
-        if (!fits) {
-            arena.release(out_off, r->out_bytes);
-            return false;
-        }
+        if (!fits) return undo(k);
+        ++tb[k]->refs;
     }
-    // staging space for new table contents
+    // staging space for new table contents: reserved for all of them before
+    // any is marked uploaded, so a failed admission stages nothing
+    size_t need = st.used;
+    for (int k = 0; k < 3; ++k)
+        if (!tb[k]->uploaded) need = gf::align256(need) + tb[k]->bytes;
+    if (need > st.bytes) return undo(3);
     for (int k = 0; k < 3; ++k) {
         if (tb[k]->uploaded) continue;
         size_t doff;
         void *h = st.bump(tb[k]->bytes, &doff);
-        if (!h) {
-            arena.release(out_off, r->out_bytes);
-            return false;
-        }
         std::memcpy(h, tb[k]->host.data(), tb[k]->bytes);
         uploads.push_back(Upload{doff, tb[k]->off, tb[k]->bytes});
         tb[k]->uploaded = true;
     }
-    for (int k = 0; k < 3; ++k) ++tb[k]->refs;
     r->out_off = out_off;
     r->slot = free_slots.back();
     free_slots.pop_back();
@@ -674,11 +693,16 @@ int gf_server_submit_ex(gf_server_t *s, const gf_params *params, const gf_propag
         r->has_props = true;
     }
     r->out_bytes = (size_t)grid->n_re * (size_t)grid->n_im * 16;
-    if (gf::align256(r->out_bytes) > s->arena.size()) {
+    // an idle server evicts every unreferenced table, so a request is
+    // admissible at some point exactly when its output and its own tables fit
+    // the arena together
+    const size_t need = gf::align256(r->out_bytes) + table_bytes(*quad);
+    if (need > s->arena.size()) {
         delete r;
         ++s->n_rejected;
-        return fail(GF_EBUDGET, "request output (%zu bytes) exceeds the device budget (%zu)",
-                    r->out_bytes, s->arena.size());
+        return fail(GF_EBUDGET,
+                    "request output and node tables (%zu bytes) exceed the device budget (%zu)",
+                    need, s->arena.size());
     }
     r->keys[0] = key_radial(*quad, *params);
     r->keys[1] = key_angular(*quad, *params);

@@ -150,6 +150,52 @@ def test_request_larger_than_budget_is_rejected():
         assert srv.stats()["rejected"] == 2
 
 
+def test_request_whose_tables_never_fit_is_rejected_at_submit():
+    """Output alone fits the 1 MiB arena, output plus its own node tables does
+    not (250^2 points = 1,000,000 bytes, 8192 radial nodes = 196,608 bytes):
+    rejected with GF_EBUDGET at submission instead of blocking the queue."""
+    with gf.Server(budget_bytes=1 << 20, max_inflight=4) as srv:
+        with pytest.raises(gf.GFError) as e:
+            srv.submit(Params(1.0, 1.0, 1.0, 1e6), Grid(250, 250, -8.0, 4.0, -4.0, 4.0),
+                       Quadrature(8192, 32, 16))
+        assert e.value.code == -5
+        # the same output with small tables is admitted and completes
+        t = srv.submit(Params(1.0, 1.0, 1.0, 1e6), Grid(250, 250, -8.0, 4.0, -4.0, 4.0),
+                       Quadrature(32, 32, 16))
+        assert srv.wait(t, WAIT_MS)
+
+
+def test_admission_evicts_only_unreferenced_tables():
+    """In a 1 MiB arena, request A (8192 x 8192 + 1024 nodes) runs and is
+    released; its tables stay cached (360,448 bytes, unreferenced).  Request B
+    brings three new tables and an output sized so that they cannot all sit
+    beside A's tables: placing one of B's later tables evicts unreferenced
+    tables, and must evict A's, never a table B has already placed.  B's
+    result is bitwise equal to its standalone scan."""
+    p = Params(1.0, 1.0, 1.0, 1e6)
+    qa = Quadrature(8192, 8192, 1024)
+    qb = Quadrature(4096, 4096, 512)
+    ga = Grid(64, 64, -8.0, 4.0, -4.0, 4.0)
+    gb = Grid(200, 160, -8.0, 4.0, -4.0, 4.0)  # 512,000 bytes of output
+    budget = 1 << 20
+    tables_a = 3 * 8192 * 8 + (3 * 4096 * 8 + 3 * 4096 * 4) + 2 * 1024 * 8
+    rad_b, ang_b, arc_b = 3 * 4096 * 8, 3 * 2048 * 8 + 3 * 2048 * 4, 2 * 512 * 8
+    free = budget - tables_a
+    assert 16 * gb.n_points + rad_b + ang_b <= free < 16 * gb.n_points + rad_b + ang_b + arc_b
+    with gf.Server(budget_bytes=budget, max_inflight=4) as srv:
+        ta = srv.submit(p, ga, qa)
+        assert srv.wait(ta, WAIT_MS)
+        srv.release(ta)
+        tb = srv.submit(p, gb, qb)
+        assert srv.wait(tb, WAIT_MS)
+        got = srv.result(tb)
+        srv.release(tb)
+        assert srv.stats()["bytes_peak"] <= budget
+    from types import SimpleNamespace
+    ref = _standalone(SimpleNamespace(params=p, quad=qb, grid=gb))
+    assert np.array_equal(got.view(np.float64), ref.view(np.float64), equal_nan=True)
+
+
 def test_poisson_trace_replay_reports_latency():
     """A seeded Poisson trace of 300 requests replayed in real time (results
     released as they complete): all complete; latency percentiles are ordered."""
