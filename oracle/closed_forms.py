@@ -218,3 +218,143 @@ def angular_continuum(u: complex, v: complex) -> complex:
     if abs(u + s) < abs(u - s):
         s = -s
     return complex(2 / (u + s))
+
+
+# ---------------------------------------------------------------- complex masses
+
+def _delta_roots(x: complex, m1sq: complex, m2sq: complex):
+    """The two roots in a of Delta(a, x) = -x a^2 + (x + m1^2 - m2^2) a + m2^2
+    (x != 0): a^2 - b a - c = 0 with b = 1 + (m1^2 - m2^2)/x, c = m2^2/x; the
+    larger root from the quadratic formula, the other from the product -c."""
+    b = 1.0 + (m1sq - m2sq) / x
+    c = m2sq / x
+    s = np.sqrt(b * b + 4.0 * c + 0j)
+    q = 0.5 * (b + s) if abs(b + s) >= abs(b - s) else 0.5 * (b - s)
+    return q, -c / q
+
+
+def _log_ratio_principal(a):
+    """Log(1 - a) - Log(-a): equals int_0^1 da'/(a' - a) along the straight
+    segment, analytic in a off [0, 1], where it jumps by 2 pi i."""
+    return mp.log(1 - a) - mp.log(-a)
+
+
+def _segment_crossing(a0: complex, a1: complex):
+    """+1 if the straight step a0 -> a1 crosses the open segment (0, 1) from
+    above, -1 from below, 0 if it does not cross it; None if the crossing
+    lies too close to an end point to decide (the caller refines the step)."""
+    if (a0.imag > 0) == (a1.imag > 0) or a0.imag == a1.imag:
+        return 0
+    t = a0.imag / (a0.imag - a1.imag)
+    re = a0.real + t * (a1.real - a0.real)
+    step = abs(a1 - a0)
+    if abs(re) < 2 * step or abs(re - 1) < 2 * step:
+        return None
+    if 0 < re < 1:
+        return 1 if a0.imag > 0 else -1
+    return 0
+
+
+def _straight_path_ok(s: complex, m1sq: complex, m2sq: complex, n: int = 4001) -> bool:
+    a = np.linspace(0.0, 1.0, n)
+    d = delta(a, s, m1sq, m2sq)
+    cross = np.nonzero((np.sign(d.imag[1:]) * np.sign(d.imag[:-1]) < 0)
+                       & ((d.real[1:] < 0) | (d.real[:-1] < 0)))[0]
+    return cross.size == 0 and not np.any((np.abs(d.imag) < 1e-15) & (d.real <= 0))
+
+
+def feynman_continued(x: complex, m1sq: complex, m2sq: complex, mu2: float,
+                      base: float | None = None, steps: int = 4000) -> complex:
+    """The subtracted bubble int_0^1 [log Delta(a, mu^2) - log Delta(a, x)] da
+    analytically continued in x for complex masses, where the principal-log
+    form of `feynman` is not the analytic function.
+
+    With the roots a_1, a_2 of Delta(a, x) = 0, integrating by parts gives
+
+        F(x) = int_C log Delta(a, x) da = Log m2^2 - 2 + sum_i (1 - a_i) L(a_i),
+        L(a) = int_C da' / (a' - a),
+
+    for an a-contour C from 0 to 1 (log Delta continued along C from its
+    principal value at a = 0, where Delta = m2^2).  The continuation in x
+    deforms C so that each root stays on the side of C it occupied at a base
+    point x0 on the positive real axis, where the straight segment is valid:
+    then L(a_i) is Log(1 - a_i) - Log(-a_i) plus 2 pi i times the number of
+    times the root has crossed the segment (0, 1) from above, minus those
+    from below.  The roots are followed along the path x0 -> x: the circle
+    |x'| = x0 from angle 0 to arg x, then the ray to x (so the path stays in
+    x's half plane and away from x = 0, where one root runs off to infinity).
+    The result is
+
+        G(x) = F_straight(mu^2) - F(x),
+
+    with the subtraction term on the straight segment (mu^2 is real).  Thus G
+    is the continuation through x's half plane from the real axis right of the
+    cut, the continuation the contour classes of the quadrature follow.  For
+    real masses it equals `feynman` off the real axis."""
+    x = complex(x)
+    m1 = complex(m1sq)
+    m2 = complex(m2sq)
+    if base is None:
+        base = max(1.0, float(mu2))
+        while not _straight_path_ok(base, m1, m2):
+            base *= 2.0
+            if base > 1e8:
+                raise ValueError("no base point on the positive real axis")
+    r0 = float(base)
+    theta = float(np.angle(x))
+    # path samples: arc then ray (both parametrised uniformly)
+    n_arc = max(2, int(steps * abs(theta) / np.pi) + 2)
+    n_ray = max(2, int(steps * abs(np.log(abs(x) / r0))) + 2)
+    path = [r0 * np.exp(1j * theta * k / (n_arc - 1)) for k in range(n_arc)]
+    ray = np.exp(1j * theta)
+    lo, hi = np.log(r0), np.log(abs(x))
+    path += [np.exp(lo + (hi - lo) * k / (n_ray - 1)) * ray for k in range(1, n_ray)]
+    path[-1] = x
+    roots = list(_delta_roots(complex(path[0]), m1, m2))
+    wind = [0, 0]
+
+    def advance(xa: complex, xb: complex, ra, depth=0):
+        nb = _delta_roots(xb, m1, m2)
+        # match the new roots to the old ones by proximity
+        if abs(nb[0] - ra[0]) + abs(nb[1] - ra[1]) > abs(nb[1] - ra[0]) + abs(nb[0] - ra[1]):
+            nb = (nb[1], nb[0])
+        big = max(abs(nb[i] - ra[i]) / (1e-3 + min(abs(ra[i]), abs(ra[i] - 1))) for i in (0, 1))
+        cr = [_segment_crossing(ra[i], nb[i]) for i in (0, 1)]
+        if (big > 0.05 or None in cr) and depth < 40:
+            xm = 0.5 * (xa + xb)
+            rm = advance(xa, xm, ra, depth + 1)
+            return advance(xm, xb, rm, depth + 1)
+        if None in cr:
+            raise ValueError(f"a root of Delta passes through an end point near x = {xb}")
+        for i in (0, 1):
+            wind[i] += cr[i]
+        return list(nb)
+
+    for k in range(1, len(path)):
+        roots = advance(complex(path[k - 1]), complex(path[k]), roots)
+
+    mp_m2 = mp.mpc(m2)
+    F = mp.log(mp_m2) - 2
+    for a, w in zip(roots, wind):
+        a = mp.mpc(a)
+        F += (1 - a) * (_log_ratio_principal(a) + 2j * mp.pi * w)
+    mu = mp.mpf(mu2)
+    m1m = mp.mpc(m1)
+    Fmu = mp.quad(lambda a: mp.log(delta(a, mu, m1m, mp_m2)), _split_points(mu, m1m, mp_m2))
+    return complex(Fmu - F)
+
+
+def _split_points(s, m1, m2):
+    pts = [mp.mpf(0), mp.mpf(1)]
+    b = m1 - m2 + s
+    if s != 0:
+        disc = mp.sqrt(b * b + 4 * s * m2)
+        roots = [(b + disc) / (2 * s), (b - disc) / (2 * s)]
+    elif b != 0:
+        roots = [-m2 / b]
+    else:
+        roots = []
+    for r in roots:
+        if 0 < mp.re(r) < 1:
+            pts.append(mp.re(r))
+    return sorted(set(pts))

@@ -253,12 +253,18 @@ static cplx angular_d1(cplx x, cplx y, cplx sxsy, cplx m1sq, int n,
 {
     cplx acc = 0.0;
     double a = 0.0;
+    /* |x + y + m1^2| and |2 sqrt(x) sqrt(y)| do not depend on j, and
+     * |w_j / D1_j| = |w_j| / |D1_j| */
+    const double u_abs = absum ? cabs(x + y + m1sq) : 0.0;
+    const double v_abs = absum ? cabs(2.0 * sxsy) : 0.0;
     for (int j = 0; j < n; ++j) {
         cplx d1 = x + y - 2.0 * sxsy * z[j] + m1sq;
         cplx t = w[j] / d1;
         acc += t;
-        if (absum)
-            a += cabs(t) * (1.0 + (cabs(x + y + m1sq) + cabs(2.0 * sxsy * z[j])) / cabs(d1));
+        if (absum) {
+            const double dabs = sqrt(creal(d1) * creal(d1) + cimag(d1) * cimag(d1));
+            a += fabs(w[j]) / dabs * (1.0 + (u_abs + v_abs * fabs(z[j])) / dabs);
+        }
     }
     if (absum) *absum += a;
     return acc;

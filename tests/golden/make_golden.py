@@ -7,6 +7,10 @@ Calls only the analytic references in `oracle.closed_forms` (40-digit mpmath):
                           at points of the paper's display box (+-5, STEP 4)
 * feynman_points.json  -- Feynman-parameter form of the subtracted bubble for
                           the real, unequal and conjugate-pair mass cases
+                          (principal logs where they give the analytic
+                          function), and for the conjugate pair in the wedge
+                          where they do not (`feynman_continued`: the a-contour
+                          deformed so the roots of Delta keep their side)
 
 Run:  python tests/golden/make_golden.py
 """
@@ -38,6 +42,15 @@ FEYNMAN_CASES = {
 }
 
 
+# conjugate pair m^2 = 1 +- 0.5i, mu^2 = 1: points of the complex-mass
+# workload's box where Delta(a, x) crosses the negative real axis for some a
+# in [0, 1], so the principal-log form is not the analytic function (|x| <= 9,
+# where the next cutoff term is below the pin's 5e-11 at Lambda^2 = 1e4)
+WEDGE_CASE = ("conjugate_1_pm_0p5i_mu2_1_wedge", 1 + 0.5j, 1 - 0.5j, 1.0,
+              [-5 + 0.5j, -5 - 0.5j, -4.5 + 0.2j, -7 + 0.1j, -9 - 1j, -6 + 1.5j, -8 + 0.6j,
+               -5.5 - 0.05j, -4.3 + 0.01j])
+
+
 def main():
     eq18 = {
         "source": "eq. 18 (exact subtracted, rescaled correlator of the worked example, "
@@ -60,6 +73,15 @@ def main():
         m1, m2 = complex(c["m1sq"]), complex(c["m2sq"])
         fey["cases"][name] = {"m1sq": [m1.real, m1.imag], "m2sq": [m2.real, m2.imag],
                               "mu2": c["mu2"], "points": pts}
+    name, m1, m2, mu2, points = WEDGE_CASE
+    pts = []
+    for x in points:
+        if cf.feynman_principal_ok(x, m1, m2, mu2):
+            raise SystemExit(f"{name}: {x} is not in the wedge")
+        g = cf.feynman_continued(x, m1, m2, mu2)
+        pts.append([x.real, x.imag, g.real, g.imag])
+    fey["cases"][name] = {"m1sq": [m1.real, m1.imag], "m2sq": [m2.real, m2.imag], "mu2": mu2,
+                          "form": "continued", "points": pts}
     with open(os.path.join(HERE, "feynman_points.json"), "w") as f:
         json.dump(fey, f, indent=1)
 

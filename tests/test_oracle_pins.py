@@ -204,14 +204,20 @@ def _load_feynman():
 
 
 @pytest.mark.parametrize("case", ["equal_m1_m2_1_mu2_1", "unequal_m1_1_m2_0p5_mu2_2",
-                                  "conjugate_1_pm_0p5i_mu2_1"])
+                                  "conjugate_1_pm_0p5i_mu2_1", "conjugate_1_pm_0p5i_mu2_1_wedge"])
 def test_oracle_matches_feynman_closed_form(case):
     """P2: the quadrature converges to the Feynman-parameter form plus the
     cutoff bias (x - mu^2) m1^2 / (2 Lambda^4).  Lambda^2 = 1e4 makes the bias
-    (~1e-8) visible, so dropping it fails."""
+    (~1e-8) visible, so dropping it fails.  The wedge case is the conjugate
+    pair of the complex-mass workload where the principal-log form is not the
+    analytic function; its reference is the continued form (roots of Delta
+    kept on their side of the a-contour)."""
     c = _load_feynman()[case]
     m1 = complex(*c["m1sq"])
     m2 = complex(*c["m2sq"])
+    if c.get("form") == "continued":
+        for pt in c["points"]:
+            assert not cf.feynman_principal_ok(complex(pt[0], pt[1]), m1, m2, c["mu2"])
     p = Params(m1, m2, c["mu2"], 1e4, 1.0)
     q = Quadrature(1024, 512, 32)
     xs = np.array([pt[0] + 1j * pt[1] for pt in c["points"]])
@@ -225,6 +231,46 @@ def test_oracle_matches_feynman_closed_form(case):
         assert abs(gg - (rr + bias)) < 5e-11, (x, cl, abs(gg - rr - bias))
         if abs(bias) > 5e-9:
             assert abs(gg - rr) > 1e-10
+
+
+def test_golden_continued_feynman_values_match_formula():
+    """The stored wedge values re-evaluate to themselves (fixture integrity)."""
+    c = _load_feynman()["conjugate_1_pm_0p5i_mu2_1_wedge"]
+    for xr, xi, gr, gi in c["points"][:3]:
+        g = cf.feynman_continued(complex(xr, xi), complex(*c["m1sq"]), complex(*c["m2sq"]),
+                                 c["mu2"])
+        assert abs(g - complex(gr, gi)) < 1e-14 * max(1.0, abs(g))
+
+
+def test_continued_feynman_equals_principal_form_where_that_is_analytic():
+    """The continued Feynman form (a-contour deformed around the roots of
+    Delta) against the straight-segment principal-log form wherever the latter
+    is the analytic function: real masses off the real axis, and the conjugate
+    pair outside the wedge."""
+    cases = [(1.0, 1.0, 1.0, [2 + 3j, -3 + 2j, -6 + 3j, 0.5 + 0.3j, -7.9 - 3.9j, -1.5 - 0.01j]),
+             (1.0, 0.25, 2.0, [-5 + 3j, 1.2 - 1.7j, -0.2 + 0.2j, -3 - 0.02j]),
+             (1 + 0.5j, 1 - 0.5j, 1.0, [2 + 3j, 0.5 + 0.3j, 4 - 4j, 0.1 + 2j, -6 - 2.5j])]
+    for m1, m2, mu2, pts in cases:
+        for x in pts:
+            assert cf.feynman_principal_ok(x, m1, m2, mu2)
+            assert abs(cf.feynman_continued(x, m1, m2, mu2) - cf.feynman(x, m1, m2, mu2)) < 1e-13
+
+
+def test_continued_feynman_reproduces_eq18_on_the_whole_box():
+    """P3 for the reference itself: with the paper's masses (m1^2 = -i/2,
+    m2^2 = +i/2, mu^2 = 0) the continued Feynman form equals eq. 18 on a 6 x 6
+    grid of the paper's +-5 box, both half planes, although the principal-log
+    form is wrong on most of the left half plane."""
+    re = np.linspace(-4.6, 4.6, 6)
+    im = np.array([-4.1, -2.3, -0.07, 0.07, 2.3, 4.1])
+    wrong = 0
+    for a in re:
+        for b in im:
+            x = complex(a, b)
+            g = cf.feynman_continued(x, -0.5j, 0.5j, 0.0)
+            assert abs(g - cf.eq18(x)) < 1e-13 * max(1.0, abs(g)), x
+            wrong += abs(cf.feynman(x, -0.5j, 0.5j, 0.0) - cf.eq18(x)) > 0.1
+    assert wrong >= 8
 
 
 def test_cutoff_convergence_rate():
