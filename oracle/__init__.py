@@ -242,11 +242,11 @@ def scan(params, quad, grid, want_cond: bool = False, props=None):
 
 
 def eval_points_q(params, quad, x):
-    """Quad-precision brute force of the same quadrature (Gauss-Chebyshev II
-    angular rule only).  Returns (g, cls)."""
-    if (getattr(quad, "angular_rule", 0) != 0 or getattr(params, "taylor_order", 0) != 0
-            or getattr(params, "dimension", 4) not in (0, 4) or getattr(quad, "radial_split", 0)):
-        raise ValueError("the quad-precision twin implements GC-II, t^0, D = 4, unsplit only")
+    """Quad-precision brute force of the same quadrature (every angular rule,
+    Taylor order and dimension; single poles, unsplit radial rule).  Returns
+    (g, cls)."""
+    if getattr(quad, "radial_split", 0):
+        raise ValueError("the quad-precision twin implements the unsplit radial rule only")
     lib = _loadq()
     x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
     xr = np.ascontiguousarray(x.real)
@@ -254,7 +254,8 @@ def eval_points_q(params, quad, x):
     g = np.zeros(2 * x.size)
     cls = ctypes.create_string_buffer(max(x.size, 1))
     pr = problem(params, quad)
-    lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls)
+    if lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls) != 0:
+        raise ValueError("the quad-precision twin rejected the problem")
     return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
 
 

@@ -21,9 +21,9 @@ typedef struct {
     double m1sq_re, m1sq_im, m2sq_re, m2sq_im;
     double mu2, lambda2, scale;
     int n_radial, n_angular, n_arc;
-    int angular_rule;   /* only 0 (Gauss-Chebyshev II) is implemented here */
-    int taylor_order;   /* only 0 is implemented here */
-    int dimension;      /* only 4 (or 0) is implemented here */
+    int angular_rule;   /* 0 GC-II, 1 GC-I, 2 tanh-sinh, 3 Gauss-Legendre */
+    int taylor_order;   /* n of t^n, -1..8 */
+    int dimension;      /* 2, 3, 4 (0 = 4) */
     int radial_split;   /* only 0 is implemented here */
     int n1, n2;         /* only 0 (single poles) is implemented here */
     double p1[32], p2[32];
@@ -73,17 +73,57 @@ static void q_gauss_legendre(int n, qr *x, qr *w)
     }
 }
 
-/* sum_j w_j / (x + y + m1^2 - 2 sxsy z_j), GC-II of order n */
-static qc q_angular(qc x, qc y, qc sxsy, qc m1sq, int n)
+/* The angular rule for the normalised D-dimensional angular measure
+ * (1 - z^2)^{(D-3)/2} dz / N_D, N_D = pi, 2, pi/2 for D = 2, 3, 4: each rule
+ * integrates g against its own weight omega(z) and is applied to
+ * g = f (1 - z^2)^{(D-3)/2} / omega.  Gauss-Chebyshev II (omega = sqrt(1-z^2),
+ * z = cos(j pi/(n+1))), Gauss-Chebyshev I (omega = 1/sqrt(1-z^2),
+ * z = cos((2j-1) pi/(2n))), tanh-sinh (z = tanh((pi/2) sinh t) on n
+ * equispaced t in [-t_max, t_max], t_max = 3, 3.5, 4 for D = 4, 3, 2),
+ * Gauss-Legendre (omega = 1).  Returns -1 for an unknown rule. */
+static int q_angular_rule(int rule, int dim, int n, qr *z, qr *w)
+{
+    const qr norm = dim == 2 ? QPI : (dim == 3 ? 2 : QPI / 2);
+    const qr ex = (qr)(dim - 3) / 2;   /* exponent of (1 - z^2) in the measure */
+    if (rule == 0 || rule == 1) {
+        for (int j = 1; j <= n; ++j) {
+            qr th = rule == 0 ? j * QPI / (n + 1) : (2 * j - 1) * QPI / (2 * n);
+            qr s = sinq(th);
+            z[j - 1] = cosq(th);
+            /* omega^-1 (1-z^2)^ex = sin^{D-4} (GC-II) or sin^{D-2} (GC-I), times
+             * the rule's own weight pi/(n+1) sin^2 or pi/n */
+            w[j - 1] = (rule == 0 ? QPI / (n + 1) * s * s * powq(s, dim - 4)
+                                  : QPI / n * powq(s, dim - 2)) / norm;
+        }
+        return 0;
+    }
+    if (rule == 2) {
+        if (n < 3) return -1;
+        const qr tmax = dim == 4 ? 3 : (dim == 3 ? 3.5Q : 4);
+        const qr h = 2 * tmax / (n - 1);
+        for (int k = 0; k < n; ++k) {
+            qr t = (k - (n - 1) / 2.0Q) * h;
+            qr u = QPI / 2 * sinhq(t);
+            qr cu = coshq(u);
+            z[k] = tanhq(u);
+            /* dz = (pi/2) cosh t / cosh^2 u dt, 1 - z^2 = 1/cosh^2 u */
+            w[k] = h * QPI / 2 * coshq(t) / (cu * cu) * powq(cu, -2 * ex) / norm;
+        }
+        return 0;
+    }
+    if (rule == 3) {
+        q_gauss_legendre(n, z, w);
+        for (int k = 0; k < n; ++k) w[k] = w[k] * powq(1 - z[k] * z[k], ex) / norm;
+        return 0;
+    }
+    return -1;
+}
+
+/* sum_j w_j / (x + y + m1^2 - 2 sxsy z_j) with the problem's angular rule */
+static qc q_angular(qc x, qc y, qc sxsy, qc m1sq, int n, const qr *z, const qr *w)
 {
     qc acc = 0;
-    for (int j = 1; j <= n; ++j) {
-        qr th = j * QPI / (n + 1);
-        qr s = sinq(th);
-        qr z = cosq(th);
-        qr w = 2 * s * s / (n + 1);
-        acc += w / (x + y - 2 * sxsy * z + m1sq);
-    }
+    for (int j = 0; j < n; ++j) acc += w[j] / (x + y - 2 * sxsy * z[j] + m1sq);
     return acc;
 }
 
@@ -95,8 +135,10 @@ typedef struct {
     qc m1sq, m2sq;
     qr beta1, beta2, lo, hi, vstar;
     int mirror_ok;
-    qr *r, *wr, *ax, *aw;
+    qr *r, *wr, *ax, *aw, *az, *azw;
+    int dim;
     qc jmu;
+    qc taylor[9];   /* K_0..K_n of the subtraction at mu^2 */
 } qctx;
 
 static qr q_angdist(qr a, qr b)
@@ -139,16 +181,24 @@ static int q_classify(const qctx *c, qc x, int *sign)
     return rot;
 }
 
+/* y^{(D-2)/2} with the square root continued along the contour from y = 0:
+ * on the ray y = e^{i phi} r it is e^{i phi/2} sqrt(r), |phi| < pi */
+static qc q_ypow(int dim, qc y)
+{
+    return dim == 4 ? y : (dim == 3 ? csqrtq(y) : mkc(1, 0));
+}
+
 static qc q_contour(const qctx *c, qc x, int cls, int sign)
 {
     const orcq_problem *p = c->p;
+    const int na = p->n_angular;
     qc sx = csqrtq(x);
     qc s = 0;
     if (cls == Q_R) {
         for (int i = 0; i < p->n_radial; ++i) {
             qc y = mkc(c->r[i], 0);
-            qc a = q_angular(x, y, sx * sqrtq(c->r[i]), c->m1sq, p->n_angular);
-            s += c->wr[i] * y / (y + c->m2sq) * a;
+            qc a = q_angular(x, y, sx * sqrtq(c->r[i]), c->m1sq, na, c->az, c->azw);
+            s += c->wr[i] * q_ypow(c->dim, y) / (y + c->m2sq) * a;
         }
         return s;
     }
@@ -157,24 +207,71 @@ static qc q_contour(const qctx *c, qc x, int cls, int sign)
     qc eh = mkc(cosq(phi / 2), sinq(phi / 2));
     for (int i = 0; i < p->n_radial; ++i) {
         qc y = e * c->r[i];
-        qc a = q_angular(x, y, sx * eh * sqrtq(c->r[i]), c->m1sq, p->n_angular);
-        s += e * c->wr[i] * y / (y + c->m2sq) * a;
+        qc a = q_angular(x, y, sx * eh * sqrtq(c->r[i]), c->m1sq, na, c->az, c->azw);
+        s += e * c->wr[i] * q_ypow(c->dim, y) / (y + c->m2sq) * a;
     }
     qr L2 = p->lambda2, L = sqrtq(L2);
     for (int k = 0; k < p->n_arc; ++k) {
         qr psi = phi * (1 - c->ax[k]) / 2;
         qc y = L2 * mkc(cosq(psi), sinq(psi));
         qc sy = L * mkc(cosq(psi / 2), sinq(psi / 2));
-        qc a = q_angular(x, y, sx * sy, c->m1sq, p->n_angular);
+        qc a = q_angular(x, y, sx * sy, c->m1sq, na, c->az, c->azw);
         qc dy = mkc(0, -1) * y * (phi / 2) * c->aw[k];
-        s += dy * y / (y + c->m2sq) * a;
+        s += dy * q_ypow(c->dim, y) / (y + c->m2sq) * a;
     }
     if (cls == Q_YRES) {
         qc y0 = -c->m2sq;
-        qc a = q_angular(x, y0, sx * csqrtq(y0), c->m1sq, p->n_angular);
-        s += sign * 2 * QPI * mkc(0, 1) * y0 * a;
+        qc a = q_angular(x, y0, sx * csqrtq(y0), c->m1sq, na, c->az, c->azw);
+        s += sign * 2 * QPI * mkc(0, 1) * q_ypow(c->dim, y0) * a;
     }
     return s;
+}
+
+/* Taylor coefficients K_1..K_n of the real-axis sum S(x) about mu^2 by
+ * Cauchy's formula, trapezoidal rule on 64 points of the circle of radius half
+ * the distance from mu^2 to the nearest x where a node's first propagator
+ * vanishes (aliasing below 2^-64 of the coefficients' size). */
+static void q_taylor(qctx *c)
+{
+    const orcq_problem *p = c->p;
+    const int n = p->taylor_order;
+    qr dmin = 1e300Q;
+    for (int i = 0; i < p->n_radial; ++i) {
+        qr sy = sqrtq(c->r[i]);
+        for (int j = 0; j < p->n_angular; ++j) {
+            qc root = csqrtq(c->r[i] * c->az[j] * c->az[j] - c->r[i] - c->m1sq);
+            qc s1 = sy * c->az[j] + root, s2 = sy * c->az[j] - root;
+            qr d1 = cabsq(s1 * s1 - p->mu2), d2 = cabsq(s2 * s2 - p->mu2);
+            if (d1 < dmin) dmin = d1;
+            if (d2 < dmin) dmin = d2;
+        }
+    }
+    const qr rho = dmin / 2;
+    const int N = 64;
+    for (int i = 1; i <= n; ++i) c->taylor[i] = 0;
+    for (int k = 0; k < N; ++k) {
+        qc e = mkc(cosq(2 * QPI * k / N), sinq(2 * QPI * k / N));
+        qc S = q_contour(c, p->mu2 + rho * e, Q_R, 0);
+        qc pw = 1;
+        for (int i = 1; i <= n; ++i) {
+            pw *= rho * e;
+            c->taylor[i] += S / pw / N;
+        }
+    }
+}
+
+/* The subtracted sum at the evaluated point xe (conj x for a mirror point):
+ * S(xe) - sum_{i=0}^{n} (xe - mu^2)^i K_i (nothing for n = -1). */
+static qc q_subtracted(const qctx *c, qc xe, qc S)
+{
+    const int n = c->p->taylor_order;
+    if (n < 0) return S;
+    qc sub = c->jmu, d = xe - c->p->mu2, pw = 1;
+    for (int i = 1; i <= n; ++i) {
+        pw *= d;
+        sub += pw * c->taylor[i];
+    }
+    return S - sub;
 }
 
 /* G at n points in quad precision, rounded to double on output (g: 2n doubles). */
@@ -198,7 +295,19 @@ int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const do
     c.vstar = crealq(csqrtq(c.m1sq));
     c.mirror_ok = (p->m1sq_im == 0 && p->m2sq_im == 0) ||
                   (p->m1sq_re == p->m2sq_re && p->m1sq_im == -p->m2sq_im);
+    if (p->radial_split || p->n1 > 1 || p->n2 > 1 || p->taylor_order < -1 ||
+        p->taylor_order > 8)
+        return -1;
+    c.dim = p->dimension == 0 ? 4 : p->dimension;
+    if (c.dim < 2 || c.dim > 4) return -1;
     int nr = p->n_radial, nc = p->n_arc > 0 ? p->n_arc : 1;
+    c.az = malloc(sizeof(qr) * p->n_angular);
+    c.azw = malloc(sizeof(qr) * p->n_angular);
+    if (q_angular_rule(p->angular_rule, c.dim, p->n_angular, c.az, c.azw) != 0) {
+        free(c.az);
+        free(c.azw);
+        return -1;
+    }
     qr *t = malloc(sizeof(qr) * nr), *tw = malloc(sizeof(qr) * nr);
     c.r = malloc(sizeof(qr) * nr);
     c.wr = malloc(sizeof(qr) * nr);
@@ -213,6 +322,7 @@ int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const do
         c.wr[i] = T / 2 * tw[i] * (1 + c.r[i]);
     }
     c.jmu = q_contour(&c, mkc(p->mu2, 0), Q_R, 0);
+    if (p->taylor_order > 0) q_taylor(&c);
 #pragma omp parallel for schedule(dynamic, 1)
     for (long k = 0; k < n; ++k) {
         qc x = mkc(x_re[k], x_im[k]);
@@ -229,15 +339,15 @@ int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const do
                 gk = mkc(NAN, NAN);
                 cl = Q_SINGULAR;
             } else {
-                gk = conjq((qr)p->scale * (q_contour(&c, xb, cb, sb) - c.jmu));
+                gk = conjq((qr)p->scale * q_subtracted(&c, xb, q_contour(&c, xb, cb, sb)));
             }
         } else {
-            gk = (qr)p->scale * (q_contour(&c, x, cl, sign) - c.jmu);
+            gk = (qr)p->scale * q_subtracted(&c, x, q_contour(&c, x, cl, sign));
         }
         g[2 * k] = (double)crealq(gk);
         g[2 * k + 1] = (double)cimagq(gk);
         if (cls) cls[k] = (signed char)cl;
     }
-    free(t); free(tw); free(c.r); free(c.wr); free(c.ax); free(c.aw);
+    free(t); free(tw); free(c.r); free(c.wr); free(c.ax); free(c.aw); free(c.az); free(c.azw);
     return 0;
 }

@@ -32,7 +32,8 @@ struct gf_plan {
 namespace gf {
 
 namespace {
-thread_local std::string g_error;
+// fixed-size so that recording an error never allocates
+thread_local char g_error[512];
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -74,12 +75,10 @@ int tiles_for(const gf_grid &g, int lanes, int *tiles_a, long long *n_tiles)
 
 int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    std::vsnprintf(g_error, sizeof(g_error), fmt, ap);
     va_end(ap);
-    g_error = buf;
     return code;
 }
 
@@ -88,7 +87,7 @@ int hip_fail(hipError_t e, const char *what)
     return fail(GF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-const char *last_error() { return g_error.c_str(); }
+const char *last_error() { return g_error; }
 
 // n-point Gauss-Legendre rule on [-1, 1], ascending nodes.  The positive
 // roots are found by Newton's method from Tricomi's asymptotic estimate and
@@ -231,18 +230,29 @@ void arc_table(int nc, std::vector<double> &arc)
 
 namespace {
 
-// A propagator as a multiset of (m^2 re, m^2 im, c re, c im), optionally conjugated.
-std::vector<std::array<double, 4>> pole_set(const double *p, int n, bool conj)
-{
-    std::vector<std::array<double, 4>> v;
-    for (int k = 0; k < n; ++k) {
-        const double s = conj ? -1.0 : 1.0;
-        // + 0.0 turns -0.0 into +0.0 so that equal values compare equal
-        v.push_back({p[4 * k] + 0.0, s * p[4 * k + 1] + 0.0, p[4 * k + 2] + 0.0,
-                     s * p[4 * k + 3] + 0.0});
+// A propagator as a multiset of (m^2 re, m^2 im, c re, c im), optionally
+// conjugated: the first n entries, sorted (a fixed-size array, no allocation).
+struct PoleSet {
+    std::array<std::array<double, 4>, GF_MAX_POLES> v{};
+    int n = 0;
+    bool operator==(const PoleSet &o) const
+    {
+        return n == o.n && std::equal(v.begin(), v.begin() + n, o.v.begin());
     }
-    std::sort(v.begin(), v.end());
-    return v;
+};
+
+PoleSet pole_set(const double *p, int n, bool conj)
+{
+    PoleSet s;
+    s.n = n;
+    for (int k = 0; k < n; ++k) {
+        const double c = conj ? -1.0 : 1.0;
+        // + 0.0 turns -0.0 into +0.0 so that equal values compare equal
+        s.v[k] = {p[4 * k] + 0.0, c * p[4 * k + 1] + 0.0, p[4 * k + 2] + 0.0,
+                  c * p[4 * k + 3] + 0.0};
+    }
+    std::sort(s.v.begin(), s.v.begin() + n);
+    return s;
 }
 
 }  // namespace

@@ -1,16 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle, element
 by element on the same cell-centred grid points (GPU tests, MI355X).
 
-Tolerance (FP64 path).  Per point the oracle also returns a condition
-number kappa: the sum over every term of the quadrature (each w_j / D over every
-contour node, times its node coefficient, and the subtraction sum) of
-|term| times the term's first-order sensitivity to relative perturbations of
-its inputs (1 + (|U| + |V z|)/|D| + |y|/|y + m2^2|), divided by |G|.  Two FP64
-evaluations of the same quadrature whose inputs and operations are each
-accurate to a few ulp (the GPU computes sqrt, sincos and the reciprocal with
-its own, equally accurate, routines) differ by at most c * eps * kappa * |G|,
-eps = 2^-53, c = 64.  The stated target, 1e-12 relative, is required
-wherever kappa <= 1e3.
+Bars (parity_bars): FP64 within max(1e-12 |G|, 64 eps kappa |G|) everywhere
+and 1e-12 relative wherever the oracle's condition number kappa <= 1e3 (the
+GPU computes sqrt, sincos and the reciprocal with its own, equally accurate,
+routines), with at most 3 % of the points of the named workloads above
+kappa = 1e3; FP32C within 1e-6 max(|G|, 1) at every point.
 """
 import math
 
@@ -22,6 +17,7 @@ torch = pytest.importorskip("torch")
 import oracle  # noqa: E402
 import paper_1205_0752_amd as gf  # noqa: E402
 from paper_1205_0752_amd.workloads import CONFIGS, Grid, Params, Quadrature, sample_points  # noqa: E402
+from parity_bars import band_report, check_fp32c, check_fp64  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -50,8 +46,9 @@ def _gpu_scan(params, quad, grid, lanes=0):
     return g, c
 
 
-def _compare(g_gpu, c_gpu, params, quad, x, g_or, c_or, cond, rel_target=1e-12):
-    """Element-wise check; returns a dict of error statistics."""
+def _compare(g_gpu, c_gpu, params, quad, x, g_or, c_or, cond, max_bad_share=None):
+    """Element-wise FP64 check (parity_bars.check_fp64); returns its
+    statistics."""
     assert g_gpu.shape == g_or.shape
     # contour class: must agree except where floating point sits on a decision
     # boundary; there the GPU value is compared with the oracle forced to the
@@ -65,19 +62,7 @@ def _compare(g_gpu, c_gpu, params, quad, x, g_or, c_or, cond, rel_target=1e-12):
     sing = c_or == oracle.SINGULAR
     assert np.all(np.isnan(g_gpu[sing & (c_gpu == oracle.SINGULAR)]))
     ok = ~sing
-    err = np.abs(g_gpu[ok] - g_or[ok])
-    mag = np.abs(g_or[ok])
-    kap = cond[ok]
-    bound = 64 * EPS * kap * mag
-    assert np.all(np.isfinite(g_gpu[ok]))
-    assert np.all(err <= np.maximum(bound, rel_target * mag)), (
-        np.max(err / np.maximum(bound, rel_target * mag)))
-    good = kap <= 1e3
-    rel = err / mag
-    if good.any():
-        assert np.max(rel[good]) <= rel_target, np.max(rel[good])
-    return {"max_rel": float(np.max(rel)), "median_rel": float(np.median(rel)),
-            "n": int(ok.sum()), "n_kappa_le_1e3": int(good.sum())}
+    return check_fp64(g_gpu[ok], g_or[ok], cond[ok], max_bad_share)
 
 
 def test_config0_full_grid_matches_oracle():
@@ -87,7 +72,7 @@ def test_config0_full_grid_matches_oracle():
     g, c = _gpu_scan(p, q, grid)
     go, co, cond = oracle.scan(p, q, grid, want_cond=True)
     x = oracle.grid_points(grid)
-    stats = _compare(g, c, p, q, x, go, co, cond)
+    stats = _compare(g, c, p, q, x, go, co, cond, max_bad_share=0.03)
     print("config0", stats)
 
 
@@ -112,7 +97,7 @@ def test_paper_worked_example_box_matches_oracle():
     g, c = _gpu_scan(p, q, grid)
     go, co, cond = oracle.scan(p, q, grid, want_cond=True)
     assert set(np.unique(c).tolist()) == {0, 1, 2, 3}
-    _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
+    _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond, max_bad_share=0.03)
 
 
 def test_eq18_on_gpu():
@@ -141,16 +126,17 @@ def test_eq18_on_gpu():
         assert e < (1e-6 if near else 5e-11), (x, e)
 
 
-def test_config1_full_size_sampled():
+def test_config1_full_grid_matches_oracle():
     """The benchmark workload at full size (1024^2 points, 256 x 128 nodes,
-    Lambda^2 = 1e6) in the benchmark's launch configuration: sampled points
-    against the oracle, plus conjugation symmetry and finiteness everywhere."""
+    Lambda^2 = 1e6) in the benchmark's launch configuration: every point
+    against the oracle (about 14 s of oracle time on 16 host threads), plus
+    conjugation symmetry of the whole grid."""
     p, grid, q = CONFIGS["c1_fp64_1024sq"]
     g, c = _gpu_scan(p, q, grid)
-    idx = sample_points(grid, 600, seed=1)
-    x = oracle.grid_points_at(grid, idx)
-    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
-    _compare(g[idx], c[idx], p, q, x, go, co, cond)
+    go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+    x = oracle.grid_points(grid)
+    stats = _compare(g, c, p, q, x, go, co, cond, max_bad_share=0.03)
+    print("config1 full grid", stats)
     assert np.all(np.isfinite(g))
     gm = g.reshape(grid.n_im, grid.n_re)
     # the grid is symmetric under Im x -> -Im x (rows b and n_im - 1 - b)
@@ -173,7 +159,11 @@ def test_config3_full_size_sampled(name):
     idx = sample_points(grid, 400, seed=3)
     x = oracle.grid_points_at(grid, idx)
     go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
-    _compare(g[idx], c[idx], p, q, x, go, co, cond)
+    print(name, _compare(g[idx], c[idx], p, q, x, go, co, cond, max_bad_share=0.03))
+    bidx = _band_sample(grid, 300, seed=4)
+    xb = oracle.grid_points_at(grid, bidx)
+    go, co, cond = oracle.eval_points(p, q, xb, want_cond=True)
+    print(name, "cut and pinch band", _compare(g[bidx], c[bidx], p, q, xb, go, co, cond))
     assert np.array_equal(np.isnan(g), c == gf.CLASS_SINGULAR)
     if complex(p.m1sq).imag == 0 and complex(p.m2sq).imag == 0:
         gm = g.reshape(grid.n_im, grid.n_re)
@@ -335,67 +325,98 @@ def test_fp64_rounding_against_quad_precision(p, grid):
     assert e_gpu.max() <= 4 * e_or.max() + 1e-16, (e_gpu.max(), e_or.max())
 
 
+@pytest.mark.parametrize("p,q", [
+    (Params(1.0, 1.0, 1.0, 1e4), Quadrature(96, 49, 16, gf.FP64, gf.TANH_SINH)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Quadrature(96, 33, 16, gf.FP64, gf.GC1)),
+    (Params(2.0, 0.7, 1.5, 1e6, 1.0, 2), Quadrature(96, 48, 16)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0, 4), Quadrature(96, 48, 16)),
+    (Params(1.0, 1.0, 1.0, 1e4, 1.0, 0, 3), Quadrature(96, 33, 16, gf.FP64, gf.GL)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0, -1, 2), Quadrature(96, 48, 16, gf.FP64, gf.GC1))],
+    ids=["tanh_sinh", "gc1_conj", "taylor2", "taylor4_conj", "dim3", "dim2_conj"])
+def test_fp64_rounding_against_quad_precision_rules_orders_dims(p, q):
+    """The FP64 kernel's rounding for the other angular rules, Taylor orders
+    and dimensions, against the __float128 twin on a 16 x 16 box: its errors
+    are no larger than the plain FP64 oracle's, within a factor 4, in median
+    and maximum over the box."""
+    grid = Grid(16, 16, -12.0, 6.0, -6.0, 6.0)
+    g, c = _gpu_scan(p, q, grid)
+    x = oracle.grid_points(grid)
+    gq, cq = oracle.eval_points_q(p, q, x)
+    go, co = oracle.eval_points(p, q, x)
+    ok = np.isfinite(gq) & (cq == c)
+    assert ok.sum() >= 0.5 * x.size
+    ref = np.abs(gq[ok])
+    e_gpu = np.abs(g[ok] - gq[ok]) / ref
+    e_or = np.abs(go[ok] - gq[ok]) / ref
+    assert np.median(e_gpu) <= 4 * np.median(e_or) + 1e-16, (np.median(e_gpu), np.median(e_or))
+    assert e_gpu.max() <= 4 * e_or.max() + 1e-16, (e_gpu.max(), e_or.max())
+
+
 # ---------------------------------------------------------------- FP32C (FP32 bulk)
 
-def _fp32c_report(g32, g_ref, x, cut_threshold):
-    """Error statistics of an FP32C scan against reference values, separately
-    within 0.05 of the cut x < -(m1 + m2)^2 and elsewhere."""
-    band = (np.abs(x.imag) < 0.05) & (x.real < -cut_threshold)
-    out = {}
-    for name, m in (("band", band), ("elsewhere", ~band)):
-        if not m.any():
-            continue
-        err = np.abs(g32[m] - g_ref[m])
-        rel = err / np.abs(g_ref[m])
-        out[name] = {"n": int(m.sum()), "max_abs": float(err.max()), "mean_abs": float(err.mean()),
-                     "max_rel": float(rel.max()), "mean_rel": float(rel.mean())}
-    return out
+def _band_sample(grid, n, seed, re_below=-1.0):
+    """n flat indices drawn from the points within 0.05 of the real axis with
+    Re x < re_below (the cut band and the pinch band of the workloads)."""
+    d_im = (grid.im_hi - grid.im_lo) / grid.n_im
+    d_re = (grid.re_hi - grid.re_lo) / grid.n_re
+    rows = [b for b in range(grid.n_im) if abs(grid.im_lo + (b + 0.5) * d_im) < 0.05]
+    cols = [a for a in range(grid.n_re) if grid.re_lo + (a + 0.5) * d_re < re_below]
+    cand = np.array([b * grid.n_re + a for b in rows for a in cols], dtype=np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(cand, size=min(n, cand.size), replace=False))
 
 
-def _fp32c_bar(g32, g_or, cond):
-    """|G32 - G| <= 1e-6 max(|G|, 1) where kappa <= 100 (the stated FP32-bulk
-    target, mixed absolute/relative since G(mu^2) = 0); everywhere
-    |G32 - G| <= 16 eps32 kappa |G| (eps32 = 2^-24: FP32 inputs of every
-    denominator and a 1.5-ulp reciprocal, first-order in kappa)."""
-    err = np.abs(g32 - g_or)
-    mag = np.abs(g_or)
-    good = cond <= 100
-    assert np.all(err[good] <= 1e-6 * np.maximum(mag[good], 1.0)), np.max(
-        err[good] / np.maximum(mag[good], 1.0))
-    assert np.all(err <= np.maximum(16 * 2.0 ** -24 * cond * mag, 1e-6 * np.maximum(mag, 1.0)))
+def _fp32c_vs_oracle(g32, c32, p, q, x):
+    """FP32C values at points x against the FP64 oracle (same class)."""
+    go, co = oracle.eval_points(p, q, x)
+    keep = (c32 == co) & (co != oracle.SINGULAR)
+    assert (~keep & (co != oracle.SINGULAR)).sum() <= 1
+    assert np.all(np.isnan(g32[co == oracle.SINGULAR]))
+    return check_fp32c(g32[keep], go[keep]), g32[keep], go[keep], x[keep]
 
 
-def test_fp32c_config2_sampled():
-    """Mixed precision on the 1024^2 box (512 x 256 nodes): sampled points
+def test_fp32c_config2_sampled_and_cut_band():
+    """Mixed precision on the 1024^2 box (512 x 256 nodes), unsplit: sampled
+    points and a sample of the cut and pinch bands (|Im x| < 0.05, Re x < -1)
     against the FP64 oracle; errors reported inside and outside the cut band."""
     p, grid, q = CONFIGS["c2_fp32c_1024sq"]
     g, c = _gpu_scan(p, q, grid)
     assert np.all(np.isfinite(g))
-    idx = sample_points(grid, 400, seed=3)
-    x = oracle.grid_points_at(grid, idx)
-    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
-    assert np.array_equal(c[idx], co) or (c[idx] != co).sum() <= 1
-    keep = c[idx] == co
-    _fp32c_bar(g[idx][keep], go[keep], cond[keep])
-    print("fp32c c2", _fp32c_report(g[idx][keep], go[keep], x[keep], 4.0))
+    for idx in (sample_points(grid, 400, seed=3), _band_sample(grid, 300, seed=6)):
+        x = oracle.grid_points_at(grid, idx)
+        stats, g32, go, xk = _fp32c_vs_oracle(g[idx], c[idx], p, q, x)
+        print("fp32c c2", stats, band_report(g32, go, xk, 4.0))
 
 
-def test_fp32c_full_grid_against_fp64_gpu_and_oracle():
-    """FP32C against the parity-checked FP64 path at every point of a 256^2 box
-    (config c2's window and node counts), and against the oracle on a sample."""
-    p = Params(1.0, 1.0, 1.0, 1e6, 1.0)
-    grid = Grid(256, 256, -16.0, 8.0, -8.0, 8.0)
-    q32 = Quadrature(512, 256, 16, gf.FP32C)
-    q64 = Quadrature(512, 256, 16, gf.FP64)
+def test_fp32c_full_grid_against_fp64_gpu():
+    """FP32C against the parity-checked FP64 path at every point of the full
+    config c2 workload (1024^2 points, 512 x 256 nodes): the FP32-bulk bar
+    holds at all 1,048,576 points, in the cut band and elsewhere."""
+    p, grid, q32 = CONFIGS["c2_fp32c_1024sq"]
+    q64 = Quadrature(q32.n_radial, q32.n_angular, q32.n_arc, gf.FP64)
     g32, c32 = _gpu_scan(p, q32, grid)
     g64, c64 = _gpu_scan(p, q64, grid)
     assert np.array_equal(c32, c64)
+    stats = check_fp32c(g32, g64)
     x = oracle.grid_points(grid)
-    rep = _fp32c_report(g32, g64, x, 4.0)
-    print("fp32c vs fp64 (all points)", rep)
-    idx = sample_points(grid, 200, seed=5)
-    go, co, cond = oracle.eval_points(p, q64, x[idx], want_cond=True)
-    _fp32c_bar(g32[idx], go, cond)
+    print("fp32c vs fp64 (all points)", stats, band_report(g32, g64, x, 4.0))
+
+
+@pytest.mark.parametrize("name", ["c3a_conj_2048sq", "c3b_unequal_2048sq"])
+def test_fp32c_config3_full_size_sampled(name):
+    """The 2048^2 complex-mass and unequal-mass workloads in FP32C at full
+    size and nodes (512 x 256 + 16): a uniform sample and a sample of the cut
+    and pinch bands against the FP64 oracle; NaN exactly at SINGULAR."""
+    p, grid, q = CONFIGS[name]
+    q = Quadrature(q.n_radial, q.n_angular, q.n_arc, gf.FP32C)
+    g, c = _gpu_scan(p, q, grid)
+    assert np.array_equal(np.isnan(g), c == gf.CLASS_SINGULAR)
+    m1, m2 = np.sqrt(complex(p.m1sq)), np.sqrt(complex(p.m2sq))
+    thr = abs(m1 + m2) ** 2
+    for idx in (sample_points(grid, 400, seed=3), _band_sample(grid, 300, seed=4)):
+        x = oracle.grid_points_at(grid, idx)
+        stats, g32, go, xk = _fp32c_vs_oracle(g[idx], c[idx], p, q, x)
+        print(name, "fp32c", stats, band_report(g32, go, xk, thr))
 
 
 def test_fp32c_ragged_and_odd_rules():
@@ -404,9 +425,26 @@ def test_fp32c_ragged_and_odd_rules():
     p = Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0)
     q = Quadrature(96, 49, 8, gf.FP32C)
     grid = Grid(29, 19, -12.0, 6.0, -6.0, 6.0)
-    go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+    go, co = oracle.scan(p, q, grid)
     for lanes in (1, 4, 64):
         g, c = _gpu_scan(p, q, grid, lanes=lanes)
-        keep = c == co
-        assert (~keep).sum() <= 1
-        _fp32c_bar(g[keep], go[keep], cond[keep])
+        keep = (c == co) & (co != oracle.SINGULAR)
+        assert (c != co).sum() <= 1
+        check_fp32c(g[keep], go[keep])
+
+
+@pytest.mark.parametrize("name", ["c0_fp64_64sq", "paper"])
+def test_fp32c_small_boxes_every_point(name):
+    """FP32C at every point of the small workload (64^2, 64 x 32 nodes) and of
+    the paper's display box with its masses (128^2, 128 x 64 nodes)."""
+    if name == "paper":
+        p, grid, q = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0), Grid(128, 128, -5.0, 5.0, -5.0, 5.0), \
+            Quadrature(128, 64, 16, gf.FP32C)
+    else:
+        p, grid, q = CONFIGS[name]
+        q = Quadrature(q.n_radial, q.n_angular, q.n_arc, gf.FP32C)
+    g, c = _gpu_scan(p, q, grid)
+    go, co = oracle.scan(p, q, grid)
+    keep = (c == co) & (co != oracle.SINGULAR)
+    assert (c != co).sum() <= 1
+    print(name, check_fp32c(g[keep], go[keep]))

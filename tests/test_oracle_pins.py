@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from oracle import closed_forms as cf
-from paper_1205_0752_amd.workloads import Grid, Params, Quadrature
+from paper_1205_0752_amd.workloads import GC1, GL, TANH_SINH, Grid, Params, Quadrature
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -450,3 +450,64 @@ def test_fp64_oracle_against_quad_precision_brute_force():
         assert np.all(err <= bound), (err / np.abs(gq), cond)
         assert np.median(err / np.abs(gq)) < 1e-13
     assert seen >= {oracle.R, oracle.Y, oracle.YRES, oracle.MIRROR}
+
+
+# the quad-precision twin beyond GC-II, t^0 and D = 4: every angular rule,
+# Taylor orders -1..4 and D = 2, 3 (each case: params, quadrature)
+Q_CASES = [
+    (Params(1.0, 1.0, 1.0, 1e4), Quadrature(64, 33, 16, 0, GC1)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Quadrature(64, 49, 16, 0, TANH_SINH)),
+    (Params(2.0, 0.7, 1.5, 1e6), Quadrature(64, 32, 16, 0, GL)),
+    (Params(2.0, 0.7, 1.5, 1e6, 1.0, 2), Quadrature(64, 32, 16)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0, 4), Quadrature(64, 32, 16)),
+    (Params(1.0, 1.0, 1.0, 1e4, 1.0, 0, 3), Quadrature(64, 33, 16, 0, GL)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6, 1.0, -1, 2), Quadrature(64, 32, 16, 0, GC1)),
+    (Params(-0.5j, 0.5j, 0.0, 1e6, 1.0, 1, 3), Quadrature(64, 48, 16, 0, TANH_SINH)),
+]
+
+
+@pytest.mark.parametrize("p,q", Q_CASES)
+def test_fp64_oracle_against_quad_precision_every_rule_order_dimension(p, q):
+    """P6 for the other rules, subtraction orders and dimensions: rounding
+    only, within 64 eps kappa |G| at every point of an 8 x 8 box."""
+    grid = Grid(8, 8, -8.0, 4.0, -4.0, 4.0)
+    x = oracle.grid_points(grid)
+    g64, c64, cond = oracle.eval_points(p, q, x, want_cond=True)
+    gq, cq = oracle.eval_points_q(p, q, x)
+    assert np.array_equal(c64, cq)
+    ok = np.isfinite(gq)
+    assert np.array_equal(ok, np.isfinite(g64)) and ok.sum() >= 48
+    err = np.abs(g64 - gq)[ok]
+    assert np.all(err <= 64 * 2.0 ** -53 * cond[ok] * np.abs(gq[ok]))
+
+
+KAPPA_GRIDS = [
+    (Params(1.0, 1.0, 1.0, 1e4), Grid(8, 8, -8.0, 4.0, -4.0, 4.0), Quadrature(64, 32, 16)),
+    (Params(1.0, 1.0, 1.0, 1e6), Grid(16, 4, -12.0, 0.0, -0.1, 0.1), Quadrature(64, 32, 16)),
+    (Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e6), Grid(8, 8, -12.0, 6.0, -6.0, 6.0), Quadrature(64, 32, 16)),
+    (Params(-0.5j, 0.5j, 0.0, 1e6), Grid(8, 8, -5.0, 5.0, -5.0, 5.0), Quadrature(64, 32, 16)),
+    (Params(2.0, 0.7, 1.5, 1e6, 1.0, 2), Grid(8, 8, -8.0, 4.0, -4.0, 4.0), Quadrature(64, 32, 16)),
+    (Params(1.0, 1.0, 1.0, 1e4, 1.0, 0, 3), Grid(8, 8, -8.0, 4.0, -4.0, 4.0), Quadrature(64, 33, 16, 0, GL)),
+]
+
+
+@pytest.mark.parametrize("p,grid,q", KAPPA_GRIDS,
+                         ids=["box", "cut_band", "conjugate", "paper", "taylor2", "dim3"])
+def test_condition_number_is_not_inflated(p, grid, q):
+    """kappa sets every FP64 parity bar (64 eps kappa |G|), so it is pinned
+    from above as well as from below: the FP64 oracle's actual rounding error
+    against the __float128 twin reaches a fixed share of eps kappa |G| -- in
+    the median over the box at least 1/20, and at each of the five points
+    with the largest kappa at least 1/100 (measured: medians 0.11-0.20,
+    largest-kappa points 0.027 and above).  An inflated kappa would push
+    these shares down by the inflation factor.  The cut-band grid holds
+    kappa up to 4e4."""
+    x = oracle.grid_points(grid)
+    g64, c64, cond = oracle.eval_points(p, q, x, want_cond=True)
+    gq, cq = oracle.eval_points_q(p, q, x)
+    ok = (cq == c64) & np.isfinite(gq)
+    share = np.abs(g64 - gq)[ok] / (2.0 ** -53 * cond[ok] * np.abs(gq[ok]))
+    assert np.all(share <= 64)
+    assert np.median(share) >= 1 / 20, np.median(share)
+    top = np.argsort(cond[ok])[-5:]
+    assert np.min(share[top]) >= 1 / 100, (share[top], cond[ok][top])

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_bars import check
 from oracle import closed_forms as cf
 from paper_1205_0752_amd.workloads import GL, Grid, Params, Quadrature
 
@@ -121,14 +122,7 @@ def test_gpu_split_scan_matches_oracle(dim, order, prec):
         go, co, cond = oracle.scan(p, q, grid, want_cond=True)
         keep = (c == co) & (co != oracle.SINGULAR)
         assert (c != co).sum() <= 1
-        err = np.abs(g[keep] - go[keep])
-        mag = np.abs(go[keep])
-        kap = cond[keep]
-        if prec == 0:
-            assert np.all(err <= np.maximum(1e-12 * mag, 64 * EPS * kap * mag)), np.max(err / mag)
-        else:
-            lim = np.maximum(16 * 2.0 ** -24 * kap * mag, 1e-6 * np.maximum(mag, 1.0))
-            assert np.all(err <= lim), np.max(err / lim)
+        check(prec, g[keep], go[keep], cond[keep], dim=dim)
 
 
 @pytest.mark.gpu
