@@ -228,6 +228,24 @@ int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_
 int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad,
             void *out, void *stream);
 
+/* gf_scan for callers that cannot allocate device memory (code that must not
+ * call hipMalloc, such as tight serving loops or work recorded into a HIP
+ * graph).  Same arguments, validation and result as gf_scan (lanes per point
+ * chosen automatically), but no plan is built or cached: the node tables and
+ * the subtraction coefficients are generated on `stream` by the library's
+ * kernels into one static device buffer of 512 KiB per device (enough for
+ * every valid quadrature; sizes beyond it return GF_EINVAL), held until the
+ * process ends, and the scan reads them there.  Nothing is allocated, on the
+ * device or the host, and nothing is copied from the host: the call only
+ * enqueues three kernels and returns.  Every call on a device shares that
+ * buffer, so calls on one device must be ordered (one stream, or
+ * synchronised streams): calls that overlap on a device race and may return
+ * wrong results.  The tables are generated on the device, so results can
+ * differ from gf_scan's in the last bits.  Errors as gf_scan
+ * (nothing enqueued on a validation error). */
+int gf_scan_noalloc(const gf_params *params, const gf_grid *grid, const gf_quadrature *quad,
+                    void *out, void *stream);
+
 /* Releases a plan.  The caller must have synchronised every stream that uses
  * it.  NULL is ignored. */
 void gf_free(gf_plan_t *plan);

@@ -12,11 +12,11 @@ from ._binding import (CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRE
                        LIB_PATH, NO_CONTOUR, OBSTRUCTED_CONTOUR, OBSTRUCTED_REAL_AXIS, REQ_DONE,
                        REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError, Plan,
                        Server, cache_clear, cut_curve, empty_result, load, obstruction_map, scan,
-                       scan_plan, version, yscan_plan)
+                       scan_noalloc, scan_plan, version, yscan_plan)
 from .workloads import (CONFIGS, FP32C, FP64, GC1, GC2, GL, TANH_SINH, Grid, Params, Propagators,
                         Quadrature)
 
-__all__ = ["Params", "Propagators", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_plan", "cache_clear",
+__all__ = ["Params", "Propagators", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_noalloc", "scan_plan", "cache_clear",
            "empty_result", "yscan_plan", "cut_curve", "obstruction_map", "version", "load", "GFError", "EXPORTS",
            "LIB_PATH", "FP64", "FP32C", "GC2", "GC1", "TANH_SINH", "GL", "CONFIGS",
            "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "OBSTRUCTED_REAL_AXIS", "OBSTRUCTED_CONTOUR",

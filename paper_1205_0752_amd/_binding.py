@@ -27,7 +27,8 @@ GF_ENOTFOUND = -6
 CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
 
 #: every symbol include/gf.h declares
-EXPORTS = ("gf_plan", "gf_plan_ex", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_free", "gf_cache_clear",
+EXPORTS = ("gf_plan", "gf_plan_ex", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_scan_noalloc",
+           "gf_free", "gf_cache_clear",
            "gf_plan_jmu", "gf_plan_taylor", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
            "gf_yscan_plan", "gf_cut_curve", "gf_obstruction_map",
            "gf_server_create", "gf_server_submit", "gf_server_submit_ex", "gf_server_poll",
@@ -125,6 +126,8 @@ def load():
         lib.gf_scan_plan_ex.argtypes = [vp, ctypes.POINTER(_Grid), vp, vp, ctypes.c_int, vp]
         lib.gf_scan.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
                                 ctypes.POINTER(_Quad), vp, vp]
+        lib.gf_scan_noalloc.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
+                                        ctypes.POINTER(_Quad), vp, vp]
         lib.gf_free.argtypes = [vp]
         lib.gf_free.restype = None
         lib.gf_cache_clear.argtypes = []
@@ -349,6 +352,19 @@ def scan(params: Params, grid: Grid, quad: Quadrature, out=None, stream=None):
     return out
 
 
+def scan_noalloc(params: Params, grid: Grid, quad: Quadrature, out, stream=None):
+    """gf_scan_noalloc: the one-call scan with node tables in the library's
+    static device buffer (nothing allocated); `out` is required."""
+    import torch
+    dev = _current_device()
+    _check_out(out, torch.complex128, grid.n_points, dev)
+    _check(load().gf_scan_noalloc(ctypes.byref(c_params(params)), ctypes.byref(c_grid(grid)),
+                                  ctypes.byref(c_quad(quad)),
+                                  ctypes.c_void_p(out.data_ptr() if grid.n_points else 0),
+                                  _stream_handle(stream)))
+    return out
+
+
 class Server:
     """Continuous-batching scan server (gf_server_*) on the current device."""
 
@@ -434,7 +450,7 @@ def version() -> str:
     return load().gf_version().decode()
 
 
-__all__ = ["Plan", "Server", "scan", "scan_plan", "yscan_plan", "cut_curve", "obstruction_map",
+__all__ = ["Plan", "Server", "scan", "scan_noalloc", "scan_plan", "yscan_plan", "cut_curve", "obstruction_map",
            "cache_clear",
            "version", "load", "GFError",
            "EXPORTS",

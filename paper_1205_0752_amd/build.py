@@ -9,7 +9,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "_libgf.so")
 SOURCES = [os.path.join(HERE, "csrc", name)
-           for name in ("gf_host.cpp", "gf_server.cpp", "gf_kernels.hip", "gf_diag_kernels.hip")]
+           for name in ("gf_host.cpp", "gf_server.cpp", "gf_kernels.hip", "gf_diag_kernels.hip",
+                         "gf_noalloc.hip")]
 ARCH = "gfx950"
 
 # Device code is built without packed FP32 instructions (the compiler would
