@@ -66,13 +66,17 @@ def measured_traffic(kernel: str):
 def evals_per_scan(cls, quad) -> int:
     """Integrand evaluations (angular terms) one scan performs, from its class
     map: R points n_r nodes, Y points n_r + n_arc, YRES and MIRROR points
-    (whose conjugate is a YRES point) n_r + n_arc + 1; times n_angular."""
+    (whose conjugate is a YRES point) n_r + n_arc + 1; LONG points (each pole
+    term on the ray, on one closing arc and, for the pole-sum benchmark's
+    conjugate pair with two real k-leg poles, two residues of the blocked
+    term: n_r + n_arc + 1 per pole on average) n_r + n_arc + 1; times
+    n_angular."""
     import numpy as np
     c = np.asarray(cls).ravel()
     nr, na, nc = quad.n_radial, quad.n_angular, quad.n_arc
     n_r = int((c == 0).sum())
     n_y = int((c == 1).sum())
-    n_res = int(((c == 2) | (c == 3)).sum())
+    n_res = int(((c == 2) | (c == 3) | (c == 5)).sum())
     return na * (n_r * nr + n_y * (nr + nc) + n_res * (nr + nc + 1))
 
 

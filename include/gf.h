@@ -26,8 +26,9 @@
  * arc |y| = Lambda^2.
  *
  * Contours (STEP 3): real axis (region R), ray at arg x plus the closing arc,
- * the same plus the residue of the k-leg pole y = -m2^2, or the conjugate
- * mirror G(x) = conj G(conj x) for real masses and conjugate mass pairs.
+ * the same plus the residue of the k-leg pole y = -m2^2, the conjugate
+ * mirror G(x) = conj G(conj x) for real masses and conjugate mass pairs, or,
+ * where none of these applies, the long way round the origin (GF_CLASS_LONG).
  * Points with no valid contour (x on a bad ray arg x = arg(-m^2) outside
  * region R, e.g. the negative real axis below -m1^2 for real masses) are
  * returned as NaN + i NaN with class GF_CLASS_SINGULAR.
@@ -91,6 +92,26 @@ extern "C" {
 #define GF_CLASS_YRES 2      /* ray + arc + residue at y = -m2^2 */
 #define GF_CLASS_MIRROR 3    /* conj of the value at conj x */
 #define GF_CLASS_SINGULAR 4  /* no valid contour: NaN */
+#define GF_CLASS_LONG 5      /* the rotation towards arg x would sweep a (p-k)-leg
+                                bad ray arg(-m1^2) and neither the residue class
+                                nor the mirror point applies (a complex (p-k)-leg
+                                pole without its conjugate on the k leg; a
+                                complex-conjugate pair on the (p-k) leg): each
+                                blocked pole's term is continued the other way
+                                round the origin, by 2 pi - |arg x| through the
+                                other half plane, which sweeps none of its own
+                                bad ray and ends on the same ray y = r e^{i arg x};
+                                its closing arc runs back the long way, to angle
+                                +-2 pi, and it adds the residues of the k-leg
+                                poles that rotation sweeps (sign -sign(arg x));
+                                the other poles' terms keep the short rotation.
+                                Inside the curve where the discretised angular
+                                cut meets a k-leg pole (from the threshold
+                                -(sqrt(m1^2) + sqrt(m2^2))^2) this is the analytic
+                                continuation; beyond it the term's cut runs along
+                                that curve and then the bad ray.  Not used in
+                                D = 3 (a full turn changes the branch of sqrt(y);
+                                those points stay GF_CLASS_SINGULAR) */
 
 /* Integrand parameters (eq. 14-16).  m1^2 sits on the (p-k) leg, m2^2 on the
  * k leg; neither may lie on the non-positive real axis.  mu2 is the real
@@ -178,7 +199,10 @@ int gf_plan(const gf_params *params, const gf_quadrature *quad, gf_plan_t **out)
  * pole's bad ray; crossing only k-leg bad rays adds the residue of each
  * crossed pole; crossing only (p-k)-leg bad rays uses the mirror point when
  * G(conj x) = conj G(x) holds, i.e. when conjugating every pole position and
- * residue maps (P1, P2) onto itself or onto (P2, P1) (as pole multisets). */
+ * residue maps (P1, P2) onto itself or onto (P2, P1) (as pole multisets), and
+ * the mirror point has a contour of its own; everywhere else off the bad rays
+ * GF_CLASS_LONG, with the short and the long rotation chosen per (p-k)-leg
+ * pole. */
 #define GF_MAX_POLES 8
 typedef struct {
     int32_t n1, n2;

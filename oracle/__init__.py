@@ -22,8 +22,8 @@ _LIB64 = os.path.join(_HERE, "_liborc.so")
 _LIBQ = os.path.join(_HERE, "_liborcq.so")
 
 # contour classes (numbering shared by both oracle files)
-R, Y, YRES, MIRROR, SINGULAR = 0, 1, 2, 3, 4
-CLASS_NAMES = {R: "R", Y: "Y", YRES: "YRES", MIRROR: "MIRROR", SINGULAR: "SINGULAR"}
+R, Y, YRES, MIRROR, SINGULAR, LONG = 0, 1, 2, 3, 4, 5
+CLASS_NAMES = {R: "R", Y: "Y", YRES: "YRES", MIRROR: "MIRROR", SINGULAR: "SINGULAR", LONG: "LONG"}
 
 
 class _Problem(ctypes.Structure):
@@ -77,8 +77,6 @@ def _load():
         lib.orc_jmu.argtypes = [ctypes.POINTER(_Problem), dp, dp]
         lib.orc_classify_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                             ctypes.c_char_p]
-        lib.orc_evals_for_class.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int]
-        lib.orc_evals_for_class.restype = ctypes.c_long
         lib.orc_threads.restype = ctypes.c_int
         lib.orc_obstruction.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                         ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p]
@@ -335,20 +333,3 @@ def classify(params, quad, x, props=None) -> np.ndarray:
     pr = problem(params, quad, props)
     lib.orc_classify_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), cls)
     return np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
-
-
-def evals_for_classes(params, quad, cls, x=None, props=None) -> int:
-    """Integrand evaluations for points of the given classes; a MIRROR point
-    costs what its mirror image costs (needs x)."""
-    lib = _load()
-    pr = problem(params, quad, props)
-    per = {c: lib.orc_evals_for_class(ctypes.byref(pr), c) for c in (R, Y, YRES)}
-    cls = np.asarray(cls)
-    total = sum(int((cls == c).sum()) * per[c] for c in (R, Y, YRES))
-    m = cls == MIRROR
-    if m.any():
-        if x is None:
-            raise ValueError("mirror points need x")
-        cb = classify(params, quad, np.conj(np.asarray(x)[m]))
-        total += sum(int((cb == c).sum()) * per[c] for c in (R, Y, YRES))
-    return total

@@ -55,7 +55,7 @@
 
 typedef double complex cplx;
 
-enum { ORC_R = 0, ORC_Y = 1, ORC_YRES = 2, ORC_MIRROR = 3, ORC_SINGULAR = 4 };
+enum { ORC_R = 0, ORC_Y = 1, ORC_YRES = 2, ORC_MIRROR = 3, ORC_SINGULAR = 4, ORC_LONG = 5 };
 
 /* Region R is chosen where v = |Im sqrt x| is below ORC_R_NEAR of its bound
  * v* = Re sqrt(m1^2), or where 1 - v/v* is at least ORC_R_SLOPE times the
@@ -298,6 +298,7 @@ typedef struct {
     double lo, hi;          /* open sector (lo, hi) reachable by rotating the ray */
     double vstar;           /* region-R bound on |Im sqrt(x)|: min_a Re sqrt(m1_a^2) */
     int mirror_ok;          /* G(conj x) = conj G(x) for these propagators */
+    int dim;                /* D: the long way round is not used for D = 3 */
 } orc_geometry;
 
 /* arg(-m^2); a real positive m^2 gives carg(-m^2) = +pi or -pi depending on
@@ -345,6 +346,7 @@ static void orc_make_geometry(const orc_problem *p, orc_geometry *g)
     }
     g->m1sq = g->m1[0];
     g->m2sq = g->m2[0];
+    g->dim = orc_dim(p);
     g->hi = M_PI;
     g->lo = -M_PI;
     g->vstar = INFINITY;
@@ -380,9 +382,13 @@ static int orc_swept(double phi, double b)
     return phi > 0.0 ? (b > 0.0 && b < phi) : (b <= 0.0 && b > phi);
 }
 
-/* Rotated-contour class of x (Y, YRES, MIRROR or SINGULAR); for YRES,
+/* Rotated-contour class of x (Y, YRES, MIRROR, LONG or SINGULAR); for YRES,
  * *res_sign = +1 or -1 and *mask flags the k-leg poles swept across, whose
- * residues the contour picks up. */
+ * residues the contour picks up.  LONG: the rotation towards arg x sweeps a
+ * (p-k)-leg bad ray and neither YRES nor the mirror point applies; each such
+ * pole's term is then continued the other way round the origin (see
+ * orc_long_sets).  SINGULAR only on a bad ray itself, or for LONG in D = 3,
+ * where a turn the long way round ends on the other branch of sqrt(y). */
 static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, int *mask)
 {
     *res_sign = 0;
@@ -404,7 +410,30 @@ static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, i
         return ORC_YRES;
     }
     if (cross1 && !m && g->mirror_ok) return ORC_MIRROR;
-    return ORC_SINGULAR;
+    return g->dim == 3 ? ORC_SINGULAR : ORC_LONG;
+}
+
+/* The two groups of a LONG point.  Rotating the ray from angle 0 to phi the
+ * short way (through the half plane of x) is blocked for the (p-k)-leg poles
+ * whose bad ray lies in between; each of their terms c1_a <1/(U_a - V z)> is
+ * continued by rotating the other way, through the other half plane, by
+ * 2 pi - |phi|, which sweeps none of its own bad ray.  Both rotations end on
+ * the same ray y = r e^{i phi}; the closing arcs |y| = Lambda^2 run back to
+ * angle 0 the short way (terms of the short group) and the long way (terms
+ * of the long group), and each group takes the residues of the k-leg poles
+ * its own rotation sweeps: the short one with sign sign(phi) (as YRES), the
+ * long one with -sign(phi).  *grp_long flags the long group's (p-k)-leg poles,
+ * *res_short and *res_long the k-leg poles whose residues each group adds. */
+static void orc_long_sets(const orc_geometry *g, double phi, int *grp_long, int *res_short,
+                          int *res_long)
+{
+    *grp_long = *res_short = *res_long = 0;
+    for (int a = 0; a < g->n1; ++a)
+        if (orc_swept(phi, g->b1[a])) *grp_long |= 1 << a;
+    for (int b = 0; b < g->n2; ++b) {
+        if (orc_swept(phi, g->b2[b])) *res_short |= 1 << b;
+        else if (ang_dist(phi, g->b2[b]) != 0.0) *res_long |= 1 << b;
+    }
 }
 
 /* Class of x; for YRES, *res_sign = +1 or -1 and *mask the residues due. */
@@ -418,7 +447,7 @@ static int orc_classify_m(const orc_geometry *g, cplx x, int *res_sign, int *mas
         for (int k = 0; k < g->n1; ++k) delta = fmin(delta, ang_dist(phi, g->b1[k]));
         for (int k = 0; k < g->n2; ++k) delta = fmin(delta, ang_dist(phi, g->b2[k]));
         if (v < ORC_R_NEAR * g->vstar || 1.0 - v / g->vstar >= ORC_R_SLOPE * delta ||
-            rot == ORC_SINGULAR) {
+            rot == ORC_SINGULAR || rot == ORC_LONG) {
             *res_sign = 0;
             *mask = 0;
             return ORC_R;
@@ -431,6 +460,22 @@ static int orc_classify(const orc_geometry *g, cplx x, int *res_sign)
 {
     int mask;
     return orc_classify_m(g, x, res_sign, &mask);
+}
+
+/* The class a point is evaluated with: a MIRROR point whose conjugate has no
+ * contour of its own (MIRROR, LONG or SINGULAR there) takes the real axis if
+ * it is valid at x, else the long way round at x (SINGULAR in D = 3). */
+static int orc_final_class(const orc_geometry *g, cplx x, int *res_sign, int *mask)
+{
+    int cls = orc_classify_m(g, x, res_sign, mask);
+    if (cls != ORC_MIRROR) return cls;
+    int sb, mb;
+    int cb = orc_classify_m(g, conj(x), &sb, &mb);
+    if (cb != ORC_MIRROR && cb != ORC_SINGULAR && cb != ORC_LONG) return cls;
+    *res_sign = 0;
+    *mask = 0;
+    if (fabs(cimag(csqrt(x))) < g->vstar) return ORC_R;
+    return g->dim == 3 ? ORC_SINGULAR : ORC_LONG;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -523,16 +568,22 @@ static void orc_radial_nodes(const orc_ctx *c, cplx xn, double *r, double *wr)
 /* <P1(D1)>(x, y) = sum_a c1_a <1/(x + y + m1_a^2 - 2 sqrt(x) sqrt(y) z)>; with
  * sens given, adds sum_a |c1_a| (that pole's absolute angular sum with its
  * sensitivity factor, as angular_d1 counts it). */
-static cplx orc_ang_p1(const orc_ctx *c, cplx x, cplx y, cplx sxsy, double *sens)
+static cplx orc_ang_p1_set(const orc_ctx *c, cplx x, cplx y, cplx sxsy, int set, double *sens)
 {
     cplx s = 0.0;
     for (int a = 0; a < c->geo.n1; ++a) {
+        if (!(set >> a & 1)) continue;
         double t = 0.0;
         s += c->geo.c1[a] * angular_d1(x, y, sxsy, c->geo.m1[a], c->p->n_angular, c->z, c->w,
                                        sens ? &t : NULL);
         if (sens) *sens += cabs(c->geo.c1[a]) * t;
     }
     return s;
+}
+
+static cplx orc_ang_p1(const orc_ctx *c, cplx x, cplx y, cplx sxsy, double *sens)
+{
+    return orc_ang_p1_set(c, x, y, sxsy, ~0, sens);
 }
 
 /* P2(y) = sum_b c2_b / (y + m2_b^2); *sens = sum_b |c2_b / (y + m2_b^2)|
@@ -549,14 +600,40 @@ static cplx orc_p2(const orc_ctx *c, cplx y, double *sens)
     return s;
 }
 
-/* One contour node: weight w (dy and the measure) at y with sqrt(y) = sy. */
-static cplx orc_node(const orc_ctx *c, cplx x, cplx sx, cplx y, cplx sy, cplx w, double *absum)
+/* One contour node of the (p-k)-leg poles in `set`: weight w (dy and the
+ * measure) at y with sqrt(y) = sy. */
+static cplx orc_node_set(const orc_ctx *c, cplx x, cplx sx, cplx y, cplx sy, cplx w, int set,
+                         double *absum)
 {
     double a = 0.0, sp = 0.0;
-    cplx ang = orc_ang_p1(c, x, y, sx * sy, absum ? &a : NULL);
+    cplx ang = orc_ang_p1_set(c, x, y, sx * sy, set, absum ? &a : NULL);
     cplx pre = w * orc_measure(orc_dim(c->p), y, sy) * orc_p2(c, y, &sp);
     if (absum) *absum += cabs(w * orc_measure(orc_dim(c->p), y, sy)) * sp * a;
     return pre * ang;
+}
+
+static cplx orc_node(const orc_ctx *c, cplx x, cplx sx, cplx y, cplx sy, cplx w, double *absum)
+{
+    return orc_node_set(c, x, sx, y, sy, w, ~0, absum);
+}
+
+/* Residues of the k-leg poles in `res` for the (p-k)-leg poles in `set`: at
+ * y0 = -m2_b^2 the residue of y^{(D-2)/2} P2(y) <P1>(y) is
+ * c2_b y0^{(D-2)/2} <P1>(y0); each is added times sign 2 pi i. */
+static cplx orc_residues(const orc_ctx *c, cplx x, cplx sx, int res, int set, int sign,
+                         double *absum)
+{
+    cplx s = 0.0;
+    for (int b = 0; b < c->geo.n2; ++b) {
+        if (!(res >> b & 1)) continue;
+        cplx y0 = -c->geo.m2[b];
+        double a = 0.0;
+        cplx ang = orc_ang_p1_set(c, x, y0, sx * csqrt(y0), set, absum ? &a : NULL);
+        cplx pre = sign * 2.0 * M_PI * I * c->geo.c2[b] * orc_measure(orc_dim(c->p), y0, csqrt(y0));
+        s += pre * ang;
+        if (absum) *absum += cabs(pre) * a;
+    }
+    return s;
 }
 
 /* The contour sum of the point x (class cls, residue flags res_mask for
@@ -583,27 +660,37 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_
     cplx eh = cexp(I * 0.5 * phi);
     for (int i = 0; i < p->n_radial; ++i)
         s += orc_node(c, x, sx, e * rn[i], eh * sqrt(rn[i]), e * wn[i], absum);
-    /* arc |y| = Lambda^2 from angle phi back to 0: psi(s) = phi (1 - s)/2,
-     * dy = i y psi'(s) ds = -i y (phi/2) ds */
+    int grp_long = 0, res_short = res_mask, res_long = 0;
+    if (cls == ORC_LONG) orc_long_sets(&c->geo, phi, &grp_long, &res_short, &res_long);
+    const int all = (1 << c->geo.n1) - 1, grp_short = all & ~grp_long;
     double lam = sqrt(p->lambda2);
-    for (int k = 0; k < p->n_arc; ++k) {
-        double psi = 0.5 * phi * (1.0 - c->arc_x[k]);
-        cplx y = p->lambda2 * cexp(I * psi);
-        cplx sy = lam * cexp(I * 0.5 * psi);
-        s += orc_node(c, x, sx, y, sy, -I * y * (0.5 * phi) * c->arc_w[k], absum);
-    }
-    if (cls == ORC_YRES) {
-        /* residue of y^{(D-2)/2} P2(y) <P1>(y) at the pole y0 = -m2_b^2 of a
-         * swept k-leg pole is c2_b y0^{(D-2)/2} <P1>(y0) */
-        for (int b = 0; b < c->geo.n2; ++b) {
-            if (!(res_mask >> b & 1)) continue;
-            cplx y0 = -c->geo.m2[b];
-            double a = 0.0;
-            cplx ang = orc_ang_p1(c, x, y0, sx * csqrt(y0), absum ? &a : NULL);
-            cplx pre = res_sign * 2.0 * M_PI * I * c->geo.c2[b] * orc_measure(dim, y0, csqrt(y0));
-            s += pre * ang;
-            if (absum) *absum += cabs(pre) * a;
+    if (grp_short) {
+        /* arc |y| = Lambda^2 from angle phi back to 0 the short way:
+         * psi(s) = phi (1 - s)/2, dy = i y psi'(s) ds = -i y (phi/2) ds */
+        for (int k = 0; k < p->n_arc; ++k) {
+            double psi = 0.5 * phi * (1.0 - c->arc_x[k]);
+            cplx y = p->lambda2 * cexp(I * psi);
+            cplx sy = lam * cexp(I * 0.5 * psi);
+            s += orc_node_set(c, x, sx, y, sy, -I * y * (0.5 * phi) * c->arc_w[k], grp_short,
+                              absum);
         }
+    }
+    if (grp_long) {
+        /* the long way: psi(s) = phi + L (1 + s)/2 with L = sign(phi) 2 pi - phi,
+         * ending at angle +-2 pi, i.e. at y = Lambda^2; dy = i y (L/2) ds */
+        double L = (phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - phi;
+        for (int k = 0; k < p->n_arc; ++k) {
+            double psi = phi + 0.5 * L * (1.0 + c->arc_x[k]);
+            cplx y = p->lambda2 * cexp(I * psi);
+            cplx sy = lam * cexp(I * 0.5 * psi);
+            s += orc_node_set(c, x, sx, y, sy, I * y * (0.5 * L) * c->arc_w[k], grp_long, absum);
+        }
+    }
+    if (cls == ORC_YRES) s += orc_residues(c, x, sx, res_mask, all, res_sign, absum);
+    if (cls == ORC_LONG) {
+        const int sg = phi > 0.0 ? 1 : -1;
+        if (grp_short) s += orc_residues(c, x, sx, res_short, grp_short, sg, absum);
+        s += orc_residues(c, x, sx, res_long, grp_long, -sg, absum);
     }
     free(rn);
     free(wn);
@@ -632,7 +719,7 @@ static cplx orc_subtraction(const orc_ctx *c, cplx x, double *absum)
 static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double *cond)
 {
     int sign = 0, mask = 0;
-    int cls = orc_classify_m(&c->geo, x, &sign, &mask);
+    int cls = orc_final_class(&c->geo, x, &sign, &mask);
     if (force_class >= 0) {
         cls = force_class;
         if (cls == ORC_YRES) {
@@ -654,11 +741,6 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
         cplx xb = conj(x);
         int sb = 0, mb = 0;
         int cb = orc_classify_m(&c->geo, xb, &sb, &mb);
-        if (cb == ORC_MIRROR || cb == ORC_SINGULAR) {
-            *g = NAN + I * NAN;
-            if (cond) *cond = NAN;
-            return ORC_SINGULAR;
-        }
         s = orc_contour_sum(c, xb, xb, cb, sb, mb, pab);
         cplx gb = c->p->scale * (s - orc_subtraction(c, xb, pab));
         *g = conj(gb);
@@ -863,23 +945,10 @@ int orc_classify_points(const orc_problem *p, long n, const double *x_re, const 
     orc_geometry g;
     orc_make_geometry(p, &g);
     for (long k = 0; k < n; ++k) {
-        int s;
-        cls[k] = (signed char)orc_classify(&g, x_re[k] + I * x_im[k], &s);
+        int s, m;
+        cls[k] = (signed char)orc_final_class(&g, x_re[k] + I * x_im[k], &s, &m);
     }
     return 0;
-}
-
-/* Integrand evaluations a point of class cls costs (n_angular per contour node). */
-long orc_evals_for_class(const orc_problem *p, int cls)
-{
-    long nodes = 0;
-    switch (cls) {
-    case ORC_R: nodes = p->n_radial; break;
-    case ORC_Y: nodes = p->n_radial + p->n_arc; break;
-    case ORC_YRES: nodes = p->n_radial + p->n_arc + 1; break;
-    default: nodes = 0;
-    }
-    return nodes * p->n_angular;
 }
 
 /* Threads an OpenMP region of the oracle uses. */
@@ -988,8 +1057,9 @@ static int orc_cut_real(const orc_problem *p, cplx x, int n, int *tie)
 }
 
 /* The ray at phi = arg x (same u), then the arc from phi back to 0 at
- * u = phi (1 - k/(n-1)), k = 0..n-1. */
-static int orc_cut_ray_arc(const orc_problem *p, cplx x, int n, int *tie)
+ * u = phi (1 - k/(n-1)), k = 0..n-1, or, the long way round the origin, from
+ * phi on to +-2 pi at u = phi + L k/(n-1), L = sign(phi) 2 pi - phi. */
+static int orc_cut_ray_arc(const orc_problem *p, cplx x, int n, int long_way, int *tie)
 {
     double phi = carg(x), T = log1p(p->lambda2);
     orc_cut_part ray = {x, p->m1sq_re + I * p->m1sq_im, 0, cexp(I * phi), p->lambda2};
@@ -998,7 +1068,9 @@ static int orc_cut_ray_arc(const orc_problem *p, cplx x, int n, int *tie)
     double *u = malloc(sizeof(double) * n);
     for (int k = 1; k < n; ++k) u[k - 1] = T * k / (n - 1);
     int hit = orc_cut_walk(&ray, u, n - 1, tie);
-    for (int k = 0; k < n; ++k) u[k] = phi * (1.0 - (double)k / (n - 1));
+    double L = (phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - phi;
+    for (int k = 0; k < n; ++k)
+        u[k] = long_way ? phi + L * k / (n - 1) : phi * (1.0 - (double)k / (n - 1));
     hit |= orc_cut_walk(&arc, u, n, tie);
     free(u);
     return hit;
@@ -1019,19 +1091,19 @@ int orc_obstruction(const orc_problem *p, long n, const double *x_re, const doub
         cplx x = x_re[k] + I * x_im[k];
         int t = 0, s;
         int v = orc_cut_real(p, x, n_samples, &t);
-        int cls = orc_classify(&g, x, &s);
+        int m;
+        int cls = orc_final_class(&g, x, &s, &m);
         cplx xe = x;
         int ecls = cls;
         if (cls == ORC_MIRROR) {
             xe = conj(x);
             ecls = orc_classify(&g, xe, &s);
-            if (ecls == ORC_MIRROR || ecls == ORC_SINGULAR) cls = ORC_SINGULAR;
         }
         if (cls == ORC_SINGULAR) {
             v |= 4;
         } else {
             int used = ecls == ORC_R ? orc_cut_real(p, xe, n_samples, &t)
-                                     : orc_cut_ray_arc(p, xe, n_samples, &t);
+                                     : orc_cut_ray_arc(p, xe, n_samples, ecls == ORC_LONG, &t);
             if (used) v |= 2;
         }
         out[k] = (unsigned char)v;

@@ -8,7 +8,7 @@ function: Python face of the C-ABI library declared in include/gf.h.
 The library is loaded on first use; importing this package does not touch the
 GPU.
 """
-from ._binding import (CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
+from ._binding import (CLASS_LONG, CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
                        LIB_PATH, NO_CONTOUR, OBSTRUCTED_CONTOUR, OBSTRUCTED_REAL_AXIS, REQ_DONE,
                        REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError, Plan,
                        Server, cache_clear, cut_curve, empty_result, load, obstruction_map, scan,
@@ -21,4 +21,4 @@ __all__ = ["Params", "Propagators", "Grid", "Quadrature", "Plan", "Server", "sca
            "LIB_PATH", "FP64", "FP32C", "GC2", "GC1", "TANH_SINH", "GL", "CONFIGS",
            "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "OBSTRUCTED_REAL_AXIS", "OBSTRUCTED_CONTOUR",
            "NO_CONTOUR", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
-           "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR"]
+           "CLASS_R", "CLASS_Y", "CLASS_YRES", "CLASS_MIRROR", "CLASS_SINGULAR", "CLASS_LONG"]

@@ -24,7 +24,7 @@ GF_EDEVICE = -4
 GF_EBUDGET = -5
 GF_ENOTFOUND = -6
 
-CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR = 0, 1, 2, 3, 4
+CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR, CLASS_LONG = 0, 1, 2, 3, 4, 5
 
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_plan_ex", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_scan_noalloc",

@@ -75,18 +75,35 @@ __device__ __forceinline__ double angle_between(double a, double b)
 // Contour class of x (STEP 3).  Rotating the ray from angle 0 to phi = arg x
 // is free inside (lo, hi); sweeping across the k-leg pole rays arg(-m2_b^2)
 // adds their residues (sign of phi); across a ray arg(-m1_a^2) the conjugate
-// point is used instead.  The real axis is preferred where it is valid (|Im
-// sqrt x| < v*) and either comfortably inside (v < kRNear v*) or closer to its
-// own edge than the ray is to a bad ray.  POLES: every pole of the two pole
-// sums has its bad ray; *res_mask flags the k-leg poles whose residue is due.
+// point is used instead where the propagators allow it.  Otherwise (kLong)
+// every (p-k)-leg pole whose bad ray the rotation would sweep has its term
+// continued the other way round the origin, through the other half plane:
+// that rotation, by 2 pi - |phi|, sweeps none of its own bad ray and ends on
+// the same ray at angle phi; its closing arc runs back the long way and it
+// takes the residues of the k-leg poles it sweeps, with the opposite sign.
+// In D = 3 a turn the long way round ends on the other branch of sqrt(y),
+// so such points stay kSingular, as do points on a bad ray itself.  The real
+// axis is preferred where it is valid (|Im sqrt x| < v*) and either
+// comfortably inside (v < kRNear v*), closer to its own edge than the ray is
+// to a bad ray, or the alternative is the long way round.
+//
+// *info packs the contour's pole sets (kInfo* below): the k-leg residues of
+// the short rotation's terms (YRES; a single pole flags bit 0), those of the
+// long rotation's terms, the (p-k)-leg poles of the long rotation, and
+// whether the real axis is valid at x.  For kMirror it holds the kLong sets
+// of x, the contour to fall back on when the conjugate point has none.
+constexpr int kInfoResLong = 8;    // bits 8-15: k-leg residues of the long rotation
+constexpr int kInfoGrpLong = 16;   // bits 16-23: (p-k)-leg poles of the long rotation
+constexpr int kInfoRValid = 1 << 24;
+
 template <bool POLES = false, class Args>
-__device__ int classify(const Args &a, double xr, double xi, int *res_sign, int *res_mask = nullptr)
+__device__ int classify(const Args &a, double xr, double xi, int *res_sign, int *info = nullptr)
 {
     cd sx = csqrt_principal(xr, xi);
     double v = fabs(sx.i);
     double phi = atan2(xi, xr);
     int rot;
-    int mask = 0;
+    int mask = 0, lng = 0;  // residues of the short rotation; the kLong sets
     *res_sign = 0;
     double delta;
     if (!POLES) {
@@ -103,16 +120,18 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign, int 
                 past2 = a.beta2 <= 0.0 && a.beta2 > phi;
             }
             bool on_bad = angle_between(phi, a.beta1) == 0.0 || angle_between(phi, a.beta2) == 0.0;
+            // the long rotation of the single (p-k)-leg pole sweeps the k-leg
+            // ray exactly when the short one does not
+            lng = (1 << kInfoGrpLong) | (past2 ? 0 : 1 << kInfoResLong);
             if (on_bad) {
                 rot = kSingular;
             } else if (past2 && !past1) {
                 rot = kYRes;
-                *res_sign = phi > 0.0 ? 1 : -1;
                 mask = 1;
             } else if (past1 && !past2 && a.mirror_ok) {
                 rot = kMirror;
             } else {
-                rot = kSingular;
+                rot = a.dim == 3 ? kSingular : kLong;
             }
         }
     } else {
@@ -123,12 +142,18 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign, int 
         bool past1 = false, on_bad = false;
         delta = M_PI;
         for (int k = 0; k < a.n1; ++k) {
-            past1 = past1 || swept(a.b1[k]);
+            if (swept(a.b1[k])) {
+                past1 = true;
+                lng |= 1 << (kInfoGrpLong + k);
+            }
             on_bad = on_bad || angle_between(phi, a.b1[k]) == 0.0;
             delta = fmin(delta, angle_between(phi, a.b1[k]));
         }
         for (int k = 0; k < a.n2; ++k) {
-            if (swept(a.b2[k])) mask |= 1 << k;
+            if (swept(a.b2[k]))
+                mask |= 1 << k;
+            else
+                lng |= 1 << (kInfoResLong + k);
             on_bad = on_bad || angle_between(phi, a.b2[k]) == 0.0;
             delta = fmin(delta, angle_between(phi, a.b2[k]));
         }
@@ -139,22 +164,25 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign, int 
             rot = kSingular;
         } else if (mask != 0 && !past1) {
             rot = kYRes;
-            *res_sign = phi > 0.0 ? 1 : -1;
         } else if (past1 && mask == 0 && a.mirror_ok) {
             rot = kMirror;
         } else {
-            rot = kSingular;
+            rot = a.dim == 3 ? kSingular : kLong;
         }
-        if (rot != kYRes) mask = 0;
     }
-    if (v < a.vstar) {
-        if (v < kRNear * a.vstar || 1.0 - v / a.vstar >= kRSlope * delta || rot == kSingular) {
-            *res_sign = 0;
-            if (res_mask) *res_mask = 0;
+    const bool r_valid = v < a.vstar;
+    if (r_valid) {
+        if (v < kRNear * a.vstar || 1.0 - v / a.vstar >= kRSlope * delta || rot == kSingular ||
+            rot == kLong) {
+            if (info) *info = kInfoRValid;
             return kR;
         }
     }
-    if (res_mask) *res_mask = mask;
+    if (rot == kYRes || rot == kLong || rot == kMirror) *res_sign = phi > 0.0 ? 1 : -1;
+    if (info)
+        *info = rot == kYRes ? mask
+                : (rot == kLong || rot == kMirror) ? (mask | lng | (r_valid ? kInfoRValid : 0))
+                                                   : 0;
     return rot;
 }
 
@@ -168,9 +196,18 @@ struct PointCtx {
     double phi;
     int nodes;  // contour nodes of this point
     int res_sign;
-    int res_mask;  // pole sums: the k-leg poles whose residue node is due
+    int info;      // the contour's pole sets, packed as by classify
     double tb[5];  // split radial rule: piece boundaries in t = log(1+r)
 };
+
+// (p-k)-leg poles whose terms rotate the short way, given the packed sets
+// (all of them for kY and kYRes; a single pole counts as pole 0).
+template <bool POLES, class Args>
+__device__ __forceinline__ int short_group(const Args &a, int info)
+{
+    const int all = POLES ? (1 << a.n1) - 1 : 1;
+    return all & ~(info >> kInfoGrpLong & 0xFF);
+}
 
 // Split radial rule: the straight part [0, T] in t = log(1+r) is cut at the
 // radii where the integrand is nearly singular -- |(sqrt x +- sqrt(-m1^2))^2|,
@@ -217,19 +254,19 @@ __device__ void split_boundaries(const Args &a, double xr, double xi, double *b)
 
 template <bool SPLIT = false, bool POLES = false, class Args>
 __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, int res_sign,
-                                int res_mask = 1)
+                                int info = 0)
 {
     PointCtx P;
     P.x1 = mk(xr + a.m1_re, xi + a.m1_im);
     P.res_sign = res_sign;
-    P.res_mask = res_mask;
+    P.info = info;
     if (SPLIT) {
         double b[5];
         split_boundaries(a, xr, xi, b);
 #pragma unroll
         for (int i = 0; i < 5; ++i) P.tb[i] = b[i];
     }
-    if (cls == kY || cls == kYRes) {
+    if (cls == kY || cls == kYRes || cls == kLong) {
         double phi = atan2(xi, xr);
         double s, c;
         sincos(phi, &s, &c);
@@ -243,7 +280,13 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
             P.dirD = P.dir;
         }
         P.phi = phi;
-        P.nodes = a.n_r + a.n_arc + (cls == kYRes ? (POLES ? __popc(res_mask) : 1) : 0);
+        // the closing arcs (short, long or both) and the residue nodes of
+        // each rotation; the short rotation's residues need its terms
+        const int grp_long = info >> kInfoGrpLong & 0xFF, grp_short = short_group<POLES>(a, info);
+        if (!grp_short) P.info &= ~0xFF;
+        const int arcs = grp_long && grp_short ? 2 : 1;
+        P.nodes = a.n_r + arcs * a.n_arc + __popc(P.info & 0xFF) +
+                  __popc(P.info >> kInfoResLong & 0xFF);
     } else {
         P.dir = mk(1.0, 0.0);
         P.dirD = P.dir;
@@ -317,26 +360,44 @@ __device__ __forceinline__ void radial_coeffs(const Args &a, const PointCtx &P, 
         w = cdiv(cscale(P.dirD, g), cadd(y, mk(a.m2_re, a.m2_im)));
 }
 
-// Node k >= n_r: the arc |y| = Lambda^2, then the residue nodes.
+// Node k >= n_r: the closing arcs |y| = Lambda^2, then the residue nodes
+// (returns true for a residue node); *set flags the (p-k)-leg poles whose
+// terms the node belongs to.  The short
+// arc runs from phi back to 0 through the half plane of x, the long arc
+// (kLong) from phi on to +-2 pi through the other one; the short rotation's
+// residues carry the sign of phi, the long rotation's the opposite sign.
 template <bool POLES, class Args>
-__device__ __forceinline__ void outer_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
-                                             cd &V2, cd &w)
+__device__ __forceinline__ bool outer_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
+                                             cd &V2, cd &w, int &set)
 {
     const cd m2 = mk(a.m2_re, a.m2_im);
     const cd x4 = mk(4.0 * (P.x1.r - a.m1_re), 4.0 * (P.x1.i - a.m1_im));
-    if (k < a.n_r + a.n_arc) {
-        const int q = k - a.n_r;
+    const int grp_long = P.info >> kInfoGrpLong & 0xFF, grp_short = short_group<POLES>(a, P.info);
+    const int arcs = grp_long && grp_short ? 2 : 1;
+    const int q = k - a.n_r;
+    if (q < arcs * a.n_arc) {
+        const bool second = q >= a.n_arc;
+        const int i = second ? q - a.n_arc : q;
+        const bool lng = second || !grp_short;
+        set = lng ? grp_long : grp_short;
         const auto *arc = ro(a.arc);
-        const double xi = arc[q];
-        const double wa = arc[a.n_arc + q];
-        const double psi = 0.5 * P.phi * (1.0 - xi);     // from phi back to 0
+        const double xi = arc[i];
+        const double wa = arc[a.n_arc + i];
+        double psi, h;
+        if (!lng) {
+            psi = 0.5 * P.phi * (1.0 - xi);                // from phi back to 0
+            h = -0.5 * P.phi * wa;
+        } else {
+            const double L = (P.phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - P.phi;
+            psi = fma(0.5 * L, 1.0 + xi, P.phi);           // from phi on to +-2 pi
+            h = 0.5 * L * wa;
+        }
         double s, c;
         sincos(psi, &s, &c);
         const cd y = mk(a.lam2 * c, a.lam2 * s);
         U = cadd(P.x1, y);
         V2 = cmul(x4, y);
-        const double h = 0.5 * P.phi * wa;
-        const cd dy = mk(y.i * h, -y.r * h);              // dy = -i y (phi/2) dxi
+        const cd dy = mk(-y.i * h, y.r * h);              // dy = i y psi'(xi) dxi
         cd f = y;                                         // y^{(D-2)/2}
         if (a.dim == 3) {
             sincos(0.5 * psi, &s, &c);
@@ -348,39 +409,51 @@ __device__ __forceinline__ void outer_coeffs(const Args &a, const PointCtx &P, i
             w = cmul(cmul(dy, f), prop2(a, y));
         else
             w = cdiv(cmul(dy, f), cadd(y, m2));
-    } else if (!POLES) {
+        return false;
+    }
+    // residue node j: the short rotation's flagged k-leg poles, then the long one's
+    int j = q - arcs * a.n_arc;
+    const int rs = P.info & 0xFF, rl = P.info >> kInfoResLong & 0xFF;
+    const int ns = __popc(rs);
+    int m = rs, sg = P.res_sign;
+    set = grp_short;
+    if (j >= ns) {
+        j -= ns;
+        m = rl;
+        sg = -sg;
+        set = grp_long;
+    }
+    const double f = sg * 2.0 * M_PI;                     // +-2 pi i Res
+    if (!POLES) {
         const cd y0 = mk(-a.m2_re, -a.m2_im);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
-        const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i Res
         const cd fy = a.dim == 4 ? y0 : (a.dim == 3 ? mk(a.sy0_re, a.sy0_im) : mk(1.0, 0.0));
         w = mk(-fy.i * f, fy.r * f);
     } else {
-        // residue node j: the j-th k-leg pole flagged in res_mask
-        const int j = k - a.n_r - a.n_arc;
-        int m = P.res_mask;
         for (int it = 0; it < j; ++it) m &= m - 1;  // drop the j lowest flags
         const int b = m ? __ffs(m) - 1 : 0;
-        const auto *q = &a.p2[4 * b];
-        const cd y0 = mk(-q[0], -q[1]);
+        const auto *q2 = &a.p2[4 * b];
+        const cd y0 = mk(-q2[0], -q2[1]);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
-        const double f = P.res_sign * 2.0 * M_PI;        // +-2 pi i c2_b y0^{(D-2)/2}
-        const cd fy = cmul(mk(q[2], q[3]), a.dim == 4 ? y0
-                                           : (a.dim == 3 ? csqrt_principal(y0.r, y0.i)
-                                                         : mk(1.0, 0.0)));
-        w = mk(-fy.i * f, fy.r * f);
+        const cd fy = cmul(mk(q2[2], q2[3]), a.dim == 4 ? y0
+                                             : (a.dim == 3 ? csqrt_principal(y0.r, y0.i)
+                                                           : mk(1.0, 0.0)));
+        w = mk(-fy.i * f, fy.r * f);                      // +-2 pi i c2_b y0^{(D-2)/2}
     }
+    return true;
 }
 
 template <bool SPLIT = false, bool POLES = false, class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V2, cd &w)
 {
+    int set;
     if (k < a.n_r)
         radial_coeffs<SPLIT, POLES>(a, P, k, U, V2, w);
     else
-        outer_coeffs<POLES>(a, P, k, U, V2, w);
+        outer_coeffs<POLES>(a, P, k, U, V2, w, set);
 }
 
 // Angular sum A = sum_j w_j / (U - V z_j) over the GC-II rule.  The rule is
@@ -619,13 +692,14 @@ __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 }
 
 // Pole sums: <P1(D1)> = sum_a c1_a <1/(U_a - V z)>, U_a = U + m1_a^2 - m1_0^2
-// (U carries pole 0); one folded angular sum per pole.
+// (U carries pole 0); one folded angular sum per pole of `set`.
 template <int PREC, bool POLES, class Args>
-__device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2)
+__device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set = ~0)
 {
     if (!POLES) return angular_sum<PREC>(a, U, V2);
     cd A = mk(0.0, 0.0);
     for (int p = 0; p < a.n1; ++p) {
+        if (!(set >> p & 1)) continue;
         const auto *q = &a.p1[4 * p];
         const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
         A = cadd(A, cmul(mk(q[2], q[3]), angular_sum<PREC>(a, Ua, V2)));

@@ -124,18 +124,19 @@ __device__ void cut_walk_straight(CutWalk &w, int n, double T)
     }
 }
 
-// Samples along the arc, psi_k = phi (1 - k/(n-1)), k = 0..n-1: the unit
-// vector rotates by e^{-i phi/(n-1)} per sample, taken afresh from sincos every
-// 64 samples.
-__device__ void cut_walk_arc(CutWalk &w, int n, double phi)
+// Samples along an arc from angle phi, psi_k = phi + span k/(n-1), k = 0..n-1
+// (span = -phi: back to 0 the short way; the long way: to +-2 pi): the unit
+// vector rotates by e^{i span/(n-1)} per sample, taken afresh from sincos
+// every 64 samples.
+__device__ void cut_walk_arc(CutWalk &w, int n, double phi, double span)
 {
-    const double dpsi = phi / (n - 1);
+    const double dpsi = span / (n - 1);
     double s, c;
-    sincos(-dpsi, &s, &c);
+    sincos(dpsi, &s, &c);
     const cd rot = mk(c, s);
     cd e = mk(1.0, 0.0);
     for (int k = 0; k < n; ++k) {
-        const double psi = fma(-(double)k, dpsi, phi);
+        const double psi = fma((double)k, dpsi, phi);
         if ((k & 63) == 0) {
             sincos(psi, &s, &c);
             e = mk(c, s);
@@ -169,9 +170,12 @@ __device__ bool cut_hits_real_axis(const ScanArgs &a, double xr, double xi, int 
     return w.hit;
 }
 
-// Ray at phi = arg x (same t samples), then the arc psi = phi (1 - k/(n-1)),
-// k = 0..n-1, which starts where the ray ends.
-__device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n, double T)
+// Ray at phi = arg x (same t samples), then the closing arc, which starts
+// where the ray ends: psi = phi (1 - k/(n-1)), k = 0..n-1, back to 0 the
+// short way, or (the long way round) psi = phi + L k/(n-1),
+// L = sign(phi) 2 pi - phi.
+__device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n, double T,
+                                 bool long_way)
 {
     CutWalk w = cut_walk_begin(a, xr, xi);
     const double phi = atan2(xi, xr);
@@ -181,7 +185,7 @@ __device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n,
     cut_walk_straight(w, n, T);
     w.arc = true;
     w.started = false;
-    cut_walk_arc(w, n, phi);
+    cut_walk_arc(w, n, phi, long_way ? (phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - phi : -phi);
     return w.hit;
 }
 
@@ -199,21 +203,23 @@ __global__ void __launch_bounds__(64) obstruction_kernel(ScanArgs a, int n, doub
     const double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
     const double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
     const bool real_hit = cut_hits_real_axis(a, xr, xi, n, T);
-    int sign = 0;
-    int cls = classify(a, xr, xi, &sign);
+    int sign = 0, info = 0;
+    int cls = classify(a, xr, xi, &sign, &info);
     double ei = xi;
     int ecls = cls;
-    if (cls == kMirror) {  // the scan evaluates the conjugate point
-        ei = -xi;
-        ecls = classify(a, xr, ei, &sign);
-        if (ecls == kMirror || ecls == kSingular) cls = kSingular;
+    if (cls == kMirror) {  // the scan evaluates the conjugate point, if it has a contour
+        ecls = classify(a, xr, -xi, &sign);
+        if (ecls == kMirror || ecls == kSingular || ecls == kLong)
+            cls = ecls = (info & kInfoRValid) ? kR : (a.dim == 3 ? kSingular : kLong);
+        else
+            ei = -xi;
     }
     int v = real_hit ? 1 : 0;
     if (cls == kSingular) {
         v |= 4;
     } else {
         const bool used_hit = ecls == kR ? (ei == xi ? real_hit : cut_hits_real_axis(a, xr, ei, n, T))
-                                         : cut_hits_ray_arc(a, xr, ei, n, T);
+                                         : cut_hits_ray_arc(a, xr, ei, n, T, ecls == kLong);
         if (used_hit) v |= 2;
     }
     out[(size_t)ib * (size_t)a.n_re + (size_t)ia] = (uint8_t)v;

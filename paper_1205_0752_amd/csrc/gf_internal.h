@@ -13,7 +13,7 @@
 namespace gf {
 
 // Contour classes (same values as GF_CLASS_*).
-enum : int { kR = 0, kY = 1, kYRes = 2, kMirror = 3, kSingular = 4 };
+enum : int { kR = 0, kY = 1, kYRes = 2, kMirror = 3, kSingular = 4, kLong = 5 };
 
 // Region-R preference: take the real-axis contour where it is valid and
 // either |Im sqrt x| < kRNear * v*, or 1 - |Im sqrt x| / v* >= kRSlope * delta

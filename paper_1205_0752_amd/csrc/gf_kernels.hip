@@ -39,18 +39,25 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 
     double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
     double xi = fma((double)ib + 0.5, a.d_im, a.im_lo);
-    int sign = 0, mask = 1;
-    int cls = valid ? classify<POLES>(a, xr, xi, &sign, &mask) : kSingular;
+    int sign = 0, info = 0;
+    int cls = valid ? classify<POLES>(a, xr, xi, &sign, &info) : kSingular;
     int ecls = cls;
     if (cls == kMirror) {
-        xi = -xi;  // evaluate at conj x, conjugate the result
-        ecls = classify<POLES>(a, xr, xi, &sign, &mask);
-        if (ecls == kMirror || ecls == kSingular) {
-            cls = kSingular;
-            ecls = kSingular;
+        // evaluate at conj x and conjugate the result; if conj x has no
+        // contour of its own, the real axis where it is valid at x, else the
+        // long way round at x (info holds its sets)
+        int sign_b = 0, info_b = 0;
+        ecls = classify<POLES>(a, xr, -xi, &sign_b, &info_b);
+        if (ecls == kMirror || ecls == kSingular || ecls == kLong) {
+            cls = ecls = (info & kInfoRValid) ? kR : (a.dim == 3 ? kSingular : kLong);
+            if (cls == kR) sign = info = 0;
+        } else {
+            xi = -xi;
+            sign = sign_b;
+            info = info_b;
         }
     }
-    const PointCtx pc = point_setup<SPLIT, POLES>(a, xr, xi, ecls, sign, mask);
+    const PointCtx pc = point_setup<SPLIT, POLES>(a, xr, xi, ecls, sign, info);
 
     // The straight part's nodes, then the arc and residue nodes, in one
     // sequence k = s, s + L, ... per lane: two loops so that the arc's sine
@@ -68,8 +75,13 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
     }
     for (; k < pc.nodes; k += L) {
         cd U, V2, w;
-        outer_coeffs<POLES>(a, pc, k, U, V2, w);
-        cd A = angular_sum_p<PREC, POLES>(a, U, V2);
+        int set;
+        // a residue node carries a whole 2 pi i Res with no quadrature weight
+        // to shrink it, and its k-leg pole can sit near the angular cut: its
+        // angular sum is taken in FP64 in every precision
+        const bool res = outer_coeffs<POLES>(a, pc, k, U, V2, w, set);
+        cd A = PREC != 0 && res ? angular_sum_p<0, POLES>(a, U, V2, set)
+                                : angular_sum_p<PREC, POLES>(a, U, V2, set);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
