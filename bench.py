@@ -7,6 +7,12 @@ the C ABI (gf_scan_plan) with the plan and the output buffer already resident
 on the device.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Besides the headline line's timed scans it reports, on the same box: the
+scan-latency percentiles of 200 individually timed scans, the FP32C leg, the
+diagnostics and extensions, serving (capacity, then 10,000-request Poisson
+traces offered at 50 % and 80 % of it), and the CPU oracle leg (timing, and
+the FP32C and FP64 scans' errors against the oracle per band).
 """
 from __future__ import annotations
 
@@ -32,7 +38,15 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
 FLOPS_PER_EVAL = 6.5
 
 
+# The survey's count for one unfolded angular term D = U - V z, |D|^2, w/|D|^2,
+# acc += t conj(D): 13 flops.  The kernel folds each symmetric pair into one
+# denominator, so that count prices twice the work the kernel does per
+# evaluation; it is reported beside the folded count, as a fraction of peak
+# that can exceed 1.
+FLOPS_PER_EVAL_UNFOLDED = 13.0
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_kernel_fp64_bench_workload_traffic.json")
+FLOPS_FILE = os.path.join(ROOT, "profiles", "scan_kernel_fp64_bench_workload_flops.json")
 # the sources that define the scan kernels' machine code
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1205_0752_amd", "csrc", name)
                   for name in ("gf_internal.h", "gf_device.h", "gf_kernels.hip")]
@@ -61,6 +75,40 @@ def measured_traffic(kernel: str):
     if rec.get("kernel") != kernel or rec.get("kernels_source_sha256") != sha:
         return None
     return float(rec["traffic_bytes_per_launch"])
+
+
+def measured_flops(kernel: str):
+    """Hardware FP64 flops per launch of `kernel` (SQ_INSTS_VALU_FLOPS_FP64 x 64
+    lanes, one rocprofv3 --pmc run) from the committed summary, or None when
+    there is none for this kernel or its sources have changed since."""
+    try:
+        with open(FLOPS_FILE) as f:
+            rec = json.load(f)
+        sha = kernel_source_sha256()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("kernels_source_sha256") != sha:
+        return None
+    return float(rec["fp64_flops_per_launch"])
+
+
+def roofline_conventions(evals: int, sec: float, peak: float, kernel: str):
+    """The dominant kernel's FLOP rate and fraction of the FP64 vector peak
+    under three counts: the folded pair (6.5 flops per evaluation, the
+    `roofline` figure), the survey's unfolded term (13), and the hardware's
+    own FP64 flop counter from the committed profile."""
+    out = {}
+    for name, fpe in (("folded_pair", FLOPS_PER_EVAL), ("unfolded_term", FLOPS_PER_EVAL_UNFOLDED)):
+        tf = evals * fpe / sec / 1e12
+        out[name] = {"flops_per_eval": fpe, "achieved_tflops": tf, "frac": tf / peak}
+    hw = measured_flops(kernel)
+    if hw is not None:
+        tf = hw / sec / 1e12
+        out["hardware_counter"] = {"flops_per_eval": hw / evals, "achieved_tflops": tf,
+                                   "frac": tf / peak, "source": os.path.relpath(FLOPS_FILE, ROOT)}
+    else:
+        out["hardware_counter"] = None
+    return out
 
 
 def evals_per_scan(cls, quad) -> int:
@@ -114,6 +162,43 @@ def cpu_baseline(params, quad, grid, seconds: float):
     return out
 
 
+def errors_vs_oracle(params, grid, quad, g32, g64, n_other=4000, seed=13):
+    """The FP32C and FP64 scans of the mixed-precision workload (same grid and
+    nodes) against the FP64 oracle, max and mean abs/rel error, separately at
+    every point within 0.05 of the cut x < -(m1 + m2)^2 and at n_other random
+    points elsewhere (part of the CPU leg: the oracle runs on the host)."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    d_re = (grid.re_hi - grid.re_lo) / grid.n_re
+    d_im = (grid.im_hi - grid.im_lo) / grid.n_im
+    a = np.arange(grid.n_re)
+    b = np.arange(grid.n_im)
+    xr = np.broadcast_to(grid.re_lo + (a[None, :] + 0.5) * d_re, (grid.n_im, grid.n_re)).ravel()
+    xi = np.broadcast_to(grid.im_lo + (b[:, None] + 0.5) * d_im, (grid.n_im, grid.n_re)).ravel()
+    thr = (abs(complex(params.m1sq)) ** 0.5 + abs(complex(params.m2sq)) ** 0.5) ** 2
+    band = np.nonzero((np.abs(xi) < 0.05) & (xr < -thr))[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    other = np.setdiff1d(rng.choice(grid.n_points, n_other + band.size, replace=False), band)[:n_other]
+    t = time.perf_counter()
+    rep = {}
+    for name, idx in (("cut_band", band), ("elsewhere", np.sort(other))):
+        x = oracle.grid_points_at(grid, idx)
+        go, _ = oracle.eval_points(params, quad, x)
+        ok = np.isfinite(go)
+        for prec, g in (("fp32c", g32), ("fp64", g64)):
+            err = np.abs(g[idx][ok] - go[ok])
+            rel = err / np.abs(go[ok])
+            rep.setdefault(prec, {})[name] = {
+                "points": int(ok.sum()), "max_abs": float(err.max()), "mean_abs": float(err.mean()),
+                "max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
+                "max_over_fp32_bar": float(np.max(err / (1e-6 * np.maximum(np.abs(go[ok]), 1.0))))}
+    rep["oracle_seconds"] = time.perf_counter() - t
+    rep["sample"] = (f"all {band.size} points of the cut band and {other.size} random points "
+                     f"elsewhere of {grid.n_re}x{grid.n_im}")
+    return rep
+
+
 def cpu_worker(n_points: int) -> int:
     """Child of cpu_baseline: times the oracle on `n_points` random points of the
     bench grid and prints one JSON object (never touches the GPU)."""
@@ -143,7 +228,7 @@ def scan_kernel_name(params, quad, lanes, props=None):
             f"{b(split)}, {b(poles)}>")
 
 
-def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None):
+def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None, latency_scans=0):
     """Times `steps` scans with HIP events on the launch stream (one event
     between consecutive scans, so each scan's duration is known as well as the
     mean); the plan and the output buffer are resident before timing starts.
@@ -168,16 +253,29 @@ def time_scan(gf, torch, params, grid, quad, steps, warmup, lanes, props=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = evs[0].elapsed_time(evs[-1]) / steps
-    per_scan = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    # scan latency: a separate sample of back-to-back scans, each between its
+    # own pair of events (after the timed region)
+    n_lat = max(latency_scans, 0)
+    lat = []
+    if n_lat:
+        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat + 1)]
+        ev2[0].record(stream)
+        for i in range(n_lat):
+            gf.scan_plan(plan, grid, out, lanes=lanes, stream=stream)
+            ev2[i + 1].record(stream)
+        torch.cuda.synchronize()
+        lat = sorted(ev2[i].elapsed_time(ev2[i + 1]) for i in range(n_lat))
     plan.close()
     sec = ms / 1e3
-    return {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
-            "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
-            "wall": wall, "lanes": used_lanes,
-            "latency_ms": {"p50": per_scan[(steps - 1) // 2],
-                           "p99": per_scan[min(steps - 1, math.ceil(0.99 * steps) - 1)],
-                           "max": per_scan[-1]},
-            "kernel": scan_kernel_name(params, quad, used_lanes, props)}
+    res = {"ms": ms, "evals": evals, "evals_per_s": evals / sec,
+           "points_per_s": grid.n_points / sec, "tflops": evals * FLOPS_PER_EVAL / sec / 1e12,
+           "wall": wall, "lanes": used_lanes, "sec": sec,
+           "kernel": scan_kernel_name(params, quad, used_lanes, props)}
+    if lat:
+        res["latency_ms"] = {"scans": n_lat, "p50": lat[(n_lat - 1) // 2],
+                             "p99": lat[min(n_lat - 1, math.ceil(0.99 * n_lat) - 1)],
+                             "max": lat[-1]}
+    return res
 
 
 def time_launches(torch, fn, reps):
@@ -265,6 +363,7 @@ def fp32c_errors(gf, torch, params, grid, quad):
         torch.cuda.synchronize()
         plan.close()
     g32, g64 = (o.cpu().numpy().ravel() for o in outs)
+    arrays = (g32, g64)
     a = np.arange(grid.n_re)
     b = np.arange(grid.n_im)
     xr = np.broadcast_to(grid.re_lo + (a[None, :] + 0.5) * (grid.re_hi - grid.re_lo) / grid.n_re,
@@ -283,7 +382,30 @@ def fp32c_errors(gf, torch, params, grid, quad):
                      "mean_abs": float(err.mean()), "max_rel": float(rel.max()),
                      "mean_rel": float(rel.mean()),
                      "frac_rel_le_1e-6": float(np.mean(rel <= 1e-6))}
-    return rep
+    return rep, arrays
+
+
+def evals_from_class_maps(gf, reqs) -> int:
+    """Integrand evaluations the served requests took, counted from each
+    request's class map (evals_per_scan with the request's own node counts).
+    The class of a point does not depend on the node counts, so the maps come
+    from scans of the same parameters and grids with the smallest quadrature
+    (after the trace, outside its timing)."""
+    import torch
+    from paper_1205_0752_amd.workloads import Quadrature
+    n_max = max(r.grid.n_points for r in reqs)
+    out = torch.empty(n_max, dtype=torch.complex128, device="cuda")
+    cls = torch.empty(n_max, dtype=torch.int8, device="cuda")
+    tiny = Quadrature(1, 2, 1)
+    total = 0
+    for r in reqs:
+        n = r.grid.n_points
+        plan = gf.Plan(r.params, tiny)
+        gf.scan_plan(plan, r.grid, out[:n].view(r.grid.n_im, r.grid.n_re),
+                     cls[:n].view(r.grid.n_im, r.grid.n_re))
+        total += evals_per_scan(cls[:n].cpu().numpy(), r.quad)
+        plan.close()
+    return total
 
 
 def serve_trace(gf, n_requests, rate, budget_bytes, seed=0):
@@ -312,16 +434,24 @@ def serve_trace(gf, n_requests, rate, budget_bytes, seed=0):
         wall = time.perf_counter() - t0
         st = srv.stats()
     span = st["first_submit_to_last_done_s"]
+    served_evals = evals_from_class_maps(gf, reqs)
     return {"requests": n_requests, "arrival_rate_per_s": rate, "seed": seed,
             "completed": st["completed"], "wall_s": wall,
             "throughput_req_per_s": st["completed"] / span,
             "points_per_s": st["points_done"] / span,
+            "evals_per_s": served_evals / span,
+            "evals_served": served_evals,
             "nominal_evals_per_s": st["nominal_evals_done"] / span,
             "latency_ms": {"mean": st["latency_mean_ms"], "p50": st["latency_p50_ms"],
                            "p90": st["latency_p90_ms"], "p99": st["latency_p99_ms"],
                            "max": st["latency_max_ms"]},
             "max_submit_lag_ms": lag * 1e3, "batches": st["batches"],
             "device_budget_bytes": st["bytes_budget"], "peak_bytes": st["bytes_peak"]}
+
+
+def progress(msg: str) -> None:
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main() -> int:
@@ -337,8 +467,11 @@ def main() -> int:
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-extensions", action="store_true",
                     help="skip the y-plane scan, obstruction map and tanh-sinh measurements")
-    ap.add_argument("--serve-requests", type=int, default=6000)
-    ap.add_argument("--serve-rate", type=float, default=1180.0, help="Poisson arrivals per second")
+    ap.add_argument("--latency-scans", type=int, default=200,
+                    help="individually timed scans for the scan-latency percentiles")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-loads", default="0.5,0.8",
+                    help="offered Poisson rates as fractions of the measured capacity")
     ap.add_argument("--serve-budget", type=int, default=1 << 30, help="device bytes")
     ap.add_argument("--profile-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
@@ -371,7 +504,10 @@ def main() -> int:
 
     params, grid, quad = CONFIGS[args.config]
     torch.cuda.set_device(0)
-    t = time_scan(gf, torch, params, grid, quad, args.steps, args.warmup, args.lanes)
+    t = time_scan(gf, torch, params, grid, quad, args.steps, args.warmup, args.lanes,
+                  latency_scans=args.latency_scans)
+    peak = FP64_PEAK_TFLOPS if quad.precision == 0 else FP32_PEAK_TFLOPS
+    progress(f"timed scans: {t['ms']:.3f} ms per step")
     result = {
         "metric": "complex grid points/s & integrand evals/s (FP64 vs FP32+compensated); "
                   "p99 scan latency",
@@ -393,7 +529,7 @@ def main() -> int:
                    "grid_points": grid.n_points, "evals_per_step": t["evals"],
                    "lanes_per_point": t["lanes"], "parallelism": "single GPU"},
         "points_per_s": t["points_per_s"],
-        "scan_latency_ms": t["latency_ms"],
+        "scan_latency_ms": t.get("latency_ms"),
         "wall_s_timed": t["wall"],
         "roofline": {"bound": "alu", "achieved": t["tflops"],
                      "peak": FP64_PEAK_TFLOPS if quad.precision == 0 else FP32_PEAK_TFLOPS,
@@ -402,32 +538,54 @@ def main() -> int:
                                             else FP32_PEAK_TFLOPS),
                      "traffic": (measured_traffic(t["kernel"])
                                  if args.config == "c1_fp64_1024sq" else None),
-                     "kernel": t["kernel"], "flops_per_eval": FLOPS_PER_EVAL},
+                     "kernel": t["kernel"], "flops_per_eval": FLOPS_PER_EVAL,
+                     "conventions": (roofline_conventions(t["evals"], t["sec"], peak, t["kernel"])
+                                     if quad.precision == 0 else None)},
+        # the paper's Table 1 ("Execution time"): total running time of its
+        # program for one unstated parameter set -- context, not a target
+        "paper_context": {"table1_total_runtime": {
+            "Intel Xeon X5650, one core": "252 min 2 s", "NVIDIA GeForce GTX 550 Ti": "6 min 21 s",
+            "NVIDIA GeForce GTX 480": "4 min 21 s", "NVIDIA Tesla C2070": "2 min 38 s"},
+            "workload": "unstated; grid fill, per-point quadrature and host transfers",
+            "precision": "not stated"},
     }
     if not args.skip_fp32c and args.config == "c1_fp64_1024sq":
         p2, g2, q2 = CONFIGS["c2_fp32c_1024sq"]
         t2 = time_scan(gf, torch, p2, g2, q2, max(2, args.steps // 2), 1, 0)
+        err_fp64, fp32c_arrays = fp32c_errors(gf, torch, p2, g2, q2)
+        progress(f"fp32c leg: {t2['ms']:.3f} ms per step")
         result["fp32c"] = {"workload": f"c2_fp32c_1024sq: {g2.n_re}x{g2.n_im} grid, "
                                        f"{q2.n_radial}x{q2.n_angular}(+{q2.n_arc} arc) nodes",
                            "evals_per_s": t2["evals_per_s"], "points_per_s": t2["points_per_s"],
-                           "ms_per_step": t2["ms"], "scan_latency_ms": t2["latency_ms"],
+                           "ms_per_step": t2["ms"],
                            "tflops": t2["tflops"],
                            "frac_of_fp32_peak": t2["tflops"] / FP32_PEAK_TFLOPS,
                            "frac_of_fp32_nonpacked": t2["tflops"] / FP64_PEAK_TFLOPS,
                            "lanes_per_point": t2["lanes"], "kernel": t2["kernel"],
-                           "error_vs_fp64": fp32c_errors(gf, torch, p2, g2, q2)}
+                           "error_vs_fp64": err_fp64}
     if not args.skip_extensions and args.config == "c1_fp64_1024sq":
         result["extensions"] = extensions(gf, torch)
+        progress("extensions done")
     if not args.skip_serving and args.config == "c1_fp64_1024sq":
-        result["serving"] = serve_trace(gf, args.serve_requests, args.serve_rate,
-                                        args.serve_budget)
-        # capacity: the same trace generator offered well above what the device sustains
+        # capacity: the trace generator offered well above what the device sustains
         cap = serve_trace(gf, 1500, 4000.0, args.serve_budget)
+        capacity = cap["throughput_req_per_s"]
+        progress(f"serving capacity: {capacity:.0f} requests/s")
         result["serving_capacity"] = {k: cap[k] for k in (
-            "requests", "arrival_rate_per_s", "completed", "throughput_req_per_s",
+            "requests", "arrival_rate_per_s", "completed", "throughput_req_per_s", "evals_per_s",
             "nominal_evals_per_s", "batches", "latency_ms")}
+        result["serving"] = []
+        for load in (float(v) for v in args.serve_loads.split(",") if v):
+            rec = serve_trace(gf, args.serve_requests, round(load * capacity, 1), args.serve_budget)
+            rec["offered_fraction_of_capacity"] = load
+            result["serving"].append(rec)
+            progress(f"serving at {load:.0%} of capacity: p99 {rec['latency_ms']['p99']:.1f} ms")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(params, quad, grid, args.cpu_seconds)
+        progress("cpu baseline done")
+        if "fp32c" in result:
+            p2, g2, q2 = CONFIGS["c2_fp32c_1024sq"]
+            result["fp32c"]["error_vs_oracle"] = errors_vs_oracle(p2, g2, q2, *fp32c_arrays)
     print(json.dumps(result), flush=True)
     return 0
 
