@@ -574,25 +574,40 @@ __device__ __forceinline__ void pair_sums64(const double *table, int npair, doub
     T1 = z0 + z1;
 }
 
+template <int SCALE = 1>
 __device__ __forceinline__ cd angular_sum64(const double *table, int npair, double wmid, cd U,
-                                            cd V2in)
+                                            cd V2in, bool scale_rt = true)
 {
+    // SCALE 1: always rescale; 0: never; -1: as scale_rt says
+    const bool scale = SCALE == 1 || (SCALE == -1 && scale_rt);
     // sum_j 2w_j / D_j = sum_j 2w_j conj(D_j) / |D_j|^2 with D_j = U^2 - V^2 z_j^2,
     // and conj(D_j) = conj(U^2) - conj(V^2) z_j^2, so the pair sum is
     // conj(U^2) T0 - conj(V^2) T1 with the real sums T0 = sum 2w_j / |D_j|^2 and
     // T1 = sum 2w_j z_j^2 / |D_j|^2; the table holds (z_j^2, 2w_j, 2w_j z_j^2).
+    // scale = false (wave-uniform): the magnitudes are known to be small
+    // enough that the products of eight denominators stay in range unscaled.
     const cd U2in = cmul(U, U);
-    const int e = scale_exponent(U2in, V2in);
-    const double u2r = ldexp(U2in.r, -e), u2i = ldexp(U2in.i, -e);
-    const double v2r = ldexp(V2in.r, -e), v2i = ldexp(V2in.i, -e);
+    int e = 0;
+    double u2r = U2in.r, u2i = U2in.i, v2r = V2in.r, v2i = V2in.i;
+    if (scale) {
+        e = scale_exponent(U2in, V2in);
+        u2r = ldexp(u2r, -e);
+        u2i = ldexp(u2i, -e);
+        v2r = ldexp(v2r, -e);
+        v2i = ldexp(v2i, -e);
+    }
     double T0, T1;
     if (near_cut_sq(u2r, u2i, v2r, v2i))
         pair_sums64<false>(table, npair, u2r, u2i, v2r, v2i, T0, T1);
     else
         pair_sums64<true>(table, npair, u2r, u2i, v2r, v2i, T0, T1);
     // the pair sum (scaled by 2^e): conj(U^2) T0 - conj(V^2) T1, then times U
-    const double sr = fma(u2r, T0, -(v2r * T1)), si = fma(u2i, T0, -(v2i * T1));
-    cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
+    double sr = fma(u2r, T0, -(v2r * T1)), si = fma(u2i, T0, -(v2i * T1));
+    if (scale) {
+        sr = ldexp(sr, -e);
+        si = ldexp(si, -e);
+    }
+    cd A = cmul(U, mk(sr, -si));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
     return A;
 }
@@ -678,16 +693,18 @@ __device__ __forceinline__ cd angular_sum_fp32c(const Args &a, cd U, cd V2)
     double lhs, d2vv;
     cut_measure(u2r, u2i, v2r, v2i, lhs, d2vv);
     if (lhs > kCutSensitivity * kCutSensitivity * d2vv)
-        return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+        return angular_sum64<-1>(a.ang, a.n_a / 2, a.wmid, U, V2, !a.unscaled);
     if (lhs > kQuad32Sensitivity * kQuad32Sensitivity * d2vv)
         return angular_sum32c<false>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e);
     return angular_sum32c<true>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e);
 }
 
-template <int PREC, class Args>
+// SCALE (FP64 only): -1 rescales as the launch's `unscaled` flag says; 0 or 1
+// fix it at compile time for a caller that has branched on the flag.
+template <int PREC, int SCALE = -1, class Args>
 __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 {
-    if (PREC == 0) return angular_sum64(a.ang, a.n_a / 2, a.wmid, U, V2);
+    if (PREC == 0) return angular_sum64<SCALE>(a.ang, a.n_a / 2, a.wmid, U, V2, !a.unscaled);
     return angular_sum_fp32c(a, U, V2);
 }
 

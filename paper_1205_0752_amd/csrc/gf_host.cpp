@@ -477,6 +477,14 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     tiles_for(g, lanes, &a.tiles_a, &nt);
     if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
     a.n_tiles = (int)nt;
+    // The FP64 angular sums multiply eight denominators |U^2 - V^2 s|^2 <=
+    // 25 M^4, M = |x| + |y| + |m1^2|, into one reciprocal; below M = 2^30 the
+    // product stays under 2^1000 without the rescaling by 2^-e.
+    double m1max = 0.0;
+    for (int k = 0; k < a.n1; ++k) m1max = std::max(m1max, std::hypot(a.p1[4 * k], a.p1[4 * k + 1]));
+    const double xmax = std::max(std::hypot(g.re_lo, g.im_lo), std::hypot(g.re_hi, g.im_hi));
+    const double xmax2 = std::max(std::hypot(g.re_lo, g.im_hi), std::hypot(g.re_hi, g.im_lo));
+    a.unscaled = std::max(xmax, xmax2) + a.lam2 + m1max < std::ldexp(1.0, 30) ? 1 : 0;
     return GF_OK;
 }
 

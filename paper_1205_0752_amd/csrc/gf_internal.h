@@ -68,6 +68,8 @@ struct ScanArgs {
     double re_lo, d_re, im_lo, d_im;
     int tiles_a;  // wave tiles along Re
     int n_tiles;  // total wave tiles
+    int unscaled;  // every |x| + |y| + |m1^2| of the scan is below 2^30: the FP64
+                   // angular sums skip their power-of-two rescaling
 
     double *out;   // interleaved complex128
     int8_t *cls;   // optional class map

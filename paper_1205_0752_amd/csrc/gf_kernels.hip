@@ -15,6 +15,8 @@
 // with cross-lane shuffles, the real-axis subtraction sum at mu^2 (eq. 14) is
 // removed, the result scaled, conjugated for mirror points, and written once.
 #include <atomic>
+#include <type_traits>
+
 #include "gf_device.h"
 
 namespace gf {
@@ -65,13 +67,48 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
     double sr = 0.0, si = 0.0;
     int k = s;
     const int n_straight = min(pc.nodes, a.n_r);
-    for (; k < n_straight; k += L) {
-        cd U, V2, w;
-        radial_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
-        cd A = angular_sum_p<PREC, POLES>(a, U, V2);
-        cd t = cmul(w, A);
-        sr += t.r;
-        si += t.i;
+    if (!POLES) {
+        // On the straight part y = e^{i phi} r the node weight is
+        //   dirD g / (e^{i phi} r + m2^2) = F g / (r + c),  c = m2^2 e^{-i phi},
+        // F = dirD e^{-i phi}: F comes out of the sum, and 1/(r + c) takes one
+        // real reciprocal of (r + Re c)^2 + (Im c)^2.  U = x + m1^2 + e^{i phi} r
+        // and V^2 = (4x e^{i phi}) r are one FMA or product per component.
+        // The FP64 sums skip their rescaling when the launch allows it
+        // (wave-uniform): the loop is compiled once with and once without.
+        const double cr = fma(a.m2_re, pc.dir.r, a.m2_im * pc.dir.i);
+        const double ci = fma(a.m2_im, pc.dir.r, -(a.m2_re * pc.dir.i));
+        const cd x4d = cmul(mk(4.0 * (pc.x1.r - a.m1_re), 4.0 * (pc.x1.i - a.m1_im)), pc.dir);
+        auto straight = [&](auto scale) {
+            constexpr int SC = decltype(scale)::value;
+            for (; k < n_straight; k += L) {
+                double r, g;
+                radial_node<SPLIT>(a, pc, k, r, g);
+                const cd U = mk(fma(pc.dir.r, r, pc.x1.r), fma(pc.dir.i, r, pc.x1.i));
+                const cd A = angular_sum<PREC, SC>(a, U, mk(x4d.r * r, x4d.i * r));
+                const double br = r + cr;
+                const double gq = g * rcp64(fma(br, br, ci * ci));
+                const double wr = gq * br, wi = -(gq * ci);  // g / (r + c)
+                sr = fma(wr, A.r, fma(-wi, A.i, sr));
+                si = fma(wr, A.i, fma(wi, A.r, si));
+            }
+        };
+        if (PREC == 0 && a.unscaled)
+            straight(std::integral_constant<int, 0>{});
+        else
+            straight(std::integral_constant<int, 1>{});
+        const cd F = cmul(pc.dirD, mk(pc.dir.r, -pc.dir.i));
+        const double tr = sr;
+        sr = fma(F.r, tr, -(F.i * si));
+        si = fma(F.r, si, F.i * tr);
+    } else {
+        for (; k < n_straight; k += L) {
+            cd U, V2, w;
+            radial_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
+            cd A = angular_sum_p<PREC, POLES>(a, U, V2);
+            cd t = cmul(w, A);
+            sr += t.r;
+            si += t.i;
+        }
     }
     for (; k < pc.nodes; k += L) {
         cd U, V2, w;
