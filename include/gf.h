@@ -210,6 +210,19 @@ typedef struct {
     double c1_re[GF_MAX_POLES], c1_im[GF_MAX_POLES];
     double m2sq_re[GF_MAX_POLES], m2sq_im[GF_MAX_POLES];
     double c2_re[GF_MAX_POLES], c2_im[GF_MAX_POLES];
+    /* Numerator (the tensor structure of eq. 4's general integrand): with
+     * numerator = 1 the integrand is N(k^2, p.k) P1((p-k)^2) P2(k^2),
+     *   N = sum_{i,j=0..2} num[3i + j] (k^2)^i (p.k)^j,  p.k = sqrt(x) sqrt(y) z,
+     * complex coefficients num_re/num_im; numerator = 0 means N = 1.  Each
+     * power of p.k folds exactly into the symmetric angular sums (one more
+     * real pair sum, no cancellation).  A polynomial numerator adds no
+     * singularity, so the contour classes are those of P1 P2; it is
+     * subtracted at mu^2 like the rest (taylor_order -1 or 0 only:
+     * GF_EUNSUPPORTED otherwise), and raises the integrand's growth at large
+     * y, so the subtracted integral can need the cutoff to stay finite. */
+    int32_t numerator;
+    int32_t reserved;
+    double num_re[9], num_im[9];
 } gf_propagators;
 
 /* gf_plan with general propagators: props replaces the masses of params

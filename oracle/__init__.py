@@ -35,7 +35,8 @@ class _Problem(ctypes.Structure):
                 ("n_arc", ctypes.c_int), ("angular_rule", ctypes.c_int),
                 ("taylor_order", ctypes.c_int), ("dimension", ctypes.c_int),
                 ("radial_split", ctypes.c_int), ("n1", ctypes.c_int), ("n2", ctypes.c_int),
-                ("p1", ctypes.c_double * 32), ("p2", ctypes.c_double * 32)]
+                ("p1", ctypes.c_double * 32), ("p2", ctypes.c_double * 32),
+                ("num_on", ctypes.c_int), ("num", ctypes.c_double * 18)]
 
 
 def build(verbose: bool = False) -> None:
@@ -124,6 +125,11 @@ def problem(params, quad, props=None) -> _Problem:
             for k, (m, c) in enumerate(poles):
                 m, c = complex(m), complex(c)
                 arr[4 * k], arr[4 * k + 1], arr[4 * k + 2], arr[4 * k + 3] = m.real, m.imag, c.real, c.imag
+        for i, j, c in getattr(props, "numerator", ()):
+            c = complex(c)
+            pr.num_on = 1
+            pr.num[2 * (3 * i + j)] += c.real
+            pr.num[2 * (3 * i + j) + 1] += c.imag
     return pr
 
 

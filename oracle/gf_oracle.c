@@ -79,6 +79,11 @@ typedef struct {
      * residue 1.  Per pole: m^2 re, m^2 im, c re, c im. */
     int n1, n2;
     double p1[32], p2[32];
+    /* numerator N(k^2, p.k) = sum_{i,j=0..2} n_ij (k^2)^i (p.k)^j multiplying
+     * P1 P2 (eq. 4's general integrand); num_on = 0 means N = 1.  n_ij is
+     * num[2(3i + j)] + i num[2(3i + j) + 1]. */
+    int num_on;
+    double num[18];
 } orc_problem;
 
 #define ORC_MAX_TAYLOR 8
@@ -270,6 +275,40 @@ static cplx angular_d1(cplx x, cplx y, cplx sxsy, cplx m1sq, int n,
     return acc;
 }
 
+/* The same sum with the numerator N(y, p.k) in every term, p.k = sxsy z_j:
+ * sum_j w_j N_j / D1_j.  absum adds per term |w_j|/|D1_j| times (the
+ * numerator's parts, each times its degree + 1, plus |N_j| times the
+ * denominator's sensitivity). */
+static cplx angular_d1_num(cplx x, cplx y, cplx sxsy, cplx m1sq, int n, const double *z,
+                           const double *w, const double *num, double *absum)
+{
+    cplx acc = 0.0;
+    double a = 0.0;
+    const double u_abs = absum ? cabs(x + y + m1sq) : 0.0;
+    const double v_abs = absum ? cabs(2.0 * sxsy) : 0.0;
+    for (int j = 0; j < n; ++j) {
+        cplx d1 = x + y - 2.0 * sxsy * z[j] + m1sq;
+        cplx pk = sxsy * z[j];
+        cplx nv = 0.0;
+        double nabs = 0.0;
+        for (int i = 0; i <= 2; ++i)
+            for (int q = 0; q <= 2; ++q) {
+                cplx c = num[2 * (3 * i + q)] + I * num[2 * (3 * i + q) + 1];
+                if (c == 0.0) continue;
+                cplx part = c * cpow(y, i) * cpow(pk, q);
+                nv += part;
+                nabs += cabs(part) * (1.0 + i + q);
+            }
+        acc += w[j] * nv / d1;
+        if (absum) {
+            const double dabs = cabs(d1);
+            a += fabs(w[j]) / dabs * (nabs + cabs(nv) * (u_abs + v_abs * fabs(z[j])) / dabs);
+        }
+    }
+    if (absum) *absum += a;
+    return acc;
+}
+
 /* Exported for the pin tests: sum_j w_j / (U - V z_j) with the oracle's GC-II
  * rule of order n. */
 void orc_angular_sum(double u_re, double u_im, double v_re, double v_im, int n,
@@ -367,6 +406,14 @@ static void orc_make_geometry(const orc_problem *p, orc_geometry *g)
                     orc_same_poles(g->n2, g->m2, g->c2, g->n2, g->m2, g->c2, 1)) ||
                    (orc_same_poles(g->n1, g->m1, g->c1, g->n2, g->m2, g->c2, 1) &&
                     orc_same_poles(g->n2, g->m2, g->c2, g->n1, g->m1, g->c1, 1));
+    /* with a numerator N(k^2, p.k): conjugation needs real coefficients, and
+     * the exchange k -> p - k of the legs does not leave N as it is */
+    if (p->num_on) {
+        int real = 1;
+        for (int k = 0; k < 9; ++k) real = real && p->num[2 * k + 1] == 0.0;
+        g->mirror_ok = real && orc_same_poles(g->n1, g->m1, g->c1, g->n1, g->m1, g->c1, 1) &&
+                       orc_same_poles(g->n2, g->m2, g->c2, g->n2, g->m2, g->c2, 1);
+    }
 }
 
 /* angular distance between two angles, in [0, pi] */
@@ -574,8 +621,11 @@ static cplx orc_ang_p1_set(const orc_ctx *c, cplx x, cplx y, cplx sxsy, int set,
     for (int a = 0; a < c->geo.n1; ++a) {
         if (!(set >> a & 1)) continue;
         double t = 0.0;
-        s += c->geo.c1[a] * angular_d1(x, y, sxsy, c->geo.m1[a], c->p->n_angular, c->z, c->w,
-                                       sens ? &t : NULL);
+        s += c->geo.c1[a] *
+             (c->p->num_on ? angular_d1_num(x, y, sxsy, c->geo.m1[a], c->p->n_angular, c->z, c->w,
+                                            c->p->num, sens ? &t : NULL)
+                           : angular_d1(x, y, sxsy, c->geo.m1[a], c->p->n_angular, c->z, c->w,
+                                        sens ? &t : NULL));
         if (sens) *sens += cabs(c->geo.c1[a]) * t;
     }
     return s;

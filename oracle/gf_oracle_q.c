@@ -27,6 +27,8 @@ typedef struct {
     int radial_split;   /* only 0 is implemented here */
     int n1, n2;         /* only 0 (single poles) is implemented here */
     double p1[32], p2[32];
+    int num_on;         /* only 0 (no numerator) is implemented here */
+    double num[18];
 } orcq_problem;   /* same layout as the FP64 oracle's problem struct */
 
 #define QPI M_PIq
@@ -295,7 +297,7 @@ int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const do
     c.vstar = crealq(csqrtq(c.m1sq));
     c.mirror_ok = (p->m1sq_im == 0 && p->m2sq_im == 0) ||
                   (p->m1sq_re == p->m2sq_re && p->m1sq_im == -p->m2sq_im);
-    if (p->radial_split || p->n1 > 1 || p->n2 > 1 || p->taylor_order < -1 ||
+    if (p->radial_split || p->n1 > 1 || p->n2 > 1 || p->num_on || p->taylor_order < -1 ||
         p->taylor_order > 8)
         return -1;
     c.dim = p->dimension == 0 ? 4 : p->dimension;

@@ -66,7 +66,9 @@ class _Props(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32)] + [
         (name, ctypes.c_double * MAX_POLES)
         for name in ("m1sq_re", "m1sq_im", "c1_re", "c1_im", "m2sq_re", "m2sq_im", "c2_re",
-                     "c2_im")]
+                     "c2_im")] + [
+        ("numerator", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("num_re", ctypes.c_double * 9), ("num_im", ctypes.c_double * 9)]
 
 
 def c_props(props):
@@ -83,6 +85,15 @@ def c_props(props):
     for k, (m, c) in enumerate(props.poles2):
         m, c = complex(m), complex(c)
         r.m2sq_re[k], r.m2sq_im[k], r.c2_re[k], r.c2_im[k] = m.real, m.imag, c.real, c.imag
+    num = getattr(props, "numerator", ())
+    if num:
+        r.numerator = 1
+        for i, j, c in num:
+            if not (0 <= i <= 2 and 0 <= j <= 2):
+                raise ValueError("numerator powers i, j must lie in 0..2")
+            c = complex(c)
+            r.num_re[3 * i + j] += c.real
+            r.num_im[3 * i + j] += c.imag
     return r
 
 

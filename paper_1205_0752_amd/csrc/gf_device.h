@@ -445,6 +445,21 @@ __device__ __forceinline__ bool outer_coeffs(const Args &a, const PointCtx &P, i
     return true;
 }
 
+// The numerator's polynomials in y = k^2 at a node (pole sums with a.num):
+// N_j(y) = sum_i n_ij y^i for the powers j = 0, 1, 2 of p.k; y = U - (x + m1^2).
+template <class Args>
+__device__ __forceinline__ void numerator_at(const Args &a, cd U, cd x1, cd *N)
+{
+    const cd y = mk(U.r - x1.r, U.i - x1.i);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const auto *c = &a.nc[2 * j];  // n_ij at 2 (3i + j)
+        cd v = mk(c[12], c[13]);       // i = 2
+        v = cadd(cmul(v, y), mk(c[6], c[7]));
+        N[j] = cadd(cmul(v, y), mk(c[0], c[1]));
+    }
+}
+
 template <bool SPLIT = false, bool POLES = false, class Args>
 __device__ __forceinline__ void node_coeffs(const Args &a, const PointCtx &P, int k, cd &U,
                                             cd &V2, cd &w)
@@ -514,10 +529,12 @@ __device__ __forceinline__ bool near_cut_sq(double ar, double ai, double br, dou
 // four) denominators share one reciprocal of their product, refined by one
 // Newton step; each 1/q_k is unfolded by multiplying out the others (the
 // scaling keeps every q_k, and so the product, in range).
-template <bool QUAD>
+template <bool QUAD, bool NUM = false>
 __device__ __forceinline__ void pair_sums64(const double *table, int npair, double ur, double ui,
-                                            double vr, double vi, double &T0, double &T1)
+                                            double vr, double vi, double &T0, double &T1,
+                                            double *T2 = nullptr)
 {
+    // NUM: also T2 = sum 2w_j z_j^4 / q_j, for numerators in p.k
     const auto *tab = ro(table);
     const double c0 = fma(ur, ur, ui * ui), c2 = fma(vr, vr, vi * vi);
     const double c1 = -2.0 * fma(ur, vr, ui * vi);
@@ -527,6 +544,7 @@ __device__ __forceinline__ void pair_sums64(const double *table, int npair, doub
         return fma(dr, dr, di * di);
     };
     double s0 = 0.0, s1 = 0.0, z0 = 0.0, z1 = 0.0;  // T0 and T1, two partial sums each
+    double y0 = 0.0, y1 = 0.0;                      // T2 (NUM)
     int p = 0;
     for (; p + 8 <= npair; p += 8) {
         const auto *t = tab + 3 * p;
@@ -546,6 +564,10 @@ __device__ __forceinline__ void pair_sums64(const double *table, int npair, doub
             z0 = fma(t[3 * k + 2], r[k], z0);
             s1 = fma(t[3 * k + 4], r[k + 1], s1);
             z1 = fma(t[3 * k + 5], r[k + 1], z1);
+            if (NUM) {
+                y0 = fma(t[3 * k + 2] * t[3 * k], r[k], y0);
+                y1 = fma(t[3 * k + 5] * t[3 * k + 3], r[k + 1], y1);
+            }
         }
     }
     for (; p + 4 <= npair; p += 4) {
@@ -563,15 +585,23 @@ __device__ __forceinline__ void pair_sums64(const double *table, int npair, doub
         z0 = fma(t[8], r2, z0);
         s1 = fma(t[10], r3, s1);
         z1 = fma(t[11], r3, z1);
+        if (NUM) {
+            y0 = fma(t[2] * t[0], r0, y0);
+            y1 = fma(t[5] * t[3], r1, y1);
+            y0 = fma(t[8] * t[6], r2, y0);
+            y1 = fma(t[11] * t[9], r3, y1);
+        }
     }
     for (; p < npair; ++p) {
         const auto *t = tab + 3 * p;
         const double r0 = rcp64(qof(t[0]));
         s0 = fma(t[1], r0, s0);
         z0 = fma(t[2], r0, z0);
+        if (NUM) y0 = fma(t[2] * t[0], r0, y0);
     }
     T0 = s0 + s1;
     T1 = z0 + z1;
+    if (NUM) *T2 = y0 + y1;
 }
 
 template <int SCALE = 1>
@@ -612,6 +642,46 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
     return A;
 }
 
+// Numerators in p.k: with p.k = (V/2) z, each folded pair gives
+//   (V/2) z [w/(U - Vz) - w/(U + Vz)]      = (V^2/2)   2w s / D(s),
+//   (V/2)^2 z^2 [w/(U - Vz) + w/(U + Vz)]  = (V^2 U/4) 2w s / D(s),
+// s = z^2, D(s) = U^2 - V^2 s (the middle node z = 0 adds nothing), and
+// sum 2w s / D = conj(U^2) T1 - conj(V^2) T2 with T2 = sum 2w s^2 / |D|^2: one
+// more real sum of positive terms, so no cancellation is introduced.
+// Returns A = <1/(U - Vz)> and S1 = sum_pairs 2w s / D(s).
+template <int SCALE = -1>
+__device__ __forceinline__ void angular_sums64_num(const double *table, int npair, double wmid,
+                                                   cd U, cd V2in, bool scale_rt, cd &A, cd &S1)
+{
+    const bool scale = SCALE == 1 || (SCALE == -1 && scale_rt);
+    const cd U2in = cmul(U, U);
+    int e = 0;
+    double u2r = U2in.r, u2i = U2in.i, v2r = V2in.r, v2i = V2in.i;
+    if (scale) {
+        e = scale_exponent(U2in, V2in);
+        u2r = ldexp(u2r, -e);
+        u2i = ldexp(u2i, -e);
+        v2r = ldexp(v2r, -e);
+        v2i = ldexp(v2i, -e);
+    }
+    double T0, T1, T2;
+    if (near_cut_sq(u2r, u2i, v2r, v2i))
+        pair_sums64<false, true>(table, npair, u2r, u2i, v2r, v2i, T0, T1, &T2);
+    else
+        pair_sums64<true, true>(table, npair, u2r, u2i, v2r, v2i, T0, T1, &T2);
+    double sr = fma(u2r, T0, -(v2r * T1)), si = fma(u2i, T0, -(v2i * T1));
+    double tr = fma(u2r, T1, -(v2r * T2)), ti = fma(u2i, T1, -(v2i * T2));
+    if (scale) {
+        sr = ldexp(sr, -e);
+        si = ldexp(si, -e);
+        tr = ldexp(tr, -e);
+        ti = ldexp(ti, -e);
+    }
+    A = cmul(U, mk(sr, -si));
+    if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    S1 = mk(tr, -ti);
+}
+
 // FP32 angular sum with blocked accumulation, on U^2 and V^2 formed in FP64
 // and scaled by the exact power of two 2^-e (e = exponent of their largest
 // component), so every FP32 denominator is O(1) and the shared-reciprocal
@@ -628,9 +698,10 @@ __device__ __forceinline__ cd angular_sum64(const double *table, int npair, doub
 // FP64) that D_j was formed from.  The table holds (z_j^2, 2w_j, 2w_j z_j^2) in FP32.
 constexpr int kBlock = 16;
 
-template <bool QUAD>
+template <bool QUAD, bool NUM = false>
 __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, double wmid, cd U,
-                                             double u2r, double u2i, double v2r, double v2i, int e)
+                                             double u2r, double u2i, double v2r, double v2i, int e,
+                                             cd *S1 = nullptr)
 {
     const auto *tab = ro(table);
     const float fu2r = (float)u2r, fu2i = (float)u2i, fv2r = (float)v2r, fv2i = (float)v2i;
@@ -641,11 +712,11 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
         const float dr = fmaf(-fv2r, s, fu2r), di = fmaf(-fv2i, s, fu2i);
         return fmaf(dr, dr, di * di);
     };
-    double T0 = 0.0, T1 = 0.0;  // FP32 block sums added in FP64
+    double T0 = 0.0, T1 = 0.0, T2 = 0.0;  // FP32 block sums added in FP64
     int p = 0;
     while (p < npair) {
         const int pe = min(p + kBlock, npair);
-        float b0 = 0.0f, d0 = 0.0f, b1 = 0.0f, d1 = 0.0f;
+        float b0 = 0.0f, d0 = 0.0f, b1 = 0.0f, d1 = 0.0f, f0 = 0.0f, f1 = 0.0f;
         const auto *t = tab + 3 * p;
         // four pairs per step, two shared reciprocals (of q0 q1 and q2 q3)
         for (; p + 4 <= pe; p += 4, t += 12) {
@@ -662,20 +733,32 @@ __device__ __forceinline__ cd angular_sum32c(const float *table, int npair, doub
             d0 = fmaf(t[8], r2, d0);
             b1 = fmaf(t[10], r3, b1);
             d1 = fmaf(t[11], r3, d1);
+            if (NUM) {
+                f0 = fmaf(t[2] * t[0], r0, f0);
+                f1 = fmaf(t[5] * t[3], r1, f1);
+                f0 = fmaf(t[8] * t[6], r2, f0);
+                f1 = fmaf(t[11] * t[9], r3, f1);
+            }
         }
         for (; p < pe; ++p, t += 3) {
             const float r0 = __builtin_amdgcn_rcpf(qof(t[0]));
             b0 = fmaf(t[1], r0, b0);
             d0 = fmaf(t[2], r0, d0);
+            if (NUM) f0 = fmaf(t[2] * t[0], r0, f0);
         }
         T0 += (double)(b0 + b1);
         T1 += (double)(d0 + d1);
+        if (NUM) T2 += (double)(f0 + f1);
     }
     const double ar = QUAD ? u2r : (double)fu2r, ai = QUAD ? u2i : (double)fu2i;
     const double br = QUAD ? v2r : (double)fv2r, bi = QUAD ? v2i : (double)fv2i;
     const double sr = fma(ar, T0, -(br * T1)), si = fma(ai, T0, -(bi * T1));
     cd A = cmul(U, mk(ldexp(sr, -e), -ldexp(si, -e)));
     if (wmid != 0.0) A = cadd(A, cdiv(mk(wmid, 0.0), U));
+    if (NUM) {
+        const double tr = fma(ar, T1, -(br * T2)), ti = fma(ai, T1, -(bi * T2));
+        *S1 = mk(ldexp(tr, -e), -ldexp(ti, -e));
+    }
     return A;
 }
 
@@ -701,6 +784,30 @@ __device__ __forceinline__ cd angular_sum_fp32c(const Args &a, cd U, cd V2)
 
 // SCALE (FP64 only): -1 rescales as the launch's `unscaled` flag says; 0 or 1
 // fix it at compile time for a caller that has branched on the flag.
+// The numerator form of the angular sums: A = <1/(U - Vz)> and
+// S1 = sum_pairs 2w s / D(s), in FP64 or (as angular_sum_fp32c chooses by the
+// node's distance from the cut) FP32C.
+template <int PREC, class Args>
+__device__ __forceinline__ void angular_sums_num(const Args &a, cd U, cd V2, cd &A, cd &S1)
+{
+    if (PREC == 0) {
+        angular_sums64_num<-1>(a.ang, a.n_a / 2, a.wmid, U, V2, !a.unscaled, A, S1);
+        return;
+    }
+    const cd U2 = cmul(U, U);
+    const int e = scale_exponent(U2, V2);
+    const double u2r = ldexp(U2.r, -e), u2i = ldexp(U2.i, -e);
+    const double v2r = ldexp(V2.r, -e), v2i = ldexp(V2.i, -e);
+    double lhs, d2vv;
+    cut_measure(u2r, u2i, v2r, v2i, lhs, d2vv);
+    if (lhs > kCutSensitivity * kCutSensitivity * d2vv)
+        angular_sums64_num<-1>(a.ang, a.n_a / 2, a.wmid, U, V2, !a.unscaled, A, S1);
+    else if (lhs > kQuad32Sensitivity * kQuad32Sensitivity * d2vv)
+        A = angular_sum32c<false, true>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e, &S1);
+    else
+        A = angular_sum32c<true, true>(a.ang32, a.n_a / 2, a.wmid, U, u2r, u2i, v2r, v2i, e, &S1);
+}
+
 template <int PREC, int SCALE = -1, class Args>
 __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 {
@@ -710,11 +817,29 @@ __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 
 // Pole sums: <P1(D1)> = sum_a c1_a <1/(U_a - V z)>, U_a = U + m1_a^2 - m1_0^2
 // (U carries pole 0); one folded angular sum per pole of `set`.
+// Numerator (pole sums with a.num): N(k^2, p.k) = N0(y) + N1(y) p.k + N2(y) (p.k)^2
+// at the node's y (N: the three polynomials' values), so per pole
+//   <N / (U_a - Vz)> = N0 A_a + N1 (V^2/2) S1_a + N2 (V^2 U_a/4) S1_a.
 template <int PREC, bool POLES, class Args>
-__device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set = ~0)
+__device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set = ~0,
+                                            const cd *N = nullptr)
 {
     if (!POLES) return angular_sum<PREC>(a, U, V2);
     cd A = mk(0.0, 0.0);
+    if (N) {
+        for (int p = 0; p < a.n1; ++p) {
+            if (!(set >> p & 1)) continue;
+            const auto *q = &a.p1[4 * p];
+            const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
+            cd Aa, S1;
+            angular_sums_num<PREC>(a, Ua, V2, Aa, S1);
+            const cd half_v2 = cscale(V2, 0.5);
+            const cd val = cadd(cmul(N[0], Aa),
+                                cmul(cadd(N[1], cmul(N[2], cscale(Ua, 0.5))), cmul(half_v2, S1)));
+            A = cadd(A, cmul(mk(q[2], q[3]), val));
+        }
+        return A;
+    }
     for (int p = 0; p < a.n1; ++p) {
         if (!(set >> p & 1)) continue;
         const auto *q = &a.p1[4 * p];

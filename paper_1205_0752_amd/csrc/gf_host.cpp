@@ -285,6 +285,11 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_propagators *props
         a.p2[4 * k + 3] = props ? props->c2_im[k] : 0.0;
         a.b2[k] = bad_ray(a.p2[4 * k], a.p2[4 * k + 1]);
     }
+    a.num = props && props->numerator ? 1 : 0;
+    for (int k = 0; k < 9; ++k) {
+        a.nc[2 * k] = a.num ? props->num_re[k] : 0.0;
+        a.nc[2 * k + 1] = a.num ? props->num_im[k] : 0.0;
+    }
     a.m1_re = a.p1[0];
     a.m1_im = a.p1[1];
     a.m2_re = a.p2[0];
@@ -323,6 +328,13 @@ void fill_constants(ScanArgs &a, const gf_params &p, const gf_propagators *props
     const auto P1 = pole_set(a.p1, a.n1, false), P2 = pole_set(a.p2, a.n2, false);
     const auto C1 = pole_set(a.p1, a.n1, true), C2 = pole_set(a.p2, a.n2, true);
     a.mirror_ok = (C1 == P1 && C2 == P2) || (C1 == P2 && C2 == P1);
+    // a numerator keeps the first symmetry only if its coefficients are real;
+    // the exchange k -> p - k changes N(k^2, p.k), so it is not used
+    if (a.num) {
+        bool real = true;
+        for (int k = 0; k < 9; ++k) real = real && a.nc[2 * k + 1] == 0.0;
+        a.mirror_ok = real && C1 == P1 && C2 == P2;
+    }
 }
 
 int validate_props(const gf_propagators *props, const gf_quadrature &q)
@@ -347,6 +359,15 @@ int validate_props(const gf_propagators *props, const gf_quadrature &q)
     }
     if (q.radial_split && (props->n1 > 1 || props->n2 > 1))
         return fail(GF_EUNSUPPORTED, "the split radial rule needs one pole per leg");
+    if (props->numerator != 0 && props->numerator != 1)
+        return fail(GF_EINVAL, "numerator must be 0 or 1");
+    if (props->numerator) {
+        for (int k = 0; k < 9; ++k)
+            if (!finite(props->num_re[k]) || !finite(props->num_im[k]))
+                return fail(GF_EINVAL, "numerator coefficients must be finite");
+        if (q.radial_split)
+            return fail(GF_EUNSUPPORTED, "the split radial rule takes no numerator");
+    }
     return GF_OK;
 }
 
@@ -536,6 +557,8 @@ int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_qu
     int rc = gf::validate_params(params, quad);
     if (rc != GF_OK) return rc;
     if ((rc = gf::validate_props(props, *quad)) != GF_OK) return rc;
+    if (props && props->numerator && params->taylor_order > 0)
+        return fail(GF_EUNSUPPORTED, "a numerator takes taylor_order -1 or 0");
     int dev;
     if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
 

@@ -54,6 +54,8 @@ struct ScanArgs {
     double p1[4 * GF_MAX_POLES];
     double p2[4 * GF_MAX_POLES];
     double b1[GF_MAX_POLES], b2[GF_MAX_POLES];
+    int num;          // pole sums: a numerator polynomial N(k^2, p.k) multiplies P1 P2
+    double nc[18];    // its coefficients n_ij of (k^2)^i (p.k)^j, (re, im) at 2 (3i + j)
     double mu2;
     double scale;
 

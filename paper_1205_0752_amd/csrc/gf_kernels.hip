@@ -104,7 +104,9 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
         for (; k < n_straight; k += L) {
             cd U, V2, w;
             radial_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
-            cd A = angular_sum_p<PREC, POLES>(a, U, V2);
+            cd N[3];
+            if (a.num) numerator_at(a, U, pc.x1, N);
+            cd A = angular_sum_p<PREC, POLES>(a, U, V2, ~0, a.num ? N : nullptr);
             cd t = cmul(w, A);
             sr += t.r;
             si += t.i;
@@ -117,8 +119,11 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
         // to shrink it, and its k-leg pole can sit near the angular cut: its
         // angular sum is taken in FP64 in every precision
         const bool res = outer_coeffs<POLES>(a, pc, k, U, V2, w, set);
-        cd A = PREC != 0 && res ? angular_sum_p<0, POLES>(a, U, V2, set)
-                                : angular_sum_p<PREC, POLES>(a, U, V2, set);
+        cd N[3];
+        const bool num = POLES && a.num;
+        if (num) numerator_at(a, U, pc.x1, N);
+        cd A = PREC != 0 && res ? angular_sum_p<0, POLES>(a, U, V2, set, num ? N : nullptr)
+                                : angular_sum_p<PREC, POLES>(a, U, V2, set, num ? N : nullptr);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;
@@ -268,7 +273,10 @@ __device__ __forceinline__ void jmu_wave_impl(const Args &a, double mu2, double 
     for (int k = lane; k < pc.nodes; k += 64) {
         cd U, V2, w;
         node_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
-        cd A = angular_sum_p<0, POLES>(a, U, V2);
+        cd N[3];
+        const bool num = POLES && a.num;
+        if (num) numerator_at(a, U, pc.x1, N);
+        cd A = angular_sum_p<0, POLES>(a, U, V2, ~0, num ? N : nullptr);
         cd t = cmul(w, A);
         sr += t.r;
         si += t.i;

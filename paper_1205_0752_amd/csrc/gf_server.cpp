@@ -676,6 +676,8 @@ int gf_server_submit_ex(gf_server_t *s, const gf_params *params, const gf_propag
     if (!s || !ticket) return fail(GF_EINVAL, "NULL argument");
     int rc = gf::validate_params(params, quad);
     if (rc == GF_OK) rc = gf::validate_props(props, *quad);
+    if (rc == GF_OK && props && props->numerator && params->taylor_order > 0)
+        rc = fail(GF_EUNSUPPORTED, "a numerator takes taylor_order -1 or 0");
     if (rc == GF_OK) rc = gf::validate_grid(*params, props, grid);
     std::lock_guard<std::mutex> lock(s->mu);
     if (rc != GF_OK) {

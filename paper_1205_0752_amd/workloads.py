@@ -46,9 +46,11 @@ class Params:
 class Propagators:
     """Pole-sum propagators P1(s) = sum_a c1_a / (s + m1_a^2) on the (p-k) leg
     and P2(s) = sum_b c2_b / (s + m2_b^2) on the k leg: tuples of (m^2, c),
-    1 to 8 poles each."""
+    1 to 8 poles each; optionally a numerator N(k^2, p.k) = sum n_ij (k^2)^i
+    (p.k)^j (i, j = 0..2) given as a tuple of (i, j, n_ij), () for N = 1."""
     poles1: tuple
     poles2: tuple
+    numerator: tuple = ()
 
     @staticmethod
     def conjugate_pair(m2: complex, c: complex = 0.5) -> tuple:
