@@ -341,6 +341,16 @@ def extensions(gf, torch):
                             "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],
                             "frac_of_fp64_peak": t["tflops"] / FP64_PEAK_TFLOPS,
                             "kernel": t["kernel"]}
+    # the same with a numerator N(k^2, p.k) of every degree up to 2 in each
+    # (one more real pair sum per folded pair, three polynomials per node)
+    num = ((0, 0, 0.8 - 0.1j), (1, 0, 0.3 + 0.2j), (2, 0, 0.01 - 0.05j), (0, 1, 0.4),
+           (1, 1, -0.2 + 0.1j), (2, 1, 0.02), (0, 2, 0.1 - 0.3j), (1, 2, 0.05), (2, 2, 0.01 + 0.01j))
+    t = time_scan(gf, torch, p, g, q, 5, 1, 0,
+                  props=Propagators(props.poles1, props.poles2, num))
+    out["numerator_scan"] = {"workload": "the pole-sum scan with a complex numerator "
+                                         "sum_{i,j<=2} n_ij (k^2)^i (p.k)^j",
+                             "ms": t["ms"], "evals_per_s": t["evals_per_s"],
+                             "kernel": t["kernel"]}
     t = time_scan(gf, torch, dataclasses.replace(p, taylor_order=2), g, q, 5, 1, 0)
     out["taylor2_scan"] = {"workload": "bench workload with the subtraction t^2 about mu^2",
                            "ms": t["ms"], "evals_per_s": t["evals_per_s"], "tflops": t["tflops"],

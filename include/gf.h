@@ -231,6 +231,34 @@ typedef struct {
 int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_quadrature *quad,
                gf_plan_t **out);
 
+/* Tabulated propagators (the integrand plug-in of the introduction and
+ * conclusions, for propagators known only as numbers at Euclidean momenta):
+ * fits the pole sum P(s) = sum_a c_a / (s + m_a^2) of gf_propagators to n
+ * samples (s_i, P(s_i)), s_i >= 0, so that P can be continued to the complex
+ * arguments the contours reach.  Host only (no GPU, no device memory).
+ *   s[n]            distinct finite sample points >= 0 (any order)
+ *   p_re[n], p_im   P(s_i); p_im may be NULL (real data)
+ *   weight[n]       positive weights W_i of the error measure, or NULL for 1
+ *                   (W_i = 1/|P(s_i)| fits relative errors, for data that
+ *                   spans decades)
+ *   max_poles       1..GF_MAX_POLES; n >= 2 (max_poles + 1)
+ *   tol             stop once max_i W_i |P(s_i) - r(s_i)| <= tol max_i W_i |P(s_i)|
+ *                   for the rational approximant r (e.g. 1e-12)
+ * Method: the AAA rational approximation (Nakatsukasa, Sete, Trefethen 2018;
+ * at most max_poles + 1 support points), its poles as the zeros of the
+ * barycentric denominator, then the residues c_a of the pole sum (no constant
+ * term) by weighted least squares over all samples; poles whose weighted
+ * term stays below 1e-3 tol max_i W_i |P(s_i)| on every sample are dropped.  Real data give real poles and
+ * exactly conjugate pole pairs with conjugate residues, so the propagator
+ * keeps G(conj x) = conj G(x).
+ * Out: *n_poles <= max_poles; m2_re/m2_im/c_re/c_im (caller arrays of
+ * max_poles) hold m_a^2 and c_a; *max_err (may be NULL) = max_i W_i |P(s_i) -
+ * fit(s_i)| / max_i W_i |P(s_i)|.  Errors: GF_EINVAL for bad arguments, no pole
+ * found, or a fitted pole on the integration path (real m^2 <= 0). */
+int gf_fit_poles(const double *s, const double *p_re, const double *p_im, const double *weight,
+                 int n, int max_poles, double tol, int *n_poles, double *m2_re, double *m2_im,
+                 double *c_re, double *c_im, double *max_err);
+
 /* Scans a grid with a plan (STEP 5, eq. 15 at every point): launches the
  * fused grid/contour/quadrature kernel on `stream` (a hipStream_t, NULL for
  * the default stream) and returns without waiting.

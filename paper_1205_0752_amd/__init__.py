@@ -11,13 +11,14 @@ GPU.
 from ._binding import (CLASS_LONG, CLASS_MIRROR, CLASS_R, CLASS_SINGULAR, CLASS_Y, CLASS_YRES, EXPORTS,
                        LIB_PATH, NO_CONTOUR, OBSTRUCTED_CONTOUR, OBSTRUCTED_REAL_AXIS, REQ_DONE,
                        REQ_QUEUED, REQ_RUNNING, YSCAN_ANGULAR, YSCAN_INTEGRAND, GFError, Plan,
-                       Server, cache_clear, cut_curve, empty_result, load, obstruction_map, scan,
+                       Server, cache_clear, cut_curve, empty_result, fit_poles, load,
+                       obstruction_map, scan,
                        scan_noalloc, scan_plan, version, yscan_plan)
 from .workloads import (CONFIGS, FP32C, FP64, GC1, GC2, GL, TANH_SINH, Grid, Params, Propagators,
                         Quadrature)
 
 __all__ = ["Params", "Propagators", "Grid", "Quadrature", "Plan", "Server", "scan", "scan_noalloc", "scan_plan", "cache_clear",
-           "empty_result", "yscan_plan", "cut_curve", "obstruction_map", "version", "load", "GFError", "EXPORTS",
+           "empty_result", "yscan_plan", "cut_curve", "obstruction_map", "fit_poles", "version", "load", "GFError", "EXPORTS",
            "LIB_PATH", "FP64", "FP32C", "GC2", "GC1", "TANH_SINH", "GL", "CONFIGS",
            "YSCAN_ANGULAR", "YSCAN_INTEGRAND", "OBSTRUCTED_REAL_AXIS", "OBSTRUCTED_CONTOUR",
            "NO_CONTOUR", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",

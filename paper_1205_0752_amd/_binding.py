@@ -29,7 +29,8 @@ CLASS_R, CLASS_Y, CLASS_YRES, CLASS_MIRROR, CLASS_SINGULAR, CLASS_LONG = 0, 1, 2
 #: every symbol include/gf.h declares
 EXPORTS = ("gf_plan", "gf_plan_ex", "gf_scan_plan", "gf_scan_plan_ex", "gf_scan", "gf_scan_noalloc",
            "gf_free", "gf_cache_clear",
-           "gf_plan_jmu", "gf_plan_taylor", "gf_plan_auto_lanes", "gf_last_error", "gf_version",
+           "gf_plan_jmu", "gf_plan_taylor", "gf_plan_auto_lanes", "gf_fit_poles", "gf_last_error",
+           "gf_version",
            "gf_yscan_plan", "gf_cut_curve", "gf_obstruction_map",
            "gf_server_create", "gf_server_submit", "gf_server_submit_ex", "gf_server_poll",
            "gf_server_wait",
@@ -153,6 +154,9 @@ def load():
                                       ctypes.POINTER(_Grid), ctypes.c_int, vp, vp]
         lib.gf_cut_curve.argtypes = [ctypes.POINTER(_Params), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.gf_fit_poles.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp]
         lib.gf_obstruction_map.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Grid),
                                            ctypes.c_int, vp, vp]
         u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -330,6 +334,35 @@ def cut_curve(params: Params, x: complex, n: int = 513):
     return out[0::4] + 1j * out[1::4], out[2::4] + 1j * out[3::4]
 
 
+def fit_poles(s, p, max_poles: int = MAX_POLES, tol: float = 1e-12, weight=None):
+    """Pole sum fitted to tabulated P(s_i), s_i >= 0 (gf_fit_poles), with
+    optional positive weights of the error measure: returns (poles, max_err)
+    with poles a tuple of (m^2, c) for Propagators."""
+    import numpy as np
+    s = np.ascontiguousarray(np.asarray(s, dtype=np.float64).ravel())
+    p = np.asarray(p, dtype=np.complex128).ravel()
+    if p.size != s.size:
+        raise ValueError("s and p must have the same length")
+    pr = np.ascontiguousarray(p.real)
+    pi = np.ascontiguousarray(p.imag)
+    wt = None
+    if weight is not None:
+        wt = np.ascontiguousarray(np.asarray(weight, dtype=np.float64).ravel())
+        if wt.size != s.size:
+            raise ValueError("s and weight must have the same length")
+    m2r, m2i, cr, ci = (np.zeros(MAX_POLES) for _ in range(4))
+    n_poles = ctypes.c_int(0)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load().gf_fit_poles(s.ctypes.data_as(dp), pr.ctypes.data_as(dp), pi.ctypes.data_as(dp),
+                               wt.ctypes.data_as(dp) if wt is not None else None,
+                               int(s.size), int(max_poles), float(tol), ctypes.byref(n_poles),
+                               m2r.ctypes.data_as(dp), m2i.ctypes.data_as(dp),
+                               cr.ctypes.data_as(dp), ci.ctypes.data_as(dp), ctypes.byref(err)))
+    k = n_poles.value
+    return tuple((complex(m2r[a], m2i[a]), complex(cr[a], ci[a])) for a in range(k)), err.value
+
+
 OBSTRUCTED_REAL_AXIS, OBSTRUCTED_CONTOUR, NO_CONTOUR = 1, 2, 4
 
 
@@ -462,6 +495,7 @@ def version() -> str:
 
 
 __all__ = ["Plan", "Server", "scan", "scan_noalloc", "scan_plan", "yscan_plan", "cut_curve", "obstruction_map",
+           "fit_poles",
            "cache_clear",
            "version", "load", "GFError",
            "EXPORTS",

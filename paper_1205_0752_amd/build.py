@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "_libgf.so")
 SOURCES = [os.path.join(HERE, "csrc", name)
            for name in ("gf_host.cpp", "gf_server.cpp", "gf_kernels.hip", "gf_diag_kernels.hip",
-                         "gf_noalloc.hip")]
+                         "gf_noalloc.hip", "gf_fit.cpp")]
 ARCH = "gfx950"
 
 # Device code is built without packed FP32 instructions (the compiler would
