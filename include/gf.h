@@ -216,10 +216,10 @@ typedef struct {
      * complex coefficients num_re/num_im; numerator = 0 means N = 1.  Each
      * power of p.k folds exactly into the symmetric angular sums (one more
      * real pair sum, no cancellation).  A polynomial numerator adds no
-     * singularity, so the contour classes are those of P1 P2; it is
-     * subtracted at mu^2 like the rest (taylor_order -1 or 0 only:
-     * GF_EUNSUPPORTED otherwise), and raises the integrand's growth at large
-     * y, so the subtracted integral can need the cutoff to stay finite. */
+     * singularity, so the contour classes are those of P1 P2 (MIRROR only
+     * with real coefficients); it is subtracted at mu^2 like the rest (any
+     * taylor_order), and raises the integrand's growth at large y, so the
+     * subtracted integral can need the cutoff to stay finite. */
     int32_t numerator;
     int32_t reserved;
     double num_re[9], num_im[9];

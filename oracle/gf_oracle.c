@@ -806,7 +806,8 @@ static int orc_point(const orc_ctx *c, cplx x, int force_class, cplx *g, double 
 static void orc_ctx_free(orc_ctx *c);
 
 /* Taylor coefficients K_i = (1/i!) d^i S/dx^i at x = mu^2, i = 0..n, of the
- * real-axis sum S(x) = sum over the radial nodes of W y/(y + m2^2) <1/D1>(x, y),
+ * real-axis sum S(x) = sum over the radial nodes of W y P2(y) <N P1(D1)>(x, y)
+ * (N = 1 without a numerator),
  * by Cauchy's integral formula: K_i = (1/(2 pi i)) contour integral of
  * S(x) / (x - mu^2)^(i+1) over |x - mu^2| = rho, with the trapezoidal rule on
  * 64 equally spaced points (exact up to (rho/R)^64 for S analytic in the disc

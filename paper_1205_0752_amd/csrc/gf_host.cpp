@@ -557,8 +557,6 @@ int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_qu
     int rc = gf::validate_params(params, quad);
     if (rc != GF_OK) return rc;
     if ((rc = gf::validate_props(props, *quad)) != GF_OK) return rc;
-    if (props && props->numerator && params->taylor_order > 0)
-        return fail(GF_EUNSUPPORTED, "a numerator takes taylor_order -1 or 0");
     int dev;
     if ((rc = gf::current_device(&dev)) != GF_OK) return rc;
 

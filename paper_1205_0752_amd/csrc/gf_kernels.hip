@@ -225,24 +225,43 @@ serve_kernel_fp32c(const ScanArgs *__restrict__ reqs, const WorkItem *__restrict
 // Subtraction sum at the real point mu^2 on the real axis, by one wavefront.
 // Higher Taylor coefficients of one folded angular sum about x = mu^2 on the
 // real axis (y = r real): with delta = x - mu^2, each symmetric pair
-// contributes 2w U(delta) / D(delta), U = U0 + delta, D = U^2 - 4 x y z^2 =
-// D0 + D1 delta + delta^2, whose power series q_i follows from
-// D q = 2w U term by term; the middle node w_mid / (U0 + delta) has
-// q_i = w_mid (-1)^i / U0^(i+1).  acc[i] += omega q_i for i = 1..n.
+// contributes A(delta) / D(delta) with D = U^2 - 4 x y z^2 = D0 + D1 delta +
+// delta^2 (U = U0 + delta), whose power series q_i follows from D q = A term
+// by term.  Without a numerator A = 2w U.  With one (N: its polynomials N_j(y)
+// in p.k, the same for every pole), the pair carries
+//   2w U N0 + 2w z^2 (V^2/2) N1 + 2w z^2 (V^2 U/4) N2,   V^2 = 4 (mu^2 + delta) y,
+// a quadratic A = a0 + a1 delta + a2 delta^2 in delta.  The middle node
+// (z = 0) w_mid N0 / (U0 + delta) has q_i = w_mid N0 (-1)^i / U0^(i+1).
+// acc[i] += omega q_i for i = 1..n.
 template <class Args>
-__device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd *acc)
+__device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd *acc,
+                            const cd *N = nullptr)
 {
     const double *tab = a.ang;
+    const double mu2 = a.mu2;
     for (int j = 0; j < a.n_a / 2; ++j) {
         const double z2 = ro(tab)[3 * j], w2 = ro(tab)[3 * j + 1];
-        const cd D0 = mk(U0.r * U0.r - U0.i * U0.i - 4.0 * a.mu2 * y * z2, 2.0 * U0.r * U0.i);
+        const cd D0 = mk(U0.r * U0.r - U0.i * U0.i - 4.0 * mu2 * y * z2, 2.0 * U0.r * U0.i);
         const cd D1 = mk(2.0 * U0.r - 4.0 * y * z2, 2.0 * U0.i);
+        cd a0 = cscale(U0, w2), a1 = mk(w2, 0.0), a2 = mk(0.0, 0.0);
+        if (N) {
+            // a0 = 2w N0 U0 + 2w z^2 y mu^2 (2 N1 + U0 N2)
+            // a1 = 2w N0 + 2w z^2 y (2 N1 + (mu^2 + U0) N2)
+            // a2 = 2w z^2 y N2
+            const double wy = w2 * z2 * y;
+            const cd n2u = cmul(N[2], U0);
+            a0 = cadd(cmul(a0, N[0]), cscale(cadd(cscale(N[1], 2.0), n2u), wy * mu2));
+            a1 = cadd(cscale(N[0], w2),
+                      cscale(cadd(cadd(cscale(N[1], 2.0), cscale(N[2], mu2)), n2u), wy));
+            a2 = cscale(N[2], wy);
+        }
         const cd rD = cdiv(mk(1.0, 0.0), D0);
         cd qm2 = mk(0.0, 0.0);
-        cd qm1 = cmul(cscale(U0, w2), rD);  // q_0
+        cd qm1 = cmul(a0, rD);  // q_0
         for (int i = 1; i <= n; ++i) {
             cd rhs = mk(-(D1.r * qm1.r - D1.i * qm1.i) - qm2.r, -(D1.r * qm1.i + D1.i * qm1.r) - qm2.i);
-            if (i == 1) rhs = cadd(rhs, mk(w2, 0.0));
+            if (i == 1) rhs = cadd(rhs, a1);
+            if (i == 2) rhs = cadd(rhs, a2);
             const cd q = cmul(rhs, rD);
             acc[i] = cadd(acc[i], cmul(omega, q));
             qm2 = qm1;
@@ -252,6 +271,7 @@ __device__ void taylor_node(const Args &a, cd U0, double y, cd omega, int n, cd 
     if (a.wmid != 0.0) {
         const cd rU = cdiv(mk(1.0, 0.0), U0);
         cd p = cscale(rU, a.wmid);
+        if (N) p = cmul(p, N[0]);
         for (int i = 1; i <= n; ++i) {
             p = cscale(cmul(p, rU), -1.0);
             acc[i] = cadd(acc[i], cmul(omega, p));
@@ -289,7 +309,8 @@ __device__ __forceinline__ void jmu_wave_impl(const Args &a, double mu2, double 
                 for (int p = 0; p < a.n1; ++p) {  // pole a of P1: U_a, weight c1_a omega
                     const auto *q = &a.p1[4 * p];
                     const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
-                    taylor_node(a, Ua, r, cmul(w, mk(q[2], q[3])), a.n_taylor, acc);
+                    taylor_node(a, Ua, r, cmul(w, mk(q[2], q[3])), a.n_taylor, acc,
+                                num ? N : nullptr);
                 }
             }
         }

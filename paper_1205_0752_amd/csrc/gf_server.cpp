@@ -676,8 +676,6 @@ int gf_server_submit_ex(gf_server_t *s, const gf_params *params, const gf_propag
     if (!s || !ticket) return fail(GF_EINVAL, "NULL argument");
     int rc = gf::validate_params(params, quad);
     if (rc == GF_OK) rc = gf::validate_props(props, *quad);
-    if (rc == GF_OK && props && props->numerator && params->taylor_order > 0)
-        rc = fail(GF_EUNSUPPORTED, "a numerator takes taylor_order -1 or 0");
     if (rc == GF_OK) rc = gf::validate_grid(*params, props, grid);
     std::lock_guard<std::mutex> lock(s->mu);
     if (rc != GF_OK) {
@@ -712,8 +710,11 @@ int gf_server_submit_ex(gf_server_t *s, const gf_params *params, const gf_propag
     // one lane per point: the batch already fills the GPU with many requests,
     // and whole 64-point tiles waste no lanes on short node lists
     r->lanes = 1;
+    // a numerator adds a third pair sum and three polynomials per node:
+    // about 1.4 times the time per evaluation (bench box, pole sums)
     r->cost_per_tile = (64.0 / r->lanes) * nominal_evals_per_point(*quad) * (props ? props->n1 : 1) *
-                       (quad->precision == GF_PREC_FP32C ? 0.6 : 1.0);
+                       (quad->precision == GF_PREC_FP32C ? 0.6 : 1.0) *
+                       (props && props->numerator ? 1.4 : 1.0);
     r->t_submit = Clock::now();
     if (!s->any_submit) {
         s->any_submit = true;
