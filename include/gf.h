@@ -247,14 +247,16 @@ int gf_plan_ex(const gf_params *params, const gf_propagators *props, const gf_qu
  * Method: the AAA rational approximation (Nakatsukasa, Sete, Trefethen 2018;
  * at most max_poles + 1 support points), its poles as the zeros of the
  * barycentric denominator, then the residues c_a of the pole sum (no constant
- * term) by weighted least squares over all samples; poles whose weighted
- * term stays below 1e-3 tol max_i W_i |P(s_i)| on every sample are dropped.  Real data give real poles and
+ * term) by weighted least squares over all samples; poles on the sampled
+ * half-line s >= 0 (spurious: AAA places them when it starts to fit noise)
+ * and poles whose weighted term stays below 1e-3 tol max_i W_i |P(s_i)| on
+ * every sample are dropped.  With noisy data choose tol above the noise.  Real data give real poles and
  * exactly conjugate pole pairs with conjugate residues, so the propagator
  * keeps G(conj x) = conj G(x).
  * Out: *n_poles <= max_poles; m2_re/m2_im/c_re/c_im (caller arrays of
  * max_poles) hold m_a^2 and c_a; *max_err (may be NULL) = max_i W_i |P(s_i) -
- * fit(s_i)| / max_i W_i |P(s_i)|.  Errors: GF_EINVAL for bad arguments, no pole
- * found, or a fitted pole on the integration path (real m^2 <= 0). */
+ * fit(s_i)| / max_i W_i |P(s_i)|.  Errors: GF_EINVAL for bad arguments or no
+ * pole found. */
 int gf_fit_poles(const double *s, const double *p_re, const double *p_im, const double *weight,
                  int n, int max_poles, double tol, int *n_poles, double *m2_re, double *m2_im,
                  double *c_re, double *c_im, double *max_err);

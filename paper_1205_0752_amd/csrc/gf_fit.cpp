@@ -311,6 +311,19 @@ extern "C" int gf_fit_poles(const double *s, const double *p_re, const double *p
             }
         }
     }
+    // A pole on the sampled half-line s >= 0 cannot belong to data that are
+    // finite there: it is one of the spurious poles AAA places when it
+    // starts to fit the data's noise (below the level tol asked for), and it
+    // is dropped.
+    {
+        double scale = 1.0;
+        for (double v : Z) scale = std::max(scale, std::fabs(v));
+        std::vector<cplx> kept;
+        for (const cplx &v : p)
+            if (!(v.real() >= 0.0 && std::fabs(v.imag()) <= 1e-9 * (std::abs(v) + 1e-6 * scale)))
+                kept.push_back(v);
+        p.swap(kept);
+    }
     // residues, then drop poles whose term stays below 1e-3 tol_abs on every
     // sample (the spurious pole-zero pairs AAA can leave), and fit again
     std::vector<cplx> c;

@@ -5,8 +5,8 @@ CPU: a rational propagator (a complex-conjugate pair and a real pole, and a
 complex-valued one) is recovered to rounding, poles and residues alike, with
 exact conjugate symmetry for real data; a non-rational Stieltjes propagator
 (s + 1)^(-4/5) is approximated to a stated accuracy with its poles on its
-branch cut and positive residues, at held-out real and complex arguments; bad
-input is rejected.  GPU: a scan with the fitted propagator equals the scan
+branch cut and positive residues, at held-out real and complex arguments;
+noisy samples keep the true poles; bad input is rejected.  GPU: a scan with the fitted propagator equals the scan
 with the exact one, and a fitted propagator scans against the oracle."""
 import numpy as np
 import pytest
@@ -84,6 +84,21 @@ def test_stieltjes_propagator_to_stated_accuracy():
     # without weights the absolute error is what shrinks
     poles_abs, err_abs = gf.fit_poles(STIELTJES_S, p, 8, 1e-13)
     assert err_abs <= 2e-5
+
+
+def test_noisy_data_keep_the_true_poles():
+    """Relative noise 1e-6 (seeded) with tol below it: AAA starts to fit the
+    noise and places spurious poles on the sampled half-line; those are
+    dropped, and the three true poles come back with the function reproduced
+    to the noise level at held-out points."""
+    gf = _gf()
+    rng = np.random.default_rng(1)
+    p = pole_sum(RATIONAL, S).real * (1.0 + 1e-6 * rng.standard_normal(S.size))
+    poles, err = gf.fit_poles(S, p, 8, 1e-7, weight=1.0 / np.abs(p))
+    assert err <= 1e-5
+    _match(poles, RATIONAL, 1e-2)
+    held = np.linspace(0.05, 900.0, 77)
+    assert np.max(np.abs(pole_sum(poles, held) / pole_sum(RATIONAL, held).real - 1.0)) <= 5e-6
 
 
 def test_fit_rejects_bad_input():
