@@ -382,8 +382,9 @@ int gf_obstruction_map(const gf_params *params, const gf_grid *grid, int n_sampl
  * FIFO order until their output (16 bytes per point) and any node tables not
  * yet resident fit in the arena and a slot is free; admitted requests run
  * concurrently: each scheduler iteration packs wave tiles of every running
- * request (a fair share of `batch_evals` integrand evaluations each, oldest
- * first, topped up with further tiles to half the tiles still to run, at
+ * request (shares of `batch_evals` integrand evaluations that grow with the
+ * square of each request's age, then the rest oldest first, topped up with
+ * further tiles to half the tiles still to run, at
  * least 1.5 and at most 6 tiles per wave slot of the device: short batches
  * while little waits, long ones under load) into persistent kernel launches, most
  * expensive tiles first, and keeps three such batches in flight; a launch's
@@ -401,7 +402,7 @@ typedef struct gf_server gf_server_t;
 typedef struct {
     size_t device_budget_bytes;  /* arena for outputs + node tables (>= 1 MiB) */
     int32_t max_inflight;        /* admitted requests at once, 1..65536 */
-    double batch_evals;          /* target integrand evaluations per batch (0 = 2e10) */
+    double batch_evals;          /* target integrand evaluations per batch (0 = 4e10) */
 } gf_server_config;
 
 #define GF_REQ_QUEUED 0
