@@ -433,6 +433,25 @@ def test_fp32c_ragged_and_odd_rules():
         check_fp32c(g[keep], go[keep])
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32c"])
+def test_rescaled_sums_at_large_magnitudes(prec):
+    """Lambda^2 = 1e10 puts |y| above 2^30, so the FP64 launch rescales U^2
+    and V^2 by powers of two (the products of eight denominators would leave
+    the double range unscaled): the bench box and a box with |x| ~ 1e6, every
+    point against the oracle."""
+    p = Params(1.0, 1.0, 1.0, 1e10, 1.0)
+    q = Quadrature(64, 32, 16, prec)
+    for grid in (Grid(27, 19, -16.0, 8.0, -8.0, 8.0), Grid(23, 17, -2e6, 1e6, -1e6, 1e6)):
+        g, c = _gpu_scan(p, q, grid)
+        go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+        if prec == 0:
+            _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
+        else:
+            keep = (c == co) & (co != oracle.SINGULAR)
+            assert (c != co).sum() <= 1
+            check_fp32c(g[keep], go[keep])
+
+
 @pytest.mark.parametrize("name", ["c0_fp64_64sq", "paper"])
 def test_fp32c_small_boxes_every_point(name):
     """FP32C at every point of the small workload (64^2, 64 x 32 nodes) and of
