@@ -221,8 +221,8 @@ typedef struct {
      * taylor_order), and raises the integrand's growth at large y, so the
      * subtracted integral can need the cutoff to stay finite. */
     int32_t numerator;
-    int32_t reserved;
-    double num_re[9], num_im[9];
+    int32_t reserved;            /* alignment of num_re; ignored, set it to 0 */
+    double num_re[9], num_im[9]; /* read only when numerator = 1 */
 } gf_propagators;
 
 /* gf_plan with general propagators: props replaces the masses of params
