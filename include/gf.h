@@ -109,9 +109,11 @@ extern "C" {
                                 cut meets a k-leg pole (from the threshold
                                 -(sqrt(m1^2) + sqrt(m2^2))^2) this is the analytic
                                 continuation; beyond it the term's cut runs along
-                                that curve and then the bad ray.  Not used in
-                                D = 3 (a full turn changes the branch of sqrt(y);
-                                those points stay GF_CLASS_SINGULAR) */
+                                that curve and then the bad ray.  In D = 3 the
+                                measure sqrt(y) is continued along the long
+                                rotation, which meets the ray, its arc and its
+                                residues at angles shifted by -+ 2 pi (the
+                                opposite sign of sqrt(y) there) */
 
 /* Integrand parameters (eq. 14-16).  m1^2 sits on the (p-k) leg, m2^2 on the
  * k leg; neither may lie on the non-positive real axis.  mu2 is the real

@@ -337,7 +337,7 @@ typedef struct {
     double lo, hi;          /* open sector (lo, hi) reachable by rotating the ray */
     double vstar;           /* region-R bound on |Im sqrt(x)|: min_a Re sqrt(m1_a^2) */
     int mirror_ok;          /* G(conj x) = conj G(x) for these propagators */
-    int dim;                /* D: the long way round is not used for D = 3 */
+    int dim;                /* D = 2, 3, 4 */
 } orc_geometry;
 
 /* arg(-m^2); a real positive m^2 gives carg(-m^2) = +pi or -pi depending on
@@ -434,8 +434,7 @@ static int orc_swept(double phi, double b)
  * residues the contour picks up.  LONG: the rotation towards arg x sweeps a
  * (p-k)-leg bad ray and neither YRES nor the mirror point applies; each such
  * pole's term is then continued the other way round the origin (see
- * orc_long_sets).  SINGULAR only on a bad ray itself, or for LONG in D = 3,
- * where a turn the long way round ends on the other branch of sqrt(y). */
+ * orc_long_sets).  SINGULAR only on a bad ray itself. */
 static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, int *mask)
 {
     *res_sign = 0;
@@ -457,7 +456,7 @@ static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, i
         return ORC_YRES;
     }
     if (cross1 && !m && g->mirror_ok) return ORC_MIRROR;
-    return g->dim == 3 ? ORC_SINGULAR : ORC_LONG;
+    return ORC_LONG;
 }
 
 /* The two groups of a LONG point.  Rotating the ray from angle 0 to phi the
@@ -469,7 +468,10 @@ static int orc_rotated_class(const orc_geometry *g, double phi, int *res_sign, i
  * angle 0 the short way (terms of the short group) and the long way (terms
  * of the long group), and each group takes the residues of the k-leg poles
  * its own rotation sweeps: the short one with sign sign(phi) (as YRES), the
- * long one with -sign(phi).  *grp_long flags the long group's (p-k)-leg poles,
+ * long one with -sign(phi).  In D = 3 the measure sqrt(y) is continued along
+ * each rotation: the long one reaches the ray, its arc and its residues with
+ * angles shifted by -+ 2 pi, which flips the sign of sqrt(y) there (the
+ * short sector holds the cut of sqrt(y)).  *grp_long flags the long group's (p-k)-leg poles,
  * *res_short and *res_long the k-leg poles whose residues each group adds. */
 static void orc_long_sets(const orc_geometry *g, double phi, int *grp_long, int *res_short,
                           int *res_long)
@@ -511,7 +513,7 @@ static int orc_classify(const orc_geometry *g, cplx x, int *res_sign)
 
 /* The class a point is evaluated with: a MIRROR point whose conjugate has no
  * contour of its own (MIRROR, LONG or SINGULAR there) takes the real axis if
- * it is valid at x, else the long way round at x (SINGULAR in D = 3). */
+ * it is valid at x, else the long way round at x. */
 static int orc_final_class(const orc_geometry *g, cplx x, int *res_sign, int *mask)
 {
     int cls = orc_classify_m(g, x, res_sign, mask);
@@ -522,7 +524,7 @@ static int orc_final_class(const orc_geometry *g, cplx x, int *res_sign, int *ma
     *res_sign = 0;
     *mask = 0;
     if (fabs(cimag(csqrt(x))) < g->vstar) return ORC_R;
-    return g->dim == 3 ? ORC_SINGULAR : ORC_LONG;
+    return ORC_LONG;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -671,7 +673,7 @@ static cplx orc_node(const orc_ctx *c, cplx x, cplx sx, cplx y, cplx sy, cplx w,
  * y0 = -m2_b^2 the residue of y^{(D-2)/2} P2(y) <P1>(y) is
  * c2_b y0^{(D-2)/2} <P1>(y0); each is added times sign 2 pi i. */
 static cplx orc_residues(const orc_ctx *c, cplx x, cplx sx, int res, int set, int sign,
-                         double *absum)
+                         double long_phi, double *absum)
 {
     cplx s = 0.0;
     for (int b = 0; b < c->geo.n2; ++b) {
@@ -679,7 +681,19 @@ static cplx orc_residues(const orc_ctx *c, cplx x, cplx sx, int res, int set, in
         cplx y0 = -c->geo.m2[b];
         double a = 0.0;
         cplx ang = orc_ang_p1_set(c, x, y0, sx * csqrt(y0), set, absum ? &a : NULL);
-        cplx pre = sign * 2.0 * M_PI * I * c->geo.c2[b] * orc_measure(orc_dim(c->p), y0, csqrt(y0));
+        /* sqrt(y0) continued along the rotation that sweeps y0: the principal
+         * one, except for the long rotation (long_phi = arg x != 0), whose
+         * angle at y0 is arg(y0) -+ 2 pi past the negative real axis; on that
+         * axis it is -pi (long_phi > 0, turning clockwise) or +pi */
+        cplx sy0 = csqrt(y0);
+        if (long_phi != 0.0) {
+            double t = carg(y0);
+            if (cimag(y0) == 0.0 && creal(y0) < 0.0) t = long_phi > 0.0 ? -M_PI : M_PI;
+            else if (long_phi > 0.0 && t > long_phi) t -= 2.0 * M_PI;
+            else if (long_phi < 0.0 && t < long_phi) t += 2.0 * M_PI;
+            sy0 = sqrt(cabs(y0)) * cexp(I * 0.5 * t);
+        }
+        cplx pre = sign * 2.0 * M_PI * I * c->geo.c2[b] * orc_measure(orc_dim(c->p), y0, sy0);
         s += pre * ang;
         if (absum) *absum += cabs(pre) * a;
     }
@@ -708,11 +722,22 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_
     double phi = carg(x);
     cplx e = cexp(I * phi);
     cplx eh = cexp(I * 0.5 * phi);
-    for (int i = 0; i < p->n_radial; ++i)
-        s += orc_node(c, x, sx, e * rn[i], eh * sqrt(rn[i]), e * wn[i], absum);
     int grp_long = 0, res_short = res_mask, res_long = 0;
     if (cls == ORC_LONG) orc_long_sets(&c->geo, phi, &grp_long, &res_short, &res_long);
     const int all = (1 << c->geo.n1) - 1, grp_short = all & ~grp_long;
+    /* sqrt(y) along each rotation: the long one reaches the ray at angle
+     * phi -+ 2 pi, where sqrt(y) = -e^{i phi/2} sqrt(r) (only the measure of
+     * D = 3 sees the sign; the angular sums are even in sqrt(y)) */
+    const int split_ray = dim == 3 && grp_long;
+    for (int i = 0; i < p->n_radial; ++i) {
+        if (!split_ray) {
+            s += orc_node(c, x, sx, e * rn[i], eh * sqrt(rn[i]), e * wn[i], absum);
+        } else {
+            if (grp_short)
+                s += orc_node_set(c, x, sx, e * rn[i], eh * sqrt(rn[i]), e * wn[i], grp_short, absum);
+            s += orc_node_set(c, x, sx, e * rn[i], -eh * sqrt(rn[i]), e * wn[i], grp_long, absum);
+        }
+    }
     double lam = sqrt(p->lambda2);
     if (grp_short) {
         /* arc |y| = Lambda^2 from angle phi back to 0 the short way:
@@ -732,15 +757,16 @@ static cplx orc_contour_sum(const orc_ctx *c, cplx x, cplx xn, int cls, int res_
         for (int k = 0; k < p->n_arc; ++k) {
             double psi = phi + 0.5 * L * (1.0 + c->arc_x[k]);
             cplx y = p->lambda2 * cexp(I * psi);
-            cplx sy = lam * cexp(I * 0.5 * psi);
+            /* continued from the ray's angle phi -+ 2 pi: e^{i (psi -+ 2 pi)/2} */
+            cplx sy = -lam * cexp(I * 0.5 * psi);
             s += orc_node_set(c, x, sx, y, sy, I * y * (0.5 * L) * c->arc_w[k], grp_long, absum);
         }
     }
-    if (cls == ORC_YRES) s += orc_residues(c, x, sx, res_mask, all, res_sign, absum);
+    if (cls == ORC_YRES) s += orc_residues(c, x, sx, res_mask, all, res_sign, 0.0, absum);
     if (cls == ORC_LONG) {
         const int sg = phi > 0.0 ? 1 : -1;
-        if (grp_short) s += orc_residues(c, x, sx, res_short, grp_short, sg, absum);
-        s += orc_residues(c, x, sx, res_long, grp_long, -sg, absum);
+        if (grp_short) s += orc_residues(c, x, sx, res_short, grp_short, sg, 0.0, absum);
+        s += orc_residues(c, x, sx, res_long, grp_long, -sg, phi, absum);
     }
     free(rn);
     free(wn);

@@ -81,8 +81,11 @@ __device__ __forceinline__ double angle_between(double a, double b)
 // that rotation, by 2 pi - |phi|, sweeps none of its own bad ray and ends on
 // the same ray at angle phi; its closing arc runs back the long way and it
 // takes the residues of the k-leg poles it sweeps, with the opposite sign.
-// In D = 3 a turn the long way round ends on the other branch of sqrt(y),
-// so such points stay kSingular, as do points on a bad ray itself.  The real
+// In D = 3 the measure sqrt(y) is continued along each rotation: the long
+// one reaches the ray, its arc and its residues at angles shifted by -+ 2 pi,
+// where sqrt(y) has the opposite sign (its cut lies in the short sector,
+// which the long rotation does not sweep).  Points on a bad ray itself are
+// kSingular.  The real
 // axis is preferred where it is valid (|Im sqrt x| < v*) and either
 // comfortably inside (v < kRNear v*), closer to its own edge than the ray is
 // to a bad ray, or the alternative is the long way round.
@@ -131,7 +134,7 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign, int 
             } else if (past1 && !past2 && a.mirror_ok) {
                 rot = kMirror;
             } else {
-                rot = a.dim == 3 ? kSingular : kLong;
+                rot = kLong;
             }
         }
     } else {
@@ -167,7 +170,7 @@ __device__ int classify(const Args &a, double xr, double xi, int *res_sign, int 
         } else if (past1 && mask == 0 && a.mirror_ok) {
             rot = kMirror;
         } else {
-            rot = a.dim == 3 ? kSingular : kLong;
+            rot = kLong;
         }
     }
     const bool r_valid = v < a.vstar;
@@ -284,6 +287,10 @@ __device__ PointCtx point_setup(const Args &a, double xr, double xi, int cls, in
         // each rotation; the short rotation's residues need its terms
         const int grp_long = info >> kInfoGrpLong & 0xFF, grp_short = short_group<POLES>(a, info);
         if (!grp_short) P.info &= ~0xFF;
+        // D = 3: the long rotation meets the ray at angle phi -+ 2 pi, where
+        // sqrt(y) = -e^{i phi/2} sqrt(r); when every term rotates the long
+        // way that is the ray's measure (mixed groups: ray_neg per term)
+        if (a.dim == 3 && cls == kLong && !grp_short) P.dirD = mk(-P.dirD.r, -P.dirD.i);
         const int arcs = grp_long && grp_short ? 2 : 1;
         P.nodes = a.n_r + arcs * a.n_arc + __popc(P.info & 0xFF) +
                   __popc(P.info >> kInfoResLong & 0xFF);
@@ -400,8 +407,11 @@ __device__ __forceinline__ bool outer_coeffs(const Args &a, const PointCtx &P, i
         const cd dy = mk(-y.i * h, y.r * h);              // dy = i y psi'(xi) dxi
         cd f = y;                                         // y^{(D-2)/2}
         if (a.dim == 3) {
+            // the long arc's angle runs from phi -+ 2 pi back to 0 along the
+            // contour: sqrt(y) = e^{i (psi -+ 2 pi)/2} Lambda = -e^{i psi/2} Lambda
             sincos(0.5 * psi, &s, &c);
-            f = mk(a.lam * c, a.lam * s);
+            const double lam = lng ? -a.lam : a.lam;
+            f = mk(lam * c, lam * s);
         } else if (a.dim == 2) {
             f = mk(1.0, 0.0);
         }
@@ -416,19 +426,36 @@ __device__ __forceinline__ bool outer_coeffs(const Args &a, const PointCtx &P, i
     const int rs = P.info & 0xFF, rl = P.info >> kInfoResLong & 0xFF;
     const int ns = __popc(rs);
     int m = rs, sg = P.res_sign;
+    bool long_rot = false;
     set = grp_short;
     if (j >= ns) {
         j -= ns;
         m = rl;
         sg = -sg;
         set = grp_long;
+        long_rot = true;
     }
     const double f = sg * 2.0 * M_PI;                     // +-2 pi i Res
+    // D = 3: sqrt(y0) continued along the rotation that sweeps y0.  The long
+    // rotation turns clockwise for phi > 0: its angle at y0 is arg(y0) - 2 pi
+    // past the negative real axis and -pi on it; counter-clockwise for
+    // phi < 0: arg(y0) + 2 pi past it and +pi on it
+    auto long_sqrt = [&](cd y0) {
+        double t = atan2(y0.i, y0.r);
+        if (y0.i == 0.0 && y0.r < 0.0) t = P.phi > 0.0 ? -M_PI : M_PI;
+        else if (P.phi > 0.0 && t > P.phi) t -= 2.0 * M_PI;
+        else if (P.phi < 0.0 && t < P.phi) t += 2.0 * M_PI;
+        double s, c;
+        sincos(0.5 * t, &s, &c);
+        const double m = sqrt(hypot(y0.r, y0.i));
+        return mk(m * c, m * s);
+    };
     if (!POLES) {
         const cd y0 = mk(-a.m2_re, -a.m2_im);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
-        const cd fy = a.dim == 4 ? y0 : (a.dim == 3 ? mk(a.sy0_re, a.sy0_im) : mk(1.0, 0.0));
+        cd fy = a.dim == 4 ? y0 : (a.dim == 3 ? mk(a.sy0_re, a.sy0_im) : mk(1.0, 0.0));
+        if (a.dim == 3 && long_rot) fy = long_sqrt(y0);
         w = mk(-fy.i * f, fy.r * f);
     } else {
         for (int it = 0; it < j; ++it) m &= m - 1;  // drop the j lowest flags
@@ -437,9 +464,9 @@ __device__ __forceinline__ bool outer_coeffs(const Args &a, const PointCtx &P, i
         const cd y0 = mk(-q2[0], -q2[1]);
         U = cadd(P.x1, y0);
         V2 = cmul(x4, y0);
-        const cd fy = cmul(mk(q2[2], q2[3]), a.dim == 4 ? y0
-                                             : (a.dim == 3 ? csqrt_principal(y0.r, y0.i)
-                                                           : mk(1.0, 0.0)));
+        cd sq = a.dim == 4 ? y0 : (a.dim == 3 ? csqrt_principal(y0.r, y0.i) : mk(1.0, 0.0));
+        if (a.dim == 3 && long_rot) sq = long_sqrt(y0);
+        const cd fy = cmul(mk(q2[2], q2[3]), sq);
         w = mk(-fy.i * f, fy.r * f);                      // +-2 pi i c2_b y0^{(D-2)/2}
     }
     return true;
@@ -820,9 +847,11 @@ __device__ __forceinline__ cd angular_sum(const Args &a, cd U, cd V2)
 // Numerator (pole sums with a.num): N(k^2, p.k) = N0(y) + N1(y) p.k + N2(y) (p.k)^2
 // at the node's y (N: the three polynomials' values), so per pole
 //   <N / (U_a - Vz)> = N0 A_a + N1 (V^2/2) S1_a + N2 (V^2 U_a/4) S1_a.
+// neg flags the poles whose terms enter with the opposite sign (the D = 3
+// measure on a ray shared by the short and the long rotation).
 template <int PREC, bool POLES, class Args>
 __device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set = ~0,
-                                            const cd *N = nullptr)
+                                            const cd *N = nullptr, int neg = 0)
 {
     if (!POLES) return angular_sum<PREC>(a, U, V2);
     cd A = mk(0.0, 0.0);
@@ -836,7 +865,8 @@ __device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set 
             const cd half_v2 = cscale(V2, 0.5);
             const cd val = cadd(cmul(N[0], Aa),
                                 cmul(cadd(N[1], cmul(N[2], cscale(Ua, 0.5))), cmul(half_v2, S1)));
-            A = cadd(A, cmul(mk(q[2], q[3]), val));
+            const double sg = neg >> p & 1 ? -1.0 : 1.0;
+            A = cadd(A, cmul(mk(sg * q[2], sg * q[3]), val));
         }
         return A;
     }
@@ -844,7 +874,8 @@ __device__ __forceinline__ cd angular_sum_p(const Args &a, cd U, cd V2, int set 
         if (!(set >> p & 1)) continue;
         const auto *q = &a.p1[4 * p];
         const cd Ua = mk(U.r + (q[0] - a.m1_re), U.i + (q[1] - a.m1_im));
-        A = cadd(A, cmul(mk(q[2], q[3]), angular_sum<PREC>(a, Ua, V2)));
+        const double sg = neg >> p & 1 ? -1.0 : 1.0;
+        A = cadd(A, cmul(mk(sg * q[2], sg * q[3]), angular_sum<PREC>(a, Ua, V2)));
     }
     return A;
 }

@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(64) obstruction_kernel(ScanArgs a, int n, doub
     if (cls == kMirror) {  // the scan evaluates the conjugate point, if it has a contour
         ecls = classify(a, xr, -xi, &sign);
         if (ecls == kMirror || ecls == kSingular || ecls == kLong)
-            cls = ecls = (info & kInfoRValid) ? kR : (a.dim == 3 ? kSingular : kLong);
+            cls = ecls = (info & kInfoRValid) ? kR : kLong;
         else
             ei = -xi;
     }

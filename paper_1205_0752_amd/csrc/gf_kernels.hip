@@ -51,7 +51,7 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
         int sign_b = 0, info_b = 0;
         ecls = classify<POLES>(a, xr, -xi, &sign_b, &info_b);
         if (ecls == kMirror || ecls == kSingular || ecls == kLong) {
-            cls = ecls = (info & kInfoRValid) ? kR : (a.dim == 3 ? kSingular : kLong);
+            cls = ecls = (info & kInfoRValid) ? kR : kLong;
             if (cls == kR) sign = info = 0;
         } else {
             xi = -xi;
@@ -101,12 +101,17 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
         sr = fma(F.r, tr, -(F.i * si));
         si = fma(F.r, si, F.i * tr);
     } else {
+        // D = 3 with both rotations: the long group's terms see the opposite
+        // sign of sqrt(y) on the shared ray (a long group alone has it in dirD)
+        const int grp_long = pc.info >> kInfoGrpLong & 0xFF;
+        const int ray_neg =
+            a.dim == 3 && ecls == kLong && short_group<POLES>(a, pc.info) ? grp_long : 0;
         for (; k < n_straight; k += L) {
             cd U, V2, w;
             radial_coeffs<SPLIT, POLES>(a, pc, k, U, V2, w);
             cd N[3];
             if (a.num) numerator_at(a, U, pc.x1, N);
-            cd A = angular_sum_p<PREC, POLES>(a, U, V2, ~0, a.num ? N : nullptr);
+            cd A = angular_sum_p<PREC, POLES>(a, U, V2, ~0, a.num ? N : nullptr, ray_neg);
             cd t = cmul(w, A);
             sr += t.r;
             si += t.i;

@@ -16,14 +16,16 @@ cut meets the k-leg pole; pole sums are the bilinear combination of their
 single-pole terms, keep G(conj x) = conj G(x) for real-analytic propagators,
 and leave no point off the real axis without a contour in D = 4.  GPU: the
 kernel's LONG points against the oracle (FP64 and FP32C, pole sums, t^2,
-D = 2) and served LONG requests equal to standalone scans."""
+D = 2 and 3) and served LONG requests equal to standalone scans.  In D = 3 the
+long way round converges to the mirror value (the measure sqrt(y) continued
+along the long rotation)."""
 import numpy as np
 import pytest
 
 import oracle
 from oracle import closed_forms as cf
 from parity_bars import check
-from paper_1205_0752_amd.workloads import GC1, Grid, Params, Propagators, Quadrature
+from paper_1205_0752_amd.workloads import GC1, GL, Grid, Params, Propagators, Quadrature
 
 GRIBOV1 = Propagators(Propagators.conjugate_pair(1.0 + 0.8j, 0.5), ((1.0, 0.6), (3.0, 0.4)))
 Q = Quadrature(512, 256, 16)
@@ -66,9 +68,8 @@ def test_single_complex_pole_matches_continued_feynman_form(m1):
 def test_pole_sum_has_a_contour_everywhere_off_the_real_axis():
     """A complex-conjugate pair on the (p-k) leg (1 +- 0.8i, residues 1/2) and
     two real poles on the k leg: on the pole-sum benchmark box no point off
-    the real axis is left without a contour in D = 4 (46 % were, before the
-    long way round); D = 3, where a turn the long way round changes the branch
-    of sqrt(y), keeps those points SINGULAR."""
+    the real axis is left without a contour (46 % were, before the long way
+    round), in D = 4 and in D = 3 with the same classes."""
     grid = Grid(64, 64, -16.0, 8.0, -8.0, 8.0)
     x = oracle.grid_points(grid)
     cls = oracle.classify(Params(1.0, 1.0, 1.0, 1e6), Q, x, props=GRIBOV1)
@@ -76,7 +77,7 @@ def test_pole_sum_has_a_contour_everywhere_off_the_real_axis():
     assert (cls == oracle.LONG).mean() > 0.3
     cls3 = oracle.classify(Params(1.0, 1.0, 1.0, 1e6, 1.0, 0, 3), Quadrature(512, 256, 16, 0, 3),
                            x, props=GRIBOV1)
-    assert np.array_equal(cls3 == oracle.SINGULAR, cls == oracle.LONG)
+    assert np.array_equal(cls3, cls)
 
 
 WEDGE = [-1.5 + 0.6j, -2.0 + 0.5j, -2.2 + 0.8j, -1.6 - 0.5j, -2.1 - 0.7j, -6.0 + 1.0j, -9.0 - 1.2j]
@@ -135,6 +136,54 @@ def test_long_class_in_two_dimensions_is_cauchy_consistent():
     assert np.max(np.abs(g_long - g_nat) / np.abs(g_nat)) < 1e-11
 
 
+def test_long_class_in_three_dimensions_converges_to_the_mirror_value():
+    """D = 3: the measure sqrt(y) continued along the long rotation has the
+    opposite sign on its ray, arc and far residues.  Where the mirror class
+    applies (paper's masses, inside the threshold) the forced long way round
+    and the mirror value differ only by the radial rule's error, which the
+    sqrt(y) end point makes algebraic: 8 times smaller per doubling of n_r
+    (order 3), so the two converge to one value.  Without the continuation
+    (the principal sqrt(y) on the long rotation) they would differ at O(1)."""
+    from paper_1205_0752_amd.workloads import GL
+    xs = [-0.3 + 0.4j, -0.5 + 0.3j, -0.6 + 0.5j]
+    d = []
+    for nr in (256, 512):
+        p = Params(-0.5j, 0.5j, 0.0, 1e6, 1.0, -1, 3)
+        q = Quadrature(nr, 256, 16, 0, GL)
+        g_long, _ = oracle.eval_points(p, q, xs, force_class=oracle.LONG)
+        g_nat, c_nat = oracle.eval_points(p, q, xs)
+        assert np.all(c_nat == oracle.MIRROR)
+        d.append(np.abs(g_long - g_nat) / np.abs(g_nat))
+    assert np.all(d[1] < 2e-7)
+    assert np.all((d[0] / d[1] > 7.0) & (d[0] / d[1] < 9.0)), d[0] / d[1]
+
+
+@pytest.mark.parametrize("phi0", [-160.0, 160.0])
+def test_long_residues_in_three_dimensions_keep_g_continuous(phi0):
+    """D = 3: a (p-k)-leg pole 1 + 0.8i (bad ray -141.3 degrees) and a k-leg
+    pole whose bad ray lies at -160 degrees (and the mirror image of the
+    setup).  Just inside that ray the long rotation sweeps the k-leg pole past
+    the negative real axis, where the continued sqrt(y0) has the opposite sign
+    of the principal one; just outside it sweeps no pole.  G is analytic
+    across the ray, so the two sides' values, extrapolated to it (split radial
+    rule, quadratic in the distance), must meet: they do to 4e-4 (D = 4,
+    where the measure has no square root: 2e-4); with the principal sqrt(y0)
+    the residue enters with the wrong sign and they miss by O(1)."""
+    from paper_1205_0752_amd.workloads import GC2
+    m2 = np.exp(1j * np.deg2rad(20.0))
+    m1, m2 = (1 + 0.8j, m2) if phi0 < 0 else (1 - 0.8j, np.conj(m2))
+    for dim, rule, tol in ((3, GL, 2e-3), (4, GC2, 1e-3)):
+        p = Params(m1, m2, 1.0, 1e6, 1.0, 0, dim)
+        q = Quadrature(1024, 128, 32, 0, rule, 1)
+        side = []
+        for sgn in (-1, 1):
+            xs = 3.0 * np.exp(1j * (np.deg2rad(phi0) + sgn * np.array([0.02, 0.04, 0.06])))
+            g, c = oracle.eval_points(p, q, xs)
+            assert np.all(c == oracle.LONG)
+            side.append(3 * g[0] - 3 * g[1] + g[2])
+        assert abs(side[1] - side[0]) <= tol * abs(side[1]), (dim, abs(side[1] - side[0]) / abs(side[1]))
+
+
 # ---------------------------------------------------------------- GPU
 
 def _gpu():
@@ -156,13 +205,14 @@ def _gpu_scan(gf, torch, p, q, grid, props=None, lanes=0):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("case", ["gribov1", "gribov1_t2", "gribov1_d2", "single_pole"])
+@pytest.mark.parametrize("case", ["gribov1", "gribov1_t2", "gribov1_d2", "gribov1_d3", "single_pole",
+                                  "single_pole_d3"])
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32c"])
 def test_gpu_long_points_match_oracle(case, prec):
     """Every point of two ragged grids (one of them the complex-mass box)
     against the oracle, LONG points included: the conjugate pair on the
-    (p-k) leg with t^0, t^2 and in D = 2, and a single complex (p-k)-leg pole
-    without mirror symmetry; several lane splits."""
+    (p-k) leg with t^0, t^2 and in D = 2 and 3, and a single complex (p-k)-leg
+    pole without mirror symmetry (D = 4 and 3); several lane splits."""
     torch, gf = _gpu()
     props, dim, order, rule = GRIBOV1, 4, 0, 0
     m1 = 1.0
@@ -170,8 +220,12 @@ def test_gpu_long_points_match_oracle(case, prec):
         order = 2
     elif case == "gribov1_d2":
         dim, order, rule = 2, -1, GC1
-    elif case == "single_pole":
+    elif case == "gribov1_d3":
+        dim, rule = 3, GL
+    elif case.startswith("single_pole"):
         props, m1 = None, 1 + 0.8j
+        if case.endswith("d3"):
+            dim, rule = 3, GL
     p = Params(m1, 1.0, 1.0, 1e6, 1.0, order, dim)
     q = Quadrature(64, 32, 16, prec, rule)
     n_long = 0
