@@ -87,6 +87,8 @@ def _load():
                                             ctypes.c_double, dp, dp]
         lib.orc_yscan.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double,
                                   ctypes.c_long, dp, dp, ctypes.c_int, dp]
+        lib.orc_point_contours.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                           ctypes.POINTER(ctypes.c_int)]
         _lib = lib
     return _lib
 
@@ -100,6 +102,8 @@ def _loadq():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.orcq_eval_points.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
                                          dp, ctypes.c_char_p]
+        lib.orcq_eval_points_sets.argtypes = [ctypes.POINTER(_Problem), ctypes.c_long, dp, dp,
+                                              ctypes.POINTER(ctypes.c_int), dp]
         _libq = lib
     return _libq
 
@@ -261,6 +265,24 @@ def eval_points_q(params, quad, x):
     if lib.orcq_eval_points(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), _dp(g), cls) != 0:
         raise ValueError("the quad-precision twin rejected the problem")
     return g[0::2] + 1j * g[1::2], np.frombuffer(cls.raw[:x.size], dtype=np.int8).copy()
+
+
+def eval_points_q_sets(params, quad, x, props=None):
+    """Quad-precision run of the same quadrature for pole sums, numerators and
+    every contour class (the long way round included), on the contours the
+    FP64 oracle chooses (passed as data: the comparison measures rounding
+    only).  Returns G (NaN where no contour)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).ravel())
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    pr = problem(params, quad, props)
+    info = np.zeros(7 * max(x.size, 1), dtype=np.int32)
+    ip = info.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    _load().orc_point_contours(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), ip)
+    g = np.zeros(2 * x.size)
+    if _loadq().orcq_eval_points_sets(ctypes.byref(pr), x.size, _dp(xr), _dp(xi), ip, _dp(g)) != 0:
+        raise ValueError("the quad-precision twin rejected the problem")
+    return g[0::2] + 1j * g[1::2]
 
 
 def yscan(params, quad, x: complex, y, what: int = 0, props=None) -> np.ndarray:

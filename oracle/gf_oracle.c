@@ -1028,6 +1028,41 @@ int orc_classify_points(const orc_problem *p, long n, const double *x_re, const 
     return 0;
 }
 
+/* The contour each point is evaluated on, for the quad-precision twin:
+ * info[7k..7k+6] = {evaluated at conj x (MIRROR), class there, residue sign,
+ * k-leg residues of the short rotation, (p-k)-leg poles of the long rotation,
+ * k-leg residues of the long rotation, 0}. */
+int orc_point_contours(const orc_problem *p, long n, const double *x_re, const double *x_im,
+                       int *info)
+{
+    orc_geometry g;
+    orc_make_geometry(p, &g);
+    for (long k = 0; k < n; ++k) {
+        cplx x = x_re[k] + I * x_im[k];
+        int sign = 0, mask = 0, conj_eval = 0;
+        int cls = orc_final_class(&g, x, &sign, &mask);
+        if (cls == ORC_MIRROR) {
+            x = conj(x);
+            cls = orc_classify_m(&g, x, &sign, &mask);
+            conj_eval = 1;
+        }
+        int grp_long = 0, res_short = mask, res_long = 0;
+        if (cls == ORC_LONG) {
+            orc_long_sets(&g, carg(x), &grp_long, &res_short, &res_long);
+            sign = carg(x) > 0.0 ? 1 : -1;
+        }
+        int *o = info + 7 * k;
+        o[0] = conj_eval;
+        o[1] = cls;
+        o[2] = sign;
+        o[3] = res_short;
+        o[4] = grp_long;
+        o[5] = res_long;
+        o[6] = 0;
+    }
+    return 0;
+}
+
 /* Threads an OpenMP region of the oracle uses. */
 int orc_threads(void) { return omp_get_max_threads(); }
 

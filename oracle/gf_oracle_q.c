@@ -353,3 +353,249 @@ int orcq_eval_points(const orcq_problem *p, long n, const double *x_re, const do
     free(t); free(tw); free(c.r); free(c.wr); free(c.ax); free(c.aw); free(c.az); free(c.azw);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* General integrands: pole sums, numerators, the long way round             */
+/* ------------------------------------------------------------------------ */
+
+/* The same quadrature for pole-sum propagators P1 = sum_a c1_a/(s + m1_a^2),
+ * P2 = sum_b c2_b/(s + m2_b^2), an optional numerator N(k^2, p.k), every
+ * contour class including the long way round, in quad precision.  The
+ * contour of each point is not chosen here: it is given (class, residue
+ * sign and pole sets, as the FP64 oracle chose them; a discrete choice, not
+ * a rounding), so that the comparison measures rounding alone.  Per point,
+ * info[7k..7k+6] = {evaluated at conj x (MIRROR), class at the evaluated
+ * point, residue sign, k-leg residues of the short rotation, (p-k)-leg poles
+ * of the long rotation, k-leg residues of the long rotation, 0}. */
+typedef struct {
+    const orcq_problem *p;
+    int n1, n2, dim;
+    qc m1[8], c1[8], m2[8], c2[8];
+    qc num[9];
+    int num_on;
+    qr *r, *wr, *ax, *aw, *az, *azw;
+    qc jmu;
+    qc taylor[9];
+} qgen;
+
+static qc q_meas(int dim, qc y, qc sy)
+{
+    return dim == 4 ? y : (dim == 3 ? sy : mkc(1, 0));
+}
+
+/* sum over the (p-k)-leg poles in `set` of c1_a sum_j w_j N_j / D1_j,
+ * D1_j = x + y + m1_a^2 - 2 sxsy z_j, N_j = N(y, sxsy z_j) (1 without one) */
+static qc q_ang_set(const qgen *g, qc x, qc y, qc sxsy, int set)
+{
+    const int na = g->p->n_angular;
+    qc s = 0;
+    for (int a = 0; a < g->n1; ++a) {
+        if (!(set >> a & 1)) continue;
+        qc acc = 0;
+        for (int j = 0; j < na; ++j) {
+            qc d = x + y - 2 * sxsy * g->az[j] + g->m1[a];
+            qc nv = 1;
+            if (g->num_on) {
+                qc pk = sxsy * g->az[j];
+                nv = 0;
+                qc yi = 1;
+                for (int i = 0; i <= 2; ++i) {
+                    qc pj = 1;
+                    for (int q = 0; q <= 2; ++q) {
+                        nv += g->num[3 * i + q] * yi * pj;
+                        pj *= pk;
+                    }
+                    yi *= y;
+                }
+            }
+            acc += g->azw[j] * nv / d;
+        }
+        s += g->c1[a] * acc;
+    }
+    return s;
+}
+
+static qc q_p2(const qgen *g, qc y)
+{
+    qc s = 0;
+    for (int b = 0; b < g->n2; ++b) s += g->c2[b] / (y + g->m2[b]);
+    return s;
+}
+
+/* the contour sum at the evaluated point x for the given class and sets */
+static qc q_contour_gen(const qgen *g, qc x, int cls, int sign, int res_short, int grp_long,
+                        int res_long)
+{
+    const orcq_problem *p = g->p;
+    const int all = (1 << g->n1) - 1, grp_short = all & ~grp_long;
+    qc sx = csqrtq(x);
+    qc s = 0;
+    if (cls == Q_R) {
+        for (int i = 0; i < p->n_radial; ++i) {
+            qc y = mkc(g->r[i], 0), sy = mkc(sqrtq(g->r[i]), 0);
+            s += g->wr[i] * q_meas(g->dim, y, sy) * q_p2(g, y) * q_ang_set(g, x, y, sx * sy, all);
+        }
+        return s;
+    }
+    qr phi = cargq(x);
+    qc e = mkc(cosq(phi), sinq(phi)), eh = mkc(cosq(phi / 2), sinq(phi / 2));
+    for (int i = 0; i < p->n_radial; ++i) {
+        qc y = e * g->r[i], sy = eh * sqrtq(g->r[i]);
+        qc pre = e * g->wr[i] * q_p2(g, y);
+        if (grp_short)
+            s += pre * q_meas(g->dim, y, sy) * q_ang_set(g, x, y, sx * sy, grp_short);
+        /* the long rotation reaches the ray at phi -+ 2 pi: sqrt(y) changes sign */
+        if (grp_long)
+            s += pre * q_meas(g->dim, y, -sy) * q_ang_set(g, x, y, sx * sy, grp_long);
+    }
+    qr L2 = p->lambda2, Lm = sqrtq(L2);
+    if (grp_short)
+        for (int k = 0; k < p->n_arc; ++k) {
+            qr psi = phi * (1 - g->ax[k]) / 2;
+            qc y = L2 * mkc(cosq(psi), sinq(psi)), sy = Lm * mkc(cosq(psi / 2), sinq(psi / 2));
+            qc dy = mkc(0, -1) * y * (phi / 2) * g->aw[k];
+            s += dy * q_meas(g->dim, y, sy) * q_p2(g, y) * q_ang_set(g, x, y, sx * sy, grp_short);
+        }
+    if (grp_long) {
+        qr Lr = (phi > 0 ? 2 * QPI : -2 * QPI) - phi;
+        for (int k = 0; k < p->n_arc; ++k) {
+            qr psi = phi + Lr * (1 + g->ax[k]) / 2;
+            qc y = L2 * mkc(cosq(psi), sinq(psi)), sy = -Lm * mkc(cosq(psi / 2), sinq(psi / 2));
+            qc dy = mkc(0, 1) * y * (Lr / 2) * g->aw[k];
+            s += dy * q_meas(g->dim, y, sy) * q_p2(g, y) * q_ang_set(g, x, y, sx * sy, grp_long);
+        }
+    }
+    /* residues: the short rotation's with `sign`, the long one's with -sign
+     * and sqrt(y0) at the long rotation's angle */
+    for (int b = 0; b < g->n2; ++b) {
+        qc y0 = -g->m2[b];
+        if (res_short >> b & 1) {
+            qc sy0 = csqrtq(y0);
+            s += sign * 2 * QPI * mkc(0, 1) * g->c2[b] * q_meas(g->dim, y0, sy0) *
+                 q_ang_set(g, x, y0, sx * sy0, grp_short);
+        }
+        if (res_long >> b & 1) {
+            qr t = cargq(y0);
+            if (cimagq(y0) == 0 && crealq(y0) < 0) t = phi > 0 ? -QPI : QPI;
+            else if (phi > 0 && t > phi) t -= 2 * QPI;
+            else if (phi < 0 && t < phi) t += 2 * QPI;
+            qc sy0 = sqrtq(cabsq(y0)) * mkc(cosq(t / 2), sinq(t / 2));
+            s += -sign * 2 * QPI * mkc(0, 1) * g->c2[b] * q_meas(g->dim, y0, sy0) *
+                 q_ang_set(g, x, y0, sx * sy0, grp_long);
+        }
+    }
+    return s;
+}
+
+/* Taylor coefficients K_1..K_n of the real-axis sum about mu^2 by Cauchy's
+ * formula on 64 points of a circle of half the distance from mu^2 to the
+ * nearest x where a node's first propagator (any pole) vanishes. */
+static void q_taylor_gen(qgen *g)
+{
+    const orcq_problem *p = g->p;
+    const int n = p->taylor_order;
+    qr dmin = 1e300Q;
+    for (int i = 0; i < p->n_radial; ++i) {
+        qr sy = sqrtq(g->r[i]);
+        for (int j = 0; j < p->n_angular; ++j)
+            for (int a = 0; a < g->n1; ++a) {
+                qc root = csqrtq(g->r[i] * g->az[j] * g->az[j] - g->r[i] - g->m1[a]);
+                qc s1 = sy * g->az[j] + root, s2 = sy * g->az[j] - root;
+                qr d1 = cabsq(s1 * s1 - p->mu2), d2 = cabsq(s2 * s2 - p->mu2);
+                if (d1 < dmin) dmin = d1;
+                if (d2 < dmin) dmin = d2;
+            }
+    }
+    const qr rho = dmin / 2;
+    const int N = 64;
+    for (int i = 1; i <= n; ++i) g->taylor[i] = 0;
+    for (int k = 0; k < N; ++k) {
+        qc e = mkc(cosq(2 * QPI * k / N), sinq(2 * QPI * k / N));
+        qc S = q_contour_gen(g, p->mu2 + rho * e, Q_R, 0, 0, 0, 0);
+        qc pw = 1;
+        for (int i = 1; i <= n; ++i) {
+            pw *= rho * e;
+            g->taylor[i] += S / pw / N;
+        }
+    }
+}
+
+int orcq_eval_points_sets(const orcq_problem *p, long n, const double *x_re, const double *x_im,
+                          const int *info, double *out)
+{
+    qgen g;
+    memset(&g, 0, sizeof(g));
+    g.p = p;
+    if (p->radial_split || p->taylor_order < -1 || p->taylor_order > 8) return -1;
+    g.dim = p->dimension == 0 ? 4 : p->dimension;
+    if (g.dim < 2 || g.dim > 4) return -1;
+    if (p->n1 == 0) {
+        g.n1 = g.n2 = 1;
+        g.m1[0] = mkc(p->m1sq_re, p->m1sq_im);
+        g.m2[0] = mkc(p->m2sq_re, p->m2sq_im);
+        g.c1[0] = g.c2[0] = 1;
+    } else {
+        if (p->n1 < 1 || p->n1 > 8 || p->n2 < 1 || p->n2 > 8) return -1;
+        g.n1 = p->n1;
+        g.n2 = p->n2;
+        for (int a = 0; a < g.n1; ++a) {
+            g.m1[a] = mkc(p->p1[4 * a], p->p1[4 * a + 1]);
+            g.c1[a] = mkc(p->p1[4 * a + 2], p->p1[4 * a + 3]);
+        }
+        for (int b = 0; b < g.n2; ++b) {
+            g.m2[b] = mkc(p->p2[4 * b], p->p2[4 * b + 1]);
+            g.c2[b] = mkc(p->p2[4 * b + 2], p->p2[4 * b + 3]);
+        }
+    }
+    g.num_on = p->num_on;
+    for (int k = 0; k < 9; ++k) g.num[k] = mkc(p->num[2 * k], p->num[2 * k + 1]);
+    int nr = p->n_radial, nc = p->n_arc > 0 ? p->n_arc : 1;
+    g.az = malloc(sizeof(qr) * p->n_angular);
+    g.azw = malloc(sizeof(qr) * p->n_angular);
+    if (q_angular_rule(p->angular_rule, g.dim, p->n_angular, g.az, g.azw) != 0) {
+        free(g.az);
+        free(g.azw);
+        return -1;
+    }
+    qr *t = malloc(sizeof(qr) * nr), *tw = malloc(sizeof(qr) * nr);
+    g.r = malloc(sizeof(qr) * nr);
+    g.wr = malloc(sizeof(qr) * nr);
+    g.ax = malloc(sizeof(qr) * nc);
+    g.aw = malloc(sizeof(qr) * nc);
+    q_gauss_legendre(nr, t, tw);
+    if (p->n_arc > 0) q_gauss_legendre(p->n_arc, g.ax, g.aw);
+    qr T = log1pq((qr)p->lambda2);
+    for (int i = 0; i < nr; ++i) {
+        qr tt = T * (t[i] + 1) / 2;
+        g.r[i] = expm1q(tt);
+        g.wr[i] = T / 2 * tw[i] * (1 + g.r[i]);
+    }
+    g.jmu = q_contour_gen(&g, mkc(p->mu2, 0), Q_R, 0, 0, 0, 0);
+    if (p->taylor_order > 0) q_taylor_gen(&g);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < n; ++k) {
+        const int *in = info + 7 * k;
+        qc x = mkc(x_re[k], in[0] ? -x_im[k] : x_im[k]);
+        qc gk;
+        if (in[1] == Q_SINGULAR) {
+            gk = mkc(NAN, NAN);
+        } else {
+            qc S = q_contour_gen(&g, x, in[1], in[2], in[3], in[4], in[5]);
+            qc sub = 0;
+            if (p->taylor_order >= 0) {
+                sub = g.jmu;
+                qc d = x - p->mu2, pw = 1;
+                for (int i = 1; i <= p->taylor_order; ++i) {
+                    pw *= d;
+                    sub += pw * g.taylor[i];
+                }
+            }
+            gk = (qr)p->scale * (S - sub);
+            if (in[0]) gk = conjq(gk);
+        }
+        out[2 * k] = (double)crealq(gk);
+        out[2 * k + 1] = (double)cimagq(gk);
+    }
+    free(t); free(tw); free(g.r); free(g.wr); free(g.ax); free(g.aw); free(g.az); free(g.azw);
+    return 0;
+}
