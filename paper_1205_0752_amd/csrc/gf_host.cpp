@@ -498,6 +498,7 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     tiles_for(g, lanes, &a.tiles_a, &nt);
     if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
     a.n_tiles = (int)nt;
+    a.tail_tiles = a.tail_row0 = a.tail_tiles_a = 0;
     // The FP64 angular sums multiply eight denominators |U^2 - V^2 s|^2 <=
     // 25 M^4, M = |x| + |y| + |m1^2|, into one reciprocal; below M = 2^30 the
     // product stays under 2^1000 without the rescaling by 2^-e.
@@ -507,6 +508,40 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     const double xmax2 = std::max(std::hypot(g.re_lo, g.im_hi), std::hypot(g.re_hi, g.im_lo));
     a.unscaled = std::max(xmax, xmax2) + a.lam2 + m1max < std::ldexp(1.0, 30) ? 1 : 0;
     return GF_OK;
+}
+
+// The tail of a large automatically-laned scan: the plain FP64 kernel at one
+// lane per point, at least kTailMinRounds rounds of its resident waves, gets its
+// last rows as tiles of kTailLanes lanes per point, about a quarter round of
+// one-lane work (16 points per resident wave), with the rows before them a
+// whole number of one-lane tiles.  Measured on the 1024^2 bench grid
+// (256 x 128 + 16 nodes, one box, ms): no tail 4.37-4.41; 64 rows at 16 lanes
+// 4.27-4.29, at 4 lanes 4.32-4.34, at 8 lanes 4.33-4.34, at 32 lanes 4.34;
+// 32 rows at 16 lanes 4.39-4.40 (too few to cover the drain), 128 rows 4.34
+// (every lane repeats its point's setup).
+constexpr long long kTailMinRounds = 2;
+constexpr long long kTailPointsPerWave = 16;
+
+void set_tail(ScanArgs &a, const gf_grid &g, int precision, int lanes)
+{
+    a.tail_tiles = a.tail_row0 = a.tail_tiles_a = 0;
+    if (precision != 0 || lanes != 1 || a.n_taylor > 0 || a.split || a.poles) return;
+    const long long slots = scan_resident_waves(0, 1, false, false, false);
+    if (a.n_tiles < kTailMinRounds * slots || g.n_re <= 0) return;
+    int tw1, th1, twt, tht;
+    tile_shape(1, &tw1, &th1);
+    tile_shape(kTailLanes, &twt, &tht);
+    const long long rows = std::max(1LL, (kTailPointsPerWave * slots + g.n_re / 2) / g.n_re);
+    const long long row0 = (g.n_im - rows) / th1 * th1;  // whole one-lane tiles before it
+    if (row0 < th1) return;
+    const long long ta = (g.n_re + twt - 1) / twt;
+    const long long tt = ta * ((g.n_im - row0 + tht - 1) / tht);
+    const long long bulk = (long long)a.tiles_a * (row0 / th1);
+    if (bulk + tt > (1LL << 30)) return;
+    a.tail_row0 = (int)row0;
+    a.tail_tiles_a = (int)ta;
+    a.tail_tiles = (int)tt;
+    a.n_tiles = (int)(bulk + tt);
 }
 
 int current_device(int *dev)
@@ -693,6 +728,7 @@ int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_
                     dev);
     gf::ScanArgs a = plan->base;
     if ((rc = gf::set_grid(a, *grid, lanes)) != GF_OK) return rc;
+    if (lanes_per_point == 0) gf::set_tail(a, *grid, plan->quad.precision, lanes);
     a.out = static_cast<double *>(out);
     a.cls = cls_out;
     hipError_t e = gf::launch_scan(a, plan->quad.precision, lanes, static_cast<hipStream_t>(stream));

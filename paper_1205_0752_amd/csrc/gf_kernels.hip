@@ -27,16 +27,18 @@ namespace {
 // point's result does not depend on which launch computes it.
 // TAYLOR = false compiles out the t^n (n >= 1) epilogue, so the order-0 scan
 // carries no extra live values; both forms compute order 0 identically.
+// Tiles are numbered row-major over the rows from row0 on, tiles_a per row.
 template <int PREC, int L, bool TAYLOR, bool SPLIT, bool POLES, class Args>
-__device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
+__device__ __forceinline__ void process_tile(const Args &a, int tile, int lane, int row0,
+                                             int tiles_a)
 {
     constexpr int P = 64 / L;
     constexpr int TW = P < 8 ? P : 8;
     constexpr int TH = P / TW;
     const int p = lane / L;
     const int s = lane % L;
-    const int ia = (tile % a.tiles_a) * TW + p % TW;
-    const int ib = (tile / a.tiles_a) * TH + p / TW;
+    const int ia = (tile % tiles_a) * TW + p % TW;
+    const int ib = row0 + (tile / tiles_a) * TH + p / TW;
     const bool valid = ia < a.n_re && ib < a.n_im;
 
     double xr = fma((double)ia + 0.5, a.d_re, a.re_lo);
@@ -174,13 +176,28 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane)
 // points without a contour ends at once), and a one-wave workgroup frees its
 // slot for the next tile by itself, where a four-wave workgroup would hold
 // the slots of its finished waves until the last one ends.
+//
+// The tail of a large one-lane scan: its last rows run as tiles of 64 / 16
+// points at 16 lanes per point, a sixteenth of a one-lane wave's work each,
+// dispatched after every one-lane tile.  They fill the slots that the last
+// round of one-lane waves leaves as it drains (waves sharing a SIMD progress
+// oldest first, so a SIMD's last waves end one by one), where otherwise SIMDs
+// would run one or two waves that cannot hide the reciprocal's latency.
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 scan_kernel_fp64(ScanArgs a)
 {
     const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<0, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
+    // (written as one if-else: an early return gave the tail's pair loop
+    // scalar-register spills)
+    if (L == 1 && !TAYLOR && !SPLIT && !POLES && a.tail_tiles > 0 &&
+        wave >= a.n_tiles - a.tail_tiles)
+        process_tile<0, kTailLanes, TAYLOR, SPLIT, POLES>(a, wave - (a.n_tiles - a.tail_tiles),
+                                                          threadIdx.x & 63, a.tail_row0,
+                                                          a.tail_tiles_a);
+    else
+        process_tile<0, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63, 0, a.tiles_a);
 }
 
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
@@ -189,7 +206,7 @@ scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63);
+    process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63, 0, a.tiles_a);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
@@ -207,7 +224,8 @@ __device__ __forceinline__ void serve_loop(const ScanArgs *reqs, const WorkItem 
         if (w >= (unsigned)n_items) break;
         const int req = ro(items)[w].req;
         const int tile = ro(items)[w].tile;
-        process_tile<PREC, L, true, SPLIT, POLES>(ro(reqs)[req], tile, lane);
+        const auto &r = ro(reqs)[req];  // keeps the constant address space
+        process_tile<PREC, L, true, SPLIT, POLES>(r, tile, lane, 0, r.tiles_a);
     }
 }
 

@@ -242,6 +242,7 @@ extern "C" int gf_scan_noalloc(const gf_params *params, const gf_grid *grid,
     a.wmid = middle_weight(quad->n_angular, quad->angular_rule, dim);
     const int lanes = auto_lanes(a, quad->precision, *grid);
     if ((rc = set_grid(a, *grid, lanes)) != GF_OK) return rc;
+    set_tail(a, *grid, quad->precision, lanes);
     a.out = static_cast<double *>(out);
     a.cls = nullptr;
 
