@@ -287,11 +287,11 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
  * contour), but none that leaves a lane fewer than 2048 angular pairs (4096
  * in FP32C), and
  * never fewer lanes than fill the GPU once: 1 for large grids, more for
- * smaller ones.  A large one-lane FP64 scan without t^n (n >= 1), split rule
- * or pole sums (at least two rounds of resident waves) runs its last rows,
- * about 16 points per resident wave, at 16 lanes per point in the same launch,
- * which shortens the end of the launch.  Results depend on the lane count only
- * through rounding. */
+ * smaller ones.  A large scan at one lane per point (FP32C: one or two)
+ * without t^n (n >= 1), split rule or pole sums (at least two rounds of
+ * resident waves) runs its last rows, about a quarter round of its work, at 16
+ * lanes per point in the same launch, which shortens the end of the launch.
+ * Results depend on the lane count only through rounding. */
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
                     int lanes_per_point, void *stream);
 

@@ -510,33 +510,38 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     return GF_OK;
 }
 
-// The tail of a large automatically-laned scan: the plain FP64 kernel at one
-// lane per point, at least kTailMinRounds rounds of its resident waves, gets its
-// last rows as tiles of kTailLanes lanes per point, about a quarter round of
-// one-lane work (16 points per resident wave), with the rows before them a
-// whole number of one-lane tiles.  Measured on the 1024^2 bench grid
-// (256 x 128 + 16 nodes, one box, ms): no tail 4.37-4.41; 64 rows at 16 lanes
-// 4.27-4.29, at 4 lanes 4.32-4.34, at 8 lanes 4.33-4.34, at 32 lanes 4.34;
-// 32 rows at 16 lanes 4.39-4.40 (too few to cover the drain), 128 rows 4.34
-// (every lane repeats its point's setup).
+// The tail of a large automatically-laned scan: the plain kernels (no t^n,
+// n >= 1, split rule or pole sums) at one lane per point, FP32C also at two,
+// with at least kTailMinRounds rounds of their resident waves, get their last
+// rows as tiles of kTailLanes lanes per point: about a quarter round of the
+// bulk's work (16 / lanes points per resident wave), with the rows before them
+// a whole number of bulk tiles.  Measured (one box per line, ms): FP64 1024^2
+// bench grid (256 x 128 + 16 nodes, one lane) no tail 4.37-4.41; 64 rows at 16
+// lanes 4.27-4.29, at 4 lanes 4.32-4.34, at 8 lanes 4.33-4.34, at 32 lanes
+// 4.34; 32 rows at 16 lanes 4.39-4.40 (too few to cover the drain), 128 rows
+// 4.34 (every lane repeats its point's setup).  FP32C 1024^2 at 512 x 256 + 16
+// nodes (two lanes): 11.97-11.98 without, 11.65-11.66 with 32-64 rows, 11.69-11.73
+// with 96; 2048^2 (one lane): 45.9-46.1 without, 45.1-45.2 with 32-64 rows.
 constexpr long long kTailMinRounds = 2;
-constexpr long long kTailPointsPerWave = 16;
+constexpr long long kTailPoints = 16;  // per resident wave, at one lane per point
 
 void set_tail(ScanArgs &a, const gf_grid &g, int precision, int lanes)
 {
     a.tail_tiles = a.tail_row0 = a.tail_tiles_a = 0;
-    if (precision != 0 || lanes != 1 || a.n_taylor > 0 || a.split || a.poles) return;
-    const long long slots = scan_resident_waves(0, 1, false, false, false);
+    if (!(lanes == 1 || (precision == 1 && lanes == 2))) return;
+    if (a.n_taylor > 0 || a.split || a.poles) return;
+    const long long slots = scan_resident_waves(precision, lanes, false, false, false);
     if (a.n_tiles < kTailMinRounds * slots || g.n_re <= 0) return;
-    int tw1, th1, twt, tht;
-    tile_shape(1, &tw1, &th1);
+    int twb, thb, twt, tht;
+    tile_shape(lanes, &twb, &thb);
     tile_shape(kTailLanes, &twt, &tht);
-    const long long rows = std::max(1LL, (kTailPointsPerWave * slots + g.n_re / 2) / g.n_re);
-    const long long row0 = (g.n_im - rows) / th1 * th1;  // whole one-lane tiles before it
-    if (row0 < th1) return;
+    const long long points = kTailPoints * slots / lanes;
+    const long long rows = std::max(1LL, (points + g.n_re / 2) / g.n_re);
+    const long long row0 = (g.n_im - rows) / thb * thb;  // whole bulk tiles before it
+    if (row0 < thb) return;
     const long long ta = (g.n_re + twt - 1) / twt;
     const long long tt = ta * ((g.n_im - row0 + tht - 1) / tht);
-    const long long bulk = (long long)a.tiles_a * (row0 / th1);
+    const long long bulk = (long long)a.tiles_a * (row0 / thb);
     if (bulk + tt > (1LL << 30)) return;
     a.tail_row0 = (int)row0;
     a.tail_tiles_a = (int)ta;

@@ -177,12 +177,13 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane, 
 // slot for the next tile by itself, where a four-wave workgroup would hold
 // the slots of its finished waves until the last one ends.
 //
-// The tail of a large one-lane scan: its last rows run as tiles of 64 / 16
-// points at 16 lanes per point, a sixteenth of a one-lane wave's work each,
-// dispatched after every one-lane tile.  They fill the slots that the last
-// round of one-lane waves leaves as it drains (waves sharing a SIMD progress
-// oldest first, so a SIMD's last waves end one by one), where otherwise SIMDs
-// would run one or two waves that cannot hide the reciprocal's latency.
+// The tail of a large scan at one lane per point (FP32C: one or two): its last
+// rows run as tiles of 64 / 16 points at 16 lanes per point, a sixteenth of a
+// one-lane wave's work each, dispatched after every other tile.  They fill
+// the slots that the last round of long waves leaves as it drains (waves
+// sharing a SIMD progress oldest first, so a SIMD's last waves end one by
+// one), where otherwise SIMDs would run one or two waves that cannot hide the
+// reciprocal's latency.
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 scan_kernel_fp64(ScanArgs a)
@@ -206,7 +207,13 @@ scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
-    process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63, 0, a.tiles_a);
+    if ((L == 1 || L == 2) && !TAYLOR && !SPLIT && !POLES && a.tail_tiles > 0 &&
+        wave >= a.n_tiles - a.tail_tiles)
+        process_tile<1, kTailLanes, TAYLOR, SPLIT, POLES>(a, wave - (a.n_tiles - a.tail_tiles),
+                                                          threadIdx.x & 63, a.tail_row0,
+                                                          a.tail_tiles_a);
+    else
+        process_tile<1, L, TAYLOR, SPLIT, POLES>(a, wave, threadIdx.x & 63, 0, a.tiles_a);
 }
 
 // Serving: a persistent launch over a packed list of (request, tile) items of
