@@ -88,6 +88,59 @@ def test_ragged_grid_all_lane_splits(lanes):
     _compare(g, c, p, q, oracle.grid_points(grid), go, co, cond)
 
 
+@pytest.mark.parametrize("prec,n_im", [(0, 1024), (1, 1000)], ids=["fp64", "fp32c"])
+def test_tail_rows_on_a_ragged_grid(prec, n_im):
+    """A large scan at the automatic lane count (one lane per point here) runs
+    its last rows at 16 lanes per point in the same launch.  On a 1030-wide
+    grid (the tail's tiles hold four points, the last one half outside the
+    grid) every point is written, its class equals the one-lane scan's and
+    its value the one-lane scan's up to rounding, and points of the last 128
+    rows (the tail and the rows before it) match the oracle at the parity
+    bar; the allocation-free scan, which takes the same tail on node tables
+    generated on the device (equal to the plan's to the last bits), writes
+    every point too and agrees to rounding."""
+    p = Params(1.0, 1.0, 1.0, 1e6)
+    q = Quadrature(128, 64, 16, prec)
+    grid = Grid(1030, n_im, -16.0, 8.0, -8.0, 8.0)
+    plan = gf.Plan(p, q)
+    assert plan.auto_lanes(grid) == 1
+    auto = gf.empty_result(grid)
+    auto.fill_(complex(float("nan"), 7.0))
+    cls_a = torch.full((grid.n_im, grid.n_re), 9, dtype=torch.int8, device="cuda")
+    gf.scan_plan(plan, grid, auto, cls_a)
+    cls_1 = torch.empty_like(cls_a)
+    one = gf.scan_plan(plan, grid, cls=cls_1, lanes=1)
+    na = gf.empty_result(grid)
+    na.fill_(complex(float("nan"), 7.0))
+    gf.scan_noalloc(p, grid, q, na)
+    torch.cuda.synchronize()
+    plan.close()
+    g, g1, gn = (t.cpu().numpy().ravel() for t in (auto, one, na))
+    c, c1 = cls_a.cpu().numpy().ravel(), cls_1.cpu().numpy().ravel()
+    assert np.array_equal(c, c1) and not np.any(c == 9)
+    sing = c == oracle.SINGULAR
+    for v in (g, gn):
+        assert np.all(np.isnan(v[sing])) and np.all(np.isfinite(v[~sing]))
+    scale = np.max(np.abs(g1[~sing]))
+    tol = 1e-13 if prec == 0 else 1e-6
+    assert np.max(np.abs(g[~sing] - g1[~sing])) <= tol * scale
+    # the device-generated tables move the quadrature by a few ulp, which the
+    # points near the angular cut amplify (kappa): a looser bar, still far
+    # below what a misplaced or missing tile would show
+    assert np.max(np.abs(gn[~sing] - g[~sing])) <= (1e-9 if prec == 0 else 2e-6) * scale
+    rows = np.arange(grid.n_points) // grid.n_re
+    rng = np.random.default_rng(5)
+    pick = rng.choice(np.nonzero((rows >= n_im - 128) & ~sing)[0], 300, replace=False)
+    x = oracle.grid_points(grid)[pick]
+    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
+    assert (co != c[pick]).sum() <= 1
+    keep = co == c[pick]
+    if prec == 0:
+        check_fp64(g[pick][keep], go[keep], cond[keep])
+    else:
+        check_fp32c(g[pick][keep], go[keep])
+
+
 def test_paper_worked_example_box_matches_oracle():
     """The paper's worked example (m1^2 = -i/2, m2^2 = +i/2, mu^2 = 0) on its
     display box (128^2 over +-5, STEP 4), all four contour classes."""
