@@ -282,16 +282,13 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
  * (1, 2, 4, ..., 64; 0 = automatic).  Each point's quadrature nodes are
  * split across that many lanes of a 64-wide wavefront and the partial sums
  * reduced with cross-lane shuffles.  Automatic takes the smallest count whose
- * wave tiles make at least 4 rounds of the kernel's resident waves (16 for pole
- * sums with a complex (p-k)-leg pole, whose plane can hold points without a
- * contour), but none that leaves a lane fewer than 2048 angular pairs (4096
- * in FP32C), and
- * never fewer lanes than fill the GPU once: 1 for large grids, more for
- * smaller ones.  A large scan at one lane per point (FP32C: one or two)
- * without t^n (n >= 1), split rule or pole sums (at least two rounds of
- * resident waves) runs its last rows, about a quarter round of its work, at 16
- * lanes per point in the same launch, which shortens the end of the launch.
- * Results depend on the lane count only through rounding. */
+ * wave tiles make at least 4 rounds of the kernel's resident waves, but none
+ * that leaves a lane fewer than 2048 angular pairs (4096 in FP32C), and never
+ * fewer lanes than fill the GPU once: 1 for large grids, more for smaller
+ * ones.  A large scan at one lane per point (FP32C: one or two; at least two
+ * rounds of resident waves) runs its last rows, about a quarter round of its
+ * work, at 16 lanes per point in the same launch, which shortens the end of
+ * the launch.  Results depend on the lane count only through rounding. */
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
                     int lanes_per_point, void *stream);
 

@@ -450,9 +450,8 @@ int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid
 // Lanes per point, the smallest count that meets three aims:
 //  * several rounds of the kernel's resident waves per launch, since the last
 //    round drains with SIMDs left one or two waves that cannot hide latency:
-//    kRounds rounds, four times that when a complex pole on the (p-k) leg can
-//    leave part of the plane without a contour (those tiles end at once; about
-//    half of them for a conjugate pair);
+//    kRounds rounds (a launch at one lane per point, FP32C also at two, then
+//    runs its last rows as a tail of short waves, set_tail);
 //  * but no count that leaves a lane fewer than kMinLanePairs angular pairs
 //    (its share of a point's contour nodes x pairs per node x (p-k)-leg
 //    poles), since every lane repeats its point's setup and the nodes split
@@ -466,9 +465,7 @@ constexpr long long kMinLanePairs[2] = {2048, 4096};  // FP64, FP32C
 int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g)
 {
     const bool taylor = base.n_taylor > 0, split = base.split != 0, poles = base.poles != 0;
-    bool open_plane = false;  // a complex (p-k)-leg pole in a pole sum
-    for (int i = 0; poles && i < base.n1; ++i) open_plane = open_plane || base.p1[4 * i + 1] != 0.0;
-    const long long rounds = open_plane ? 4 * kRounds : kRounds;
+    const long long rounds = kRounds;
     const long long pairs = (long long)((base.n_a + 1) / 2) * (poles ? base.n1 : 1);
     const long long nodes = (long long)base.n_r + base.n_arc + (poles ? base.n2 : 1);
     int fill = 0, want = 0, work = 1;
@@ -510,9 +507,9 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     return GF_OK;
 }
 
-// The tail of a large automatically-laned scan: the plain kernels (no t^n,
-// n >= 1, split rule or pole sums) at one lane per point, FP32C also at two,
-// with at least kTailMinRounds rounds of their resident waves, get their last
+// The tail of a large automatically-laned scan: every kernel form (t^n, split
+// rule, pole sums and numerators alike) at one lane per point, FP32C also at
+// two, with at least kTailMinRounds rounds of its resident waves, gets its last
 // rows as tiles of kTailLanes lanes per point: about a quarter round of the
 // bulk's work (16 / lanes points per resident wave), with the rows before them
 // a whole number of bulk tiles.  Measured (one box per line, ms): FP64 1024^2
@@ -522,6 +519,10 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
 // 4.34 (every lane repeats its point's setup).  FP32C 1024^2 at 512 x 256 + 16
 // nodes (two lanes): 11.97-11.98 without, 11.65-11.66 with 32-64 rows, 11.69-11.73
 // with 96; 2048^2 (one lane): 45.9-46.1 without, 45.1-45.2 with 32-64 rows.
+// The other forms on the bench grid and nodes (one box): t^2 4.38 -> 4.25,
+// split rule 5.07 -> 4.83; pole sums (a conjugate pair on the (p-k) leg, two
+// k-leg poles) at four lanes without a tail 9.33, at one lane with it 8.99,
+// and with a numerator 13.25 -> 12.57.
 constexpr long long kTailMinRounds = 2;
 constexpr long long kTailPoints = 16;  // per resident wave, at one lane per point
 
@@ -529,8 +530,8 @@ void set_tail(ScanArgs &a, const gf_grid &g, int precision, int lanes)
 {
     a.tail_tiles = a.tail_row0 = a.tail_tiles_a = 0;
     if (!(lanes == 1 || (precision == 1 && lanes == 2))) return;
-    if (a.n_taylor > 0 || a.split || a.poles) return;
-    const long long slots = scan_resident_waves(precision, lanes, false, false, false);
+    const long long slots =
+        scan_resident_waves(precision, lanes, a.n_taylor > 0, a.split != 0, a.poles != 0);
     if (a.n_tiles < kTailMinRounds * slots || g.n_re <= 0) return;
     int twb, thb, twt, tht;
     tile_shape(lanes, &twb, &thb);

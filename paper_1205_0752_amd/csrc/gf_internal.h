@@ -70,7 +70,7 @@ struct ScanArgs {
     double re_lo, d_re, im_lo, d_im;
     int tiles_a;  // wave tiles along Re
     int n_tiles;  // total wave tiles
-    // large plain scans at one lane per point (FP32C: one or two): the last
+    // large scans at one lane per point (FP32C: one or two): the last
     // tail_tiles tiles cover the rows from tail_row0 on at kTailLanes lanes per
     // point (tail_tiles_a of them per row)
     int tail_tiles, tail_row0, tail_tiles_a;
@@ -147,8 +147,8 @@ int validate_grid(const gf_params &p, const gf_propagators *props, const gf_grid
 int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g);
 // grid fields and wave tiles of a ScanArgs for `lanes` lanes per point
 int set_grid(ScanArgs &a, const gf_grid &g, int lanes);
-// for an automatically chosen lane count: give a large plain scan at one lane
-// per point (FP32C: one or two) its tail of short waves (no change otherwise)
+// for an automatically chosen lane count: give a large scan at one lane per
+// point (FP32C: one or two) its tail of short waves (no change otherwise)
 void set_tail(ScanArgs &a, const gf_grid &g, int precision, int lanes);
 int current_device(int *dev);
 size_t align256(size_t b);

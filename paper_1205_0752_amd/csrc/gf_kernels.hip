@@ -177,7 +177,8 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane, 
 // slot for the next tile by itself, where a four-wave workgroup would hold
 // the slots of its finished waves until the last one ends.
 //
-// The tail of a large scan at one lane per point (FP32C: one or two): its last
+// The tail of a large scan at one lane per point (FP32C: one or two), in every
+// kernel form: its last
 // rows run as tiles of 64 / 16 points at 16 lanes per point, a sixteenth of a
 // one-lane wave's work each, dispatched after every other tile.  They fill
 // the slots that the last round of long waves leaves as it drains (waves
@@ -192,8 +193,7 @@ scan_kernel_fp64(ScanArgs a)
     if (wave >= a.n_tiles) return;  // uniform per wave
     // (written as one if-else: an early return gave the tail's pair loop
     // scalar-register spills)
-    if (L == 1 && !TAYLOR && !SPLIT && !POLES && a.tail_tiles > 0 &&
-        wave >= a.n_tiles - a.tail_tiles)
+    if (L == 1 && a.tail_tiles > 0 && wave >= a.n_tiles - a.tail_tiles)
         process_tile<0, kTailLanes, TAYLOR, SPLIT, POLES>(a, wave - (a.n_tiles - a.tail_tiles),
                                                           threadIdx.x & 63, a.tail_row0,
                                                           a.tail_tiles_a);
@@ -207,8 +207,7 @@ scan_kernel_fp32c(ScanArgs a)
 {
     const int wave = blockIdx.x;
     if (wave >= a.n_tiles) return;  // uniform per wave
-    if ((L == 1 || L == 2) && !TAYLOR && !SPLIT && !POLES && a.tail_tiles > 0 &&
-        wave >= a.n_tiles - a.tail_tiles)
+    if ((L == 1 || L == 2) && a.tail_tiles > 0 && wave >= a.n_tiles - a.tail_tiles)
         process_tile<1, kTailLanes, TAYLOR, SPLIT, POLES>(a, wave - (a.n_tiles - a.tail_tiles),
                                                           threadIdx.x & 63, a.tail_row0,
                                                           a.tail_tiles_a);
