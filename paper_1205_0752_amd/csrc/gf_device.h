@@ -528,15 +528,21 @@ constexpr double kQuad32Sensitivity = 4.0;
 
 // 2 (|U^2|^2 + |V^2|^2) |V^2|^2 and dist^2 |V^2|^2 (no division), on U^2 = (ar, ai),
 // V^2 = (br, bi): the squared ratio, up to a factor of at most 2, is lhs / d2vv.
-// The distance is |U^2| before the segment (dot <= 0), |U^2 - V^2| beyond it
-// (dot >= |V^2|^2), else |cross| / |V^2|.
+// With dot = Re(U^2 conj V^2) and t = dot clamped to [0, |V^2|^2] (the nearest
+// point of the segment [0, V^2] to U^2 is V^2 t / |V^2|^2),
+//   dist^2 |V^2|^2 = |U^2|^2 |V^2|^2 - 2 dot t + t^2,
+// which is |U^2|^2 |V^2|^2 before the segment, |U^2 - V^2|^2 |V^2|^2 beyond it and
+// Im(U^2 conj V^2)^2 beside it, without a branch.  Beside the segment it is a
+// difference whose rounding, ~eps |U^2|^2 |V^2|^2, is far below the threshold's
+// lhs / kCutSensitivity^2: a near node stays near.
 __device__ __forceinline__ void cut_measure(double ar, double ai, double br, double bi,
                                             double &lhs, double &d2vv)
 {
     const double vv = br * br + bi * bi;
     const double uu = ar * ar + ai * ai;
-    const double dot = ar * br + ai * bi, cross = ar * bi - ai * br;
-    d2vv = dot <= 0.0 ? uu * vv : (dot >= vv ? (uu - 2.0 * dot + vv) * vv : cross * cross);
+    const double dot = ar * br + ai * bi;
+    const double t = fmin(fmax(dot, 0.0), vv);
+    d2vv = fma(t, fma(-2.0, dot, t), uu * vv);
     lhs = 2.0 * (uu + vv) * vv;  // 0 when V^2 = 0: the sum is exactly 1/U, never near
 }
 
