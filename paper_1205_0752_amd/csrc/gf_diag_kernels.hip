@@ -57,8 +57,7 @@ struct CutWalk {
     cd dir;     // direction of a straight part
     double lam2;
     bool arc;   // current part: false = straight, true = arc
-    double pu, pi;
-    bool started, hit;
+    bool hit;
 };
 
 __device__ __forceinline__ cd cut_zeta(const CutWalk &w, double u)
@@ -75,75 +74,83 @@ __device__ __forceinline__ cd cut_zeta(const CutWalk &w, double u)
     return cdiv(cmul(U, U), cmul(w.x4, y));
 }
 
-// Im zeta has the sign of Im(U^2 conj(4 x y)) (|4 x y|^2 > 0): the sampling
-// needs no division.
-__device__ __forceinline__ double cut_im_sign(const CutWalk &w, cd y)
+// A sign change of Im zeta between the samples at parameters lo and hi (Im
+// zeta positive at lo when lo_pos): 40 bisection steps on the part's
+// parameter (with zeta itself) locate its zero, and the cut crosses the
+// contour there if Re zeta lies in [0, 1].
+__device__ void cut_bisect(CutWalk &w, double lo, double hi, bool lo_pos)
 {
-    const cd U = cadd(w.x1, y);
-    const cd U2 = cmul(U, U);
-    const cd D = cmul(w.x4, y);
-    return U2.i * D.r - U2.r * D.i;
-}
-
-// One sample at parameter u, contour point y: a sign change of Im zeta since
-// the previous sample is located by bisection on u (with zeta itself).
-__device__ void cut_step(CutWalk &w, double u, cd y)
-{
-    const double si = cut_im_sign(w, y);
-    if (w.started && ((w.pi > 0.0) != (si > 0.0))) {
-        double lo = w.pu, hi = u;
-        const bool lo_pos = w.pi > 0.0;
-        for (int it = 0; it < 40; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if ((cut_zeta(w, mid).i > 0.0) == lo_pos)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const cd zc = cut_zeta(w, 0.5 * (lo + hi));
-        if (zc.r >= 0.0 && zc.r <= 1.0) w.hit = true;
+    for (int it = 0; it < 40; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if ((cut_zeta(w, mid).i > 0.0) == lo_pos)
+            lo = mid;
+        else
+            hi = mid;
     }
-    w.pu = u;
-    w.pi = si;
-    w.started = true;
+    const cd zc = cut_zeta(w, 0.5 * (lo + hi));
+    if (zc.r >= 0.0 && zc.r <= 1.0) w.hit = true;
 }
 
-// Samples along the straight part, y_k = dir (e^{u_k} - 1), u_k = k h,
-// h = T/(n-1), k = 1..n-1: e^{u} - 1 follows e_{k+1} = e_k c + e_k + c
-// (c = e^h - 1), taken afresh from expm1 every 64 samples, so each sample sits
-// within ~64 ulp of its exact position (far inside the oracle's tie band).
+// Samples along the straight part, y_k = dir e_k, e_k = e^{u_k} - 1, u_k = k h,
+// h = T/(n-1), k = 1..n-1: e follows e_{k+1} = e_k c + e_k + c (c = e^h - 1),
+// taken afresh from expm1 every 64 samples, so each sample sits within ~64
+// ulp of its exact position (far inside the oracle's tie band).  Im zeta has
+// the sign of Im(U^2 conj(4 x y)) (|4 x y|^2 > 0), and with 4 x y = (4 x dir) e,
+// e > 0, of Im(U^2 conj(4 x dir)) = ur (2 ui c_r - ur c_i) + ui^2 c_i, U = x1 + dir e:
+// no division and no product with e.
 __device__ void cut_walk_straight(CutWalk &w, int n, double T)
 {
     const double h = T / (n - 1);
     const double c = expm1(h);
+    const cd c4 = cmul(w.x4, w.dir);
+    const double c4r2 = 2.0 * c4.r;
     double e = 0.0;
+    bool prev = false;
     for (int k = 1; k < n; ++k) {
-        const double u = k * h;
-        e = (k & 63) == 1 ? expm1(u) : fma(e, c, e + c);
-        cut_step(w, u, cscale(w.dir, e));
+        e = (k & 63) == 1 ? expm1(k * h) : fma(e, c, e + c);
+        const double ur = fma(w.dir.r, e, w.x1.r), ui = fma(w.dir.i, e, w.x1.i);
+        const double v = fma(ur, fma(ui, c4r2, -(ur * c4.i)), ui * (ui * c4.i));
+        const bool pos = v > 0.0;
+        if (k > 1 && pos != prev) cut_bisect(w, (k - 1) * h, k * h, prev);
+        prev = pos;
     }
 }
 
 // Samples along an arc from angle phi, psi_k = phi + span k/(n-1), k = 0..n-1
 // (span = -phi: back to 0 the short way; the long way: to +-2 pi): the unit
-// vector rotates by e^{i span/(n-1)} per sample, taken afresh from sincos
-// every 64 samples.
+// vector e = e^{i psi} rotates by e^{i span/(n-1)} per sample, taken afresh
+// from sincos every 64 samples.  With y = Lambda^2 e and e conj(e) = 1,
+//   U^2 conj(4 x y) = Lambda^2 conj(4x) (x1^2 conj(e) + 2 Lambda^2 x1 + Lambda^4 e),
+// so Im zeta has the sign of alpha + b_c cos psi + b_s sin psi with
+// A = conj(4x) x1^2, B = Lambda^4 conj(4x), alpha = Im(2 Lambda^2 conj(4x) x1),
+// b_c = Im A + Im B, b_s = Re B - Re A: two FMAs a sample.  Its terms add up to
+// at most ((Lambda^2 + |x1|) / (Lambda^2 - |x1|))^2 times the value's own scale,
+// so the rounding stays that of the direct product.
 __device__ void cut_walk_arc(CutWalk &w, int n, double phi, double span)
 {
     const double dpsi = span / (n - 1);
     double s, c;
     sincos(dpsi, &s, &c);
     const cd rot = mk(c, s);
+    const cd cx4 = mk(w.x4.r, -w.x4.i);
+    const double l2 = w.lam2, l4 = l2 * l2;
+    const cd A = cmul(cx4, cmul(w.x1, w.x1));
+    const cd B = cscale(cx4, l4);
+    const double alpha = 2.0 * l2 * fma(cx4.r, w.x1.i, cx4.i * w.x1.r);
+    const double bc = A.i + B.i, bs = B.r - A.r;
     cd e = mk(1.0, 0.0);
+    bool prev = false;
     for (int k = 0; k < n; ++k) {
-        const double psi = fma((double)k, dpsi, phi);
         if ((k & 63) == 0) {
-            sincos(psi, &s, &c);
+            sincos(fma((double)k, dpsi, phi), &s, &c);
             e = mk(c, s);
         } else {
             e = cmul(e, rot);
         }
-        cut_step(w, psi, cscale(e, w.lam2));
+        const bool pos = fma(bc, e.r, fma(bs, e.i, alpha)) > 0.0;
+        if (k > 0 && pos != prev)
+            cut_bisect(w, fma((double)(k - 1), dpsi, phi), fma((double)k, dpsi, phi), prev);
+        prev = pos;
     }
 }
 
@@ -155,9 +162,6 @@ __device__ CutWalk cut_walk_begin(const ScanArgs &a, double xr, double xi)
     w.dir = mk(1.0, 0.0);
     w.lam2 = a.lam2;
     w.arc = false;
-    w.pu = 0.0;
-    w.pi = 0.0;
-    w.started = false;
     w.hit = false;
     return w;
 }
@@ -184,7 +188,6 @@ __device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n,
     w.dir = mk(c, s);
     cut_walk_straight(w, n, T);
     w.arc = true;
-    w.started = false;
     cut_walk_arc(w, n, phi, long_way ? (phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - phi : -phi);
     return w.hit;
 }
