@@ -107,6 +107,9 @@ __device__ void cut_walk_straight(CutWalk &w, int n, double T)
     double e = 0.0;
     bool prev = false;
     for (int k = 1; k < n; ++k) {
+        // once every point of the wave has met the cut, the rest of the part
+        // cannot change the map (wave-uniform)
+        if ((k & 63) == 1 && __all(w.hit)) break;
         e = (k & 63) == 1 ? expm1(k * h) : fma(e, c, e + c);
         const double ur = fma(w.dir.r, e, w.x1.r), ui = fma(w.dir.i, e, w.x1.i);
         const double v = fma(ur, fma(ui, c4r2, -(ur * c4.i)), ui * (ui * c4.i));
