@@ -537,7 +537,10 @@ def main() -> int:
                                f"m1^2={params.m1sq}, m2^2={params.m2sq}, mu^2={params.mu2}, "
                                f"Lambda^2={params.lambda2:g}",
                    "grid_points": grid.n_points, "evals_per_step": t["evals"],
-                   "lanes_per_point": t["lanes"], "parallelism": "single GPU"},
+                   "lanes_per_point": t["lanes"],
+                   "tail": ("the last rows at 16 lanes per point in the same launch (about 16 "
+                            "points per resident wave)") if t["lanes"] == 1 else None,
+                   "parallelism": "single GPU"},
         "points_per_s": t["points_per_s"],
         "scan_latency_ms": t.get("latency_ms"),
         "wall_s_timed": t["wall"],
