@@ -178,13 +178,12 @@ __device__ __forceinline__ void process_tile(const Args &a, int tile, int lane, 
 // the slots of its finished waves until the last one ends.
 //
 // The tail of a large scan at one lane per point (FP32C: one or two), in every
-// kernel form: its last
-// rows run as tiles of 64 / 16 points at 16 lanes per point, a sixteenth of a
-// one-lane wave's work each, dispatched after every other tile.  They fill
-// the slots that the last round of long waves leaves as it drains (waves
-// sharing a SIMD progress oldest first, so a SIMD's last waves end one by
-// one), where otherwise SIMDs would run one or two waves that cannot hide the
-// reciprocal's latency.
+// kernel form: its last rows run as tiles of 64 / 16 points at 16 lanes per
+// point, a sixteenth of a one-lane wave's work each, dispatched after every
+// other tile.  They fill the slots that the last round of long waves leaves as
+// it drains (waves sharing a SIMD progress oldest first, so a SIMD's last
+// waves end one by one), where otherwise SIMDs would run one or two waves that
+// cannot hide the reciprocal's latency.
 template <int L, bool TAYLOR, bool SPLIT, bool POLES>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 scan_kernel_fp64(ScanArgs a)
