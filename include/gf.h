@@ -307,7 +307,9 @@ int gf_scan(const gf_params *params, const gf_grid *grid, const gf_quadrature *q
  * every valid quadrature; sizes beyond it return GF_EINVAL), held until the
  * process ends, and the scan reads them there.  Nothing is allocated, on the
  * device or the host, and nothing is copied from the host: the call only
- * enqueues three kernels and returns.  Every call on a device shares that
+ * enqueues three kernels and returns (so it can be recorded into a graph;
+ * the first call on a device also looks up the buffer's device address, a
+ * host-side query: make it outside the recording).  Every call on a device shares that
  * buffer, so calls on one device must be ordered (one stream, or
  * synchronised streams): calls that overlap on a device race and may return
  * wrong results.  The tables are generated on the device, so results can
