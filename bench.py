@@ -38,7 +38,7 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
 FLOPS_PER_EVAL = 6.5
 
 
-# The survey's count for one unfolded angular term D = U - V z, |D|^2, w/|D|^2,
+# The count for one unfolded angular term D = U - V z, |D|^2, w/|D|^2,
 # acc += t conj(D): 13 flops.  The kernel folds each symmetric pair into one
 # denominator, so that count prices twice the work the kernel does per
 # evaluation; it is reported beside the folded count, as a fraction of peak
@@ -95,7 +95,7 @@ def measured_flops(kernel: str):
 def roofline_conventions(evals: int, sec: float, peak: float, kernel: str):
     """The dominant kernel's FLOP rate and fraction of the FP64 vector peak
     under three counts: the folded pair (6.5 flops per evaluation, the
-    `roofline` figure), the survey's unfolded term (13), and the hardware's
+    `roofline` figure), one unfolded term (13), and the hardware's
     own FP64 flop counter from the committed profile."""
     out = {}
     for name, fpe in (("folded_pair", FLOPS_PER_EVAL), ("unfolded_term", FLOPS_PER_EVAL_UNFOLDED)):
