@@ -274,6 +274,39 @@ def test_singular_points_nan_and_class():
     assert np.isnan(g).sum() >= 3
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32c"])
+@pytest.mark.parametrize("p", [Params(1.0, 1.0, 0.0, 1e4, 1.0), Params(1 + 0.5j, 1 - 0.5j, 1.0, 1e4, 1.0),
+                               Params(-0.5j, 0.5j, 0.0, 1e4, 1.0)], ids=["real_mu0", "conj", "paper"])
+def test_degenerate_points_x_zero_and_x_mu2(p, prec):
+    """Grid points exactly at x = 0 (V^2 = 0: every angular term is 1/U) and
+    exactly at x = mu^2 (G = 0 by the subtraction): a 5 x 5 box of unit
+    cells centred on 0 puts both on the grid for mu^2 in {0, 1}.  Every point
+    against the oracle at the parity bar; at x = mu^2 |G| stays at rounding
+    size next to the subtracted sum."""
+    q = Quadrature(64, 32, 16, prec)
+    grid = Grid(5, 5, -2.5, 2.5, -2.5, 2.5)
+    x = oracle.grid_points(grid)
+    assert (x == 0).sum() == 1 and (x == 1.0).sum() == 1
+    g, c = _gpu_scan(p, q, grid)
+    go, co, cond = oracle.scan(p, q, grid, want_cond=True)
+    assert np.array_equal(c, co)
+    k = int(np.nonzero(x == complex(p.mu2))[0][0])
+    ok = co != oracle.SINGULAR
+    assert ok[k] and go[k] == 0
+    assert np.all(np.isnan(g[~ok]))
+    # every point but x = mu^2 (G = 0, no relative bar) at the parity bar
+    ok[k] = False
+    if prec == 0:
+        check_fp64(g[ok], go[ok], cond[ok])
+    else:
+        check_fp32c(g[ok], go[ok])
+    plan = gf.Plan(p, q)
+    jmu = plan.jmu()
+    plan.close()
+    # the subtracted sum at mu^2 itself: rounding of |J(mu^2)| only
+    assert abs(g[k]) <= (1e-12 if prec == 0 else 1e-6) * max(1.0, abs(jmu)), (g[k], jmu)
+
+
 def test_one_call_scan_matches_plan_scan_and_is_deterministic():
     p, grid, q = CONFIGS["c0_fp64_64sq"]
     a = gf.scan(p, grid, q)
