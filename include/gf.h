@@ -288,7 +288,11 @@ int gf_scan_plan(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *
  * ones.  A large scan at one lane per point (FP32C: one or two; at least two
  * rounds of resident waves) runs its last rows, about a quarter round of its
  * work, at 16 lanes per point in the same launch, which shortens the end of
- * the launch.  Results depend on the lane count only through rounding. */
+ * the launch.  Results depend on the lane count only through rounding.
+ * One launch holds at most 2^26 - 4 wave tiles (a tile is 64 / lanes points,
+ * 64 at one lane per point): an explicit count that needs more returns
+ * GF_EINVAL before anything is enqueued (2 lanes on a grid of 2^31 points,
+ * 64 lanes on one of more than 2^26 - 4); the automatic count never does. */
 int gf_scan_plan_ex(const gf_plan_t *plan, const gf_grid *grid, void *out, int8_t *cls_out,
                     int lanes_per_point, void *stream);
 

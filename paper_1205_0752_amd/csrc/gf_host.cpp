@@ -483,6 +483,13 @@ int auto_lanes(const ScanArgs &base, int precision, const gf_grid &g)
     return std::max(fill, std::min(want, work));
 }
 
+// Every tile is one 64-wide block of a one-dimensional launch (the y-plane
+// scan packs four to a 256-wide block), and a dispatch counts its work-items
+// in 32 bits: a launch holds at most (2^32 - 256) / 64 tiles.  At one lane
+// per point the largest grid (2^31 points) takes 2^25 tiles; more lanes per
+// point on a grid that large are refused rather than launched.
+constexpr long long kMaxLaunchTiles = ((1LL << 32) - 256) / 64;
+
 int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
 {
     a.n_re = g.n_re;
@@ -493,7 +500,11 @@ int set_grid(ScanArgs &a, const gf_grid &g, int lanes)
     a.d_im = (g.im_hi - g.im_lo) / (double)g.n_im;
     long long nt;
     tiles_for(g, lanes, &a.tiles_a, &nt);
-    if (nt > (1LL << 30)) return fail(GF_EINVAL, "grid too large for %d lanes per point", lanes);
+    if (nt > kMaxLaunchTiles)
+        return fail(GF_EINVAL,
+                    "grid too large for %d lanes per point: %lld wave tiles, one launch holds "
+                    "at most %lld (fewer lanes per point)",
+                    lanes, nt, kMaxLaunchTiles);
     a.n_tiles = (int)nt;
     a.tail_tiles = a.tail_row0 = a.tail_tiles_a = 0;
     // The FP64 angular sums multiply eight denominators |U^2 - V^2 s|^2 <=
@@ -543,7 +554,7 @@ void set_tail(ScanArgs &a, const gf_grid &g, int precision, int lanes)
     const long long ta = (g.n_re + twt - 1) / twt;
     const long long tt = ta * ((g.n_im - row0 + tht - 1) / tht);
     const long long bulk = (long long)a.tiles_a * (row0 / thb);
-    if (bulk + tt > (1LL << 30)) return;
+    if (bulk + tt > kMaxLaunchTiles) return;
     a.tail_row0 = (int)row0;
     a.tail_tiles_a = (int)ta;
     a.tail_tiles = (int)tt;

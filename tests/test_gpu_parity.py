@@ -307,6 +307,54 @@ def test_degenerate_points_x_zero_and_x_mu2(p, prec):
     assert abs(g[k]) <= (1e-12 if prec == 0 else 1e-6) * max(1.0, abs(jmu)), (g[k], jmu)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32c"])
+def test_largest_grid_2_31_points(prec):
+    """The largest grid the library takes, 65536 x 32768 = 2^31 points (flat
+    indices up to 2^31 - 1, a 32 GiB result), at few nodes per point: the
+    automatic count (one lane per point, with the 16-lane tail) covers every
+    point exactly once -- every class written, every value finite off the
+    SINGULAR class and NaN on it -- and the first and last points of the
+    grid, of its last row and a spread of others match the oracle at the
+    parity bar.  An explicit lane count whose wave tiles one launch cannot
+    hold is refused before anything is enqueued."""
+    p, q = Params(1.0, 1.0, 1.0, 1e4), Quadrature(8, 6, 2, prec)
+    grid = Grid(65536, 32768, -16.0, 8.0, -8.0, 8.0)
+    n = grid.n_points
+    assert n == 2 ** 31
+    plan = gf.Plan(p, q)
+    assert plan.auto_lanes(grid) == 1
+    out = gf.empty_result(grid)
+    out.fill_(complex(float("nan"), 7.0))
+    cls = torch.full((grid.n_im, grid.n_re), 9, dtype=torch.int8, device="cuda")
+    gf.scan_plan(plan, grid, out, cls)
+    with pytest.raises(Exception, match="one launch holds"):
+        gf.scan_plan(plan, grid, out, cls, lanes=2)
+    torch.cuda.synchronize()
+    plan.close()
+    assert int(((cls < 0) | (cls > 5)).sum()) == 0
+    sing = cls == oracle.SINGULAR
+    assert int((torch.isfinite(out) == sing).sum()) == 0
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([
+        [0, grid.n_re - 1, n - grid.n_re, n - 1, n // 2 - 1, n // 2],
+        n - grid.n_re + rng.choice(grid.n_re, 60, replace=False),
+        rng.choice(n, 200, replace=False)]).astype(np.int64))
+    it = torch.from_numpy(idx).to("cuda")
+    g = out.view(-1)[it].cpu().numpy()
+    c = cls.view(-1)[it].cpu().numpy()
+    del out, cls, sing, it
+    torch.cuda.empty_cache()
+    x = oracle.grid_points_at(grid, idx)
+    go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
+    assert (co != c).sum() <= 1
+    keep = (co == c) & (co != oracle.SINGULAR)
+    assert keep[np.searchsorted(idx, n - 1)]
+    if prec == 0:
+        check_fp64(g[keep], go[keep], cond[keep])
+    else:
+        check_fp32c(g[keep], go[keep])
+
+
 def test_one_call_scan_matches_plan_scan_and_is_deterministic():
     p, grid, q = CONFIGS["c0_fp64_64sq"]
     a = gf.scan(p, grid, q)
