@@ -154,3 +154,34 @@ def test_gpu_obstruction_full_box_properties():
     assert not np.any(o & 2)
     assert np.array_equal((o & 4) > 0, cls == gf.CLASS_SINGULAR)
     assert not np.any((o[cls == gf.CLASS_R] & 1) > 0)
+
+
+@pytest.mark.gpu
+def test_gpu_obstruction_largest_grid():
+    """The largest grid the library takes, 65536 x 32768 = 2^31 points, at 64
+    samples per contour part: every point is written (no bit above the three
+    defined ones survives from a 0xff fill), and the grid's first and last
+    points, its last row and a spread of others equal the oracle's bits away
+    from rounding ties."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1205_0752_amd as gf
+
+    p, n_s = MASSES[1], 64
+    grid = Grid(65536, 32768, -16.0, 8.0, -8.0, 8.0)
+    n = grid.n_points
+    out = torch.full((grid.n_im, grid.n_re), 255, dtype=torch.uint8, device="cuda")
+    gf.obstruction_map(p, grid, n_s, out=out)
+    torch.cuda.synchronize()
+    assert int((out > 7).sum()) == 0
+    rng = np.random.default_rng(17)
+    idx = np.unique(np.concatenate([
+        [0, grid.n_re - 1, n - grid.n_re, n - 1, n // 2 - 1, n // 2],
+        n - grid.n_re + rng.choice(grid.n_re, 60, replace=False),
+        rng.choice(n, 200, replace=False)]).astype(np.int64))
+    got = out.view(-1)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    want, tie = oracle.obstruction(p, oracle.grid_points_at(grid, idx), n_s)
+    assert not np.any((got != want) & ~tie)

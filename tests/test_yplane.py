@@ -163,3 +163,37 @@ def test_gpu_yscan_peaks_on_cut_curve():
     yp, ym = gf.cut_curve(p, X, 4097)
     dist = np.min(np.abs(np.concatenate([yp, ym]) - ymax))
     assert dist <= 2 * np.hypot(16 / 256, 16 / 256), (ymax, dist)
+
+
+@pytest.mark.gpu
+def test_gpu_yscan_largest_grid():
+    """The largest y grid the library takes, 65536 x 32768 = 2^31 points (a
+    32 GiB result), at four angular nodes: every point is written, and the
+    grid's first and last points, its last row and a spread of others match
+    the oracle within the conditioning bound above."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gf = _gf()
+    p, q = PARAMS[1], Quadrature(16, 4, 4)
+    grid = Grid(65536, 32768, -8.0, 8.0, -8.0, 8.0)
+    n = grid.n_points
+    plan = gf.Plan(p, q)
+    out = gf.empty_result(grid)
+    out.fill_(complex(float("nan"), 7.0))
+    gf.yscan_plan(plan, X, grid, 0, out=out)
+    torch.cuda.synchronize()
+    plan.close()
+    assert int((torch.isnan(out.real) & (out.imag == 7.0)).sum()) == 0
+    rng = np.random.default_rng(13)
+    idx = np.unique(np.concatenate([
+        [0, grid.n_re - 1, n - grid.n_re, n - 1, n // 2 - 1, n // 2],
+        n - grid.n_re + rng.choice(grid.n_re, 60, replace=False),
+        rng.choice(n, 200, replace=False)]).astype(np.int64))
+    got = out.view(-1)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    ys = oracle.grid_points_at(grid, idx)
+    ref = oracle.yscan(p, q, X, ys, 0)
+    bound = 64 * 2.0 ** -53 * _cond(X, ys, complex(p.m1sq), q.n_angular) + 1e-14 * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= bound)
