@@ -365,7 +365,9 @@ bool gf_server::admit_one(Request *r, Stage &st, std::vector<Request *> &fresh,
     a.wmid = tb[1]->wmid;
     a.arc = reinterpret_cast<const double *>(d_arena + tb[2]->off);
     a.jmu = d_jmu + 2 * (GF_MAX_TAYLOR + 1) * (size_t)r->slot;
-    gf::set_grid(a, r->g, r->lanes);
+    // cannot fail: one lane per point on a grid checked at submission (at
+    // most 2^31 points, 2^25 tiles)
+    (void)gf::set_grid(a, r->g, r->lanes);
     a.out = reinterpret_cast<double *>(d_arena + out_off);
     a.cls = nullptr;
     r->n_tiles = a.n_tiles;
