@@ -91,31 +91,71 @@ __device__ void cut_bisect(CutWalk &w, double lo, double hi, bool lo_pos)
     if (zc.r >= 0.0 && zc.r <= 1.0) w.hit = true;
 }
 
+// The walks below take their samples in chunks of 64 from a fresh anchor,
+// four samples at a time, each group's first sample carried over from the
+// one before as one more step of the same recurrence.  The four signs are
+// compared with one branch per group (sign changes are rare: at most one per
+// real-segment walk on the bench box); inside it a loop kept rolled bisects
+// each change in order, so a walk holds one copy of the bisection.  Only a
+// walk's last group can reach past its last sample (v1..v3 false); nothing
+// reads the signs after it.  Once every point of the wave has met the cut,
+// the rest of the part cannot change the map: the wave leaves the part at the
+// next chunk (wave-uniform).  Positions, signs, brackets and their order are
+// those of a one-sample-at-a-time walk.
+__device__ __forceinline__ bool group_changes(bool prev, bool p0, bool p1, bool p2, bool p3,
+                                              bool v0, bool v1, bool v2, bool v3)
+{
+    return (v0 && p0 != prev) || (v1 && p1 != p0) || (v2 && p2 != p1) || (v3 && p3 != p2);
+}
+
+__device__ __forceinline__ void group_bisect(CutWalk &w, bool prev, bool p0, bool p1, bool p2,
+                                             bool p3, bool v0, bool v1, bool v2, bool v3,
+                                             double k, double step, double base)
+{
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+        const bool a = j == 0 ? prev : (j == 1 ? p0 : (j == 2 ? p1 : p2));
+        const bool b = j == 0 ? p0 : (j == 1 ? p1 : (j == 2 ? p2 : p3));
+        const bool v = j == 0 ? v0 : (j == 1 ? v1 : (j == 2 ? v2 : v3));
+        if (v && b != a)
+            cut_bisect(w, fma(k + (double)j - 1.0, step, base), fma(k + (double)j, step, base), a);
+    }
+}
+
 // Samples along the straight part, y_k = dir e_k, e_k = e^{u_k} - 1, u_k = k h,
 // h = T/(n-1), k = 1..n-1: e follows e_{k+1} = e_k c + e_k + c (c = e^h - 1),
 // taken afresh from expm1 every 64 samples, so each sample sits within ~64
 // ulp of its exact position (far inside the oracle's tie band).  Im zeta has
 // the sign of Im(U^2 conj(4 x y)) (|4 x y|^2 > 0), and with 4 x y = (4 x dir) e,
 // e > 0, of Im(U^2 conj(4 x dir)) = ur (2 ui c_r - ur c_i) + ui^2 c_i, U = x1 + dir e:
-// no division and no product with e.
+// no division and no product with e.  On the real segment (REAL, dir = 1) ui is
+// x1.i itself, as fma(0, e, x1.i) gives for finite e.
+template <bool REAL>
 __device__ void cut_walk_straight(CutWalk &w, int n, double T)
 {
     const double h = T / (n - 1);
     const double c = expm1(h);
     const cd c4 = cmul(w.x4, w.dir);
     const double c4r2 = 2.0 * c4.r;
-    double e = 0.0;
+    auto pos_at = [&](double e) {
+        const double ur = fma(w.dir.r, e, w.x1.r);
+        const double ui = REAL ? w.x1.i : fma(w.dir.i, e, w.x1.i);
+        return fma(ur, fma(ui, c4r2, -(ur * c4.i)), ui * (ui * c4.i)) > 0.0;
+    };
     bool prev = false;
-    for (int k = 1; k < n; ++k) {
-        // once every point of the wave has met the cut, the rest of the part
-        // cannot change the map (wave-uniform)
-        if ((k & 63) == 1 && __all(w.hit)) break;
-        e = (k & 63) == 1 ? expm1(k * h) : fma(e, c, e + c);
-        const double ur = fma(w.dir.r, e, w.x1.r), ui = fma(w.dir.i, e, w.x1.i);
-        const double v = fma(ur, fma(ui, c4r2, -(ur * c4.i)), ui * (ui * c4.i));
-        const bool pos = v > 0.0;
-        if (k > 1 && pos != prev) cut_bisect(w, (k - 1) * h, k * h, prev);
-        prev = pos;
+    for (int k0 = 1; k0 < n; k0 += 64) {
+        if (__all(w.hit)) break;
+        const int kend = min(k0 + 64, n);
+        double e0 = expm1(k0 * h);
+        for (int k = k0; k < kend; k += 4) {
+            const double e1 = fma(e0, c, e0 + c), e2 = fma(e1, c, e1 + c), e3 = fma(e2, c, e2 + c);
+            const bool p0 = pos_at(e0), p1 = pos_at(e1), p2 = pos_at(e2), p3 = pos_at(e3);
+            const bool v0 = k > 1, v1 = k + 1 < kend, v2 = k + 2 < kend, v3 = k + 3 < kend;
+            if (group_changes(prev, p0, p1, p2, p3, v0, v1, v2, v3))
+                group_bisect(w, prev, p0, p1, p2, p3, v0, v1, v2, v3, (double)k, h, 0.0);
+            prev = p3;
+            e0 = fma(e3, c, e3 + c);
+        }
     }
 }
 
@@ -141,19 +181,22 @@ __device__ void cut_walk_arc(CutWalk &w, int n, double phi, double span)
     const cd B = cscale(cx4, l4);
     const double alpha = 2.0 * l2 * fma(cx4.r, w.x1.i, cx4.i * w.x1.r);
     const double bc = A.i + B.i, bs = B.r - A.r;
-    cd e = mk(1.0, 0.0);
+    auto pos_at = [&](cd e) { return fma(bc, e.r, fma(bs, e.i, alpha)) > 0.0; };
     bool prev = false;
-    for (int k = 0; k < n; ++k) {
-        if ((k & 63) == 0) {
-            sincos(fma((double)k, dpsi, phi), &s, &c);
-            e = mk(c, s);
-        } else {
-            e = cmul(e, rot);
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        if (__all(w.hit)) break;
+        const int kend = min(k0 + 64, n);
+        sincos(fma((double)k0, dpsi, phi), &s, &c);
+        cd e0 = mk(c, s);
+        for (int k = k0; k < kend; k += 4) {
+            const cd e1 = cmul(e0, rot), e2 = cmul(e1, rot), e3 = cmul(e2, rot);
+            const bool p0 = pos_at(e0), p1 = pos_at(e1), p2 = pos_at(e2), p3 = pos_at(e3);
+            const bool v0 = k > 0, v1 = k + 1 < kend, v2 = k + 2 < kend, v3 = k + 3 < kend;
+            if (group_changes(prev, p0, p1, p2, p3, v0, v1, v2, v3))
+                group_bisect(w, prev, p0, p1, p2, p3, v0, v1, v2, v3, (double)k, dpsi, phi);
+            prev = p3;
+            e0 = cmul(e3, rot);
         }
-        const bool pos = fma(bc, e.r, fma(bs, e.i, alpha)) > 0.0;
-        if (k > 0 && pos != prev)
-            cut_bisect(w, fma((double)(k - 1), dpsi, phi), fma((double)k, dpsi, phi), prev);
-        prev = pos;
     }
 }
 
@@ -173,7 +216,7 @@ __device__ CutWalk cut_walk_begin(const ScanArgs &a, double xr, double xi)
 __device__ bool cut_hits_real_axis(const ScanArgs &a, double xr, double xi, int n, double T)
 {
     CutWalk w = cut_walk_begin(a, xr, xi);
-    cut_walk_straight(w, n, T);
+    cut_walk_straight<true>(w, n, T);
     return w.hit;
 }
 
@@ -189,7 +232,7 @@ __device__ bool cut_hits_ray_arc(const ScanArgs &a, double xr, double xi, int n,
     double s, c;
     sincos(phi, &s, &c);
     w.dir = mk(c, s);
-    cut_walk_straight(w, n, T);
+    cut_walk_straight<false>(w, n, T);
     w.arc = true;
     cut_walk_arc(w, n, phi, long_way ? (phi > 0.0 ? 2.0 * M_PI : -2.0 * M_PI) - phi : -phi);
     return w.hit;
