@@ -92,33 +92,41 @@ __device__ void cut_bisect(CutWalk &w, double lo, double hi, bool lo_pos)
 }
 
 // The walks below take their samples in chunks of 64 from a fresh anchor,
-// four samples at a time, each group's first sample carried over from the
-// one before as one more step of the same recurrence.  The four signs are
+// eight samples at a time, each group's first sample carried over from the
+// one before as one more step of the same recurrence.  The eight signs are
 // compared with one branch per group (sign changes are rare: at most one per
 // real-segment walk on the bench box); inside it a loop kept rolled bisects
-// each change in order, so a walk holds one copy of the bisection.  Only a
-// walk's last group can reach past its last sample (v1..v3 false); nothing
-// reads the signs after it.  Once every point of the wave has met the cut,
-// the rest of the part cannot change the map: the wave leaves the part at the
-// next chunk (wave-uniform).  Positions, signs, brackets and their order are
-// those of a one-sample-at-a-time walk.
-__device__ __forceinline__ bool group_changes(bool prev, bool p0, bool p1, bool p2, bool p3,
-                                              bool v0, bool v1, bool v2, bool v3)
+// each change in order, so a walk holds one copy of the bisection.  The
+// comparison starts from the sign of the walk's first sample, which has no
+// predecessor; only a walk's last group can reach past its last sample
+// (valid[j] false), and nothing reads the signs after it.  Once every point of
+// the wave has met the cut, the rest of the part cannot change the map: the
+// wave leaves the part at the next chunk (wave-uniform).  Positions, signs,
+// brackets and their order are those of a one-sample-at-a-time walk.
+constexpr int kGroup = 8;
+
+__device__ __forceinline__ bool group_changes(bool prev, const bool (&p)[kGroup], int k, int k_end)
 {
-    return (v0 && p0 != prev) || (v1 && p1 != p0) || (v2 && p2 != p1) || (v3 && p3 != p2);
+    bool any = p[0] != prev;
+#pragma unroll
+    for (int j = 1; j < kGroup; ++j) any |= (k + j < k_end) & (p[j] != p[j - 1]);  // no short cut
+    return any;
 }
 
-__device__ __forceinline__ void group_bisect(CutWalk &w, bool prev, bool p0, bool p1, bool p2,
-                                             bool p3, bool v0, bool v1, bool v2, bool v3,
-                                             double k, double step, double base)
+__device__ __forceinline__ void group_bisect(CutWalk &w, bool prev, const bool (&p)[kGroup], int k,
+                                             int k_end, double step, double base)
 {
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const bool a = j == 0 ? prev : (j == 1 ? p0 : (j == 2 ? p1 : p2));
-        const bool b = j == 0 ? p0 : (j == 1 ? p1 : (j == 2 ? p2 : p3));
-        const bool v = j == 0 ? v0 : (j == 1 ? v1 : (j == 2 ? v2 : v3));
-        if (v && b != a)
-            cut_bisect(w, fma(k + (double)j - 1.0, step, base), fma(k + (double)j, step, base), a);
+    for (int j = 0; j < kGroup && k + j < k_end; ++j) {
+        bool a = prev, b = p[0];
+#pragma unroll
+        for (int i = 1; i < kGroup; ++i)  // p[j - 1], p[j] without indexing registers dynamically
+            if (i == j) {
+                a = p[i - 1];
+                b = p[i];
+            }
+        if (b != a)
+            cut_bisect(w, fma((double)(k + j - 1), step, base), fma((double)(k + j), step, base), a);
     }
 }
 
@@ -142,19 +150,22 @@ __device__ void cut_walk_straight(CutWalk &w, int n, double T)
         const double ui = REAL ? w.x1.i : fma(w.dir.i, e, w.x1.i);
         return fma(ur, fma(ui, c4r2, -(ur * c4.i)), ui * (ui * c4.i)) > 0.0;
     };
-    bool prev = false;
+    bool prev = pos_at(expm1(h));  // the first sample, k = 1
     for (int k0 = 1; k0 < n; k0 += 64) {
         if (__all(w.hit)) break;
         const int kend = min(k0 + 64, n);
         double e0 = expm1(k0 * h);
-        for (int k = k0; k < kend; k += 4) {
-            const double e1 = fma(e0, c, e0 + c), e2 = fma(e1, c, e1 + c), e3 = fma(e2, c, e2 + c);
-            const bool p0 = pos_at(e0), p1 = pos_at(e1), p2 = pos_at(e2), p3 = pos_at(e3);
-            const bool v0 = k > 1, v1 = k + 1 < kend, v2 = k + 2 < kend, v3 = k + 3 < kend;
-            if (group_changes(prev, p0, p1, p2, p3, v0, v1, v2, v3))
-                group_bisect(w, prev, p0, p1, p2, p3, v0, v1, v2, v3, (double)k, h, 0.0);
-            prev = p3;
-            e0 = fma(e3, c, e3 + c);
+        for (int k = k0; k < kend; k += kGroup) {
+            double e[kGroup];
+            bool p[kGroup];
+            e[0] = e0;
+#pragma unroll
+            for (int j = 1; j < kGroup; ++j) e[j] = fma(e[j - 1], c, e[j - 1] + c);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) p[j] = pos_at(e[j]);
+            if (group_changes(prev, p, k, kend)) group_bisect(w, prev, p, k, kend, h, 0.0);
+            prev = p[kGroup - 1];
+            e0 = fma(e[kGroup - 1], c, e[kGroup - 1] + c);
         }
     }
 }
@@ -182,20 +193,27 @@ __device__ void cut_walk_arc(CutWalk &w, int n, double phi, double span)
     const double alpha = 2.0 * l2 * fma(cx4.r, w.x1.i, cx4.i * w.x1.r);
     const double bc = A.i + B.i, bs = B.r - A.r;
     auto pos_at = [&](cd e) { return fma(bc, e.r, fma(bs, e.i, alpha)) > 0.0; };
-    bool prev = false;
+    bool prev;
+    {
+        sincos(fma(0.0, dpsi, phi), &s, &c);  // the first sample, k = 0, as the walk takes it
+        prev = pos_at(mk(c, s));
+    }
     for (int k0 = 0; k0 < n; k0 += 64) {
         if (__all(w.hit)) break;
         const int kend = min(k0 + 64, n);
         sincos(fma((double)k0, dpsi, phi), &s, &c);
         cd e0 = mk(c, s);
-        for (int k = k0; k < kend; k += 4) {
-            const cd e1 = cmul(e0, rot), e2 = cmul(e1, rot), e3 = cmul(e2, rot);
-            const bool p0 = pos_at(e0), p1 = pos_at(e1), p2 = pos_at(e2), p3 = pos_at(e3);
-            const bool v0 = k > 0, v1 = k + 1 < kend, v2 = k + 2 < kend, v3 = k + 3 < kend;
-            if (group_changes(prev, p0, p1, p2, p3, v0, v1, v2, v3))
-                group_bisect(w, prev, p0, p1, p2, p3, v0, v1, v2, v3, (double)k, dpsi, phi);
-            prev = p3;
-            e0 = cmul(e3, rot);
+        for (int k = k0; k < kend; k += kGroup) {
+            cd e[kGroup];
+            bool p[kGroup];
+            e[0] = e0;
+#pragma unroll
+            for (int j = 1; j < kGroup; ++j) e[j] = cmul(e[j - 1], rot);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) p[j] = pos_at(e[j]);
+            if (group_changes(prev, p, k, kend)) group_bisect(w, prev, p, k, kend, dpsi, phi);
+            prev = p[kGroup - 1];
+            e0 = cmul(e[kGroup - 1], rot);
         }
     }
 }
