@@ -99,7 +99,8 @@ __device__ void cut_bisect(CutWalk &w, double lo, double hi, bool lo_pos)
 // each change in order, so a walk holds one copy of the bisection.  The
 // comparison starts from the sign of the walk's first sample, which has no
 // predecessor; only a walk's last group can reach past its last sample
-// (valid[j] false), and nothing reads the signs after it.  Once every point of
+// (k + j >= k_end: those signs are not compared, and nothing reads them after
+// it).  Once every point of
 // the wave has met the cut, the rest of the part cannot change the map: the
 // wave leaves the part at the next chunk (wave-uniform).  Positions, signs,
 // brackets and their order are those of a one-sample-at-a-time walk.
