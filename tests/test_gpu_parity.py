@@ -315,8 +315,9 @@ def test_largest_grid_2_31_points(prec):
     point exactly once -- every class written, every value finite off the
     SINGULAR class and NaN on it -- and the first and last points of the
     grid, of its last row and a spread of others match the oracle at the
-    parity bar.  An explicit lane count whose wave tiles one launch cannot
-    hold is refused before anything is enqueued."""
+    parity bar; the allocation-free scan at the same size writes every
+    point and agrees with it.  An explicit lane count whose wave tiles one
+    launch cannot hold is refused before anything is enqueued."""
     p, q = Params(1.0, 1.0, 1.0, 1e4), Quadrature(8, 6, 2, prec)
     grid = Grid(65536, 32768, -16.0, 8.0, -8.0, 8.0)
     n = grid.n_points
@@ -342,8 +343,19 @@ def test_largest_grid_2_31_points(prec):
     it = torch.from_numpy(idx).to("cuda")
     g = out.view(-1)[it].cpu().numpy()
     c = cls.view(-1)[it].cpu().numpy()
+    # the allocation-free scan (node tables generated on the device) at the
+    # same size into the same buffer: every point written, the samples equal
+    # to the plan's up to the tables' last bits
+    out.fill_(complex(float("nan"), 7.0))
+    gf.scan_noalloc(p, grid, q, out)
+    torch.cuda.synchronize()
+    assert int((torch.isfinite(out) == sing).sum()) == 0
+    gn = out.view(-1)[it].cpu().numpy()
     del out, cls, sing, it
     torch.cuda.empty_cache()
+    fin = np.isfinite(g)
+    assert np.array_equal(fin, np.isfinite(gn))
+    assert np.max(np.abs(gn[fin] - g[fin])) <= (1e-9 if prec == 0 else 2e-6) * np.max(np.abs(g[fin]))
     x = oracle.grid_points_at(grid, idx)
     go, co, cond = oracle.eval_points(p, q, x, want_cond=True)
     assert (co != c).sum() <= 1
