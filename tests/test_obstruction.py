@@ -185,3 +185,25 @@ def test_gpu_obstruction_largest_grid():
     torch.cuda.empty_cache()
     want, tie = oracle.obstruction(p, oracle.grid_points_at(grid, idx), n_s)
     assert not np.any((got != want) & ~tie)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [2, 3, 5, 9, 70, 131])
+def test_gpu_obstruction_short_and_ragged_walks(n):
+    """Walks of every length class: shorter than one group of samples, one
+    group and a bit, and chunks whose last group reaches past the walk's last
+    sample, on the straight parts (n - 1 samples) and the arcs (n): the map
+    equals the oracle's bit for bit away from rounding ties."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1205_0752_amd as gf
+
+    grid = Grid(45, 37, -12.0, 6.0, -6.0, 6.0)
+    x = oracle.grid_points(grid)
+    for p in MASSES:
+        got = gf.obstruction_map(p, grid, n)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().ravel()
+        want, tie = oracle.obstruction(p, x, n)
+        assert not np.any((got != want) & ~tie), (p, n, np.nonzero((got != want) & ~tie)[0][:5])
